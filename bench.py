@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Exact launch-order evaluations per second on one MI355X.
+
+One step is the whole evaluation path over one kernel set of the n=10
+workload (10 kernels, 256-CU MI355X-shaped model, 3,628,800 launch orders):
+
+  1. derive per-block use and durations, and the launch order of Algorithm 1
+     (host, inside libko);
+  2. the makespan of that order (device);
+  3. the makespans of all n! orders, with per-set extremes, the rank counts
+     against the heuristic order's makespan (its percentile) and a 1024-bin
+     histogram (device).
+
+Inputs are synthetic and seeded (SeedSequence([20151123, 1, 0])) and resident
+in HBM before timing starts.  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# integer VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# algorithmic int32 lane-operations per order: 13 per block of the set
+# (8 to test and claim a CU, 4 to release it, 1 for the finish time)
+OPS_PER_BLOCK = 13
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", type=int, default=1, help="synthetic workload index (default 1: n=10)")
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="target duration of the CPU oracle sample (0 = skip)")
+    return p.parse_args()
+
+
+def cpu_baseline(model, ks, seconds: float) -> dict:
+    """The CPU oracle, as it stands, on a bounded prefix of the same orders."""
+    import oracle
+    threads = oracle.default_threads()
+    pilot = 200 * threads
+    t0 = time.perf_counter()
+    oracle.makespans_range(model.as_dict(), ks, 0, pilot, threads)
+    dt = time.perf_counter() - t0
+    count = max(pilot, int(pilot * max(seconds - dt, 0.0) / max(dt, 1e-9)))
+    t0 = time.perf_counter()
+    oracle.makespans_range(model.as_dict(), ks, pilot, count, threads)
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "orders/s", "cores": threads, "kind": "oracle",
+            "sample": f"lexicographic ranks {pilot}..{pilot + count - 1} of the same set "
+                      f"({count} orders, {dt:.1f} s, plain C event-driven oracle, -O2, "
+                      f"{threads} threads)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(every evaluation shards by rank range; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1511_07983_amd as ko
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.WORKLOADS[args.workload]
+    ks = synth.draw_set(args.workload, 0)
+    n = len(ks)
+    N = math.factorial(n)
+    off = [0, n]
+    kernels = ko.kernel_array(ks)
+    b_total = int(ks["n_tblk"].sum())
+
+    ms = torch.empty(N, dtype=torch.int64, device=dev)
+    st = torch.empty(8, dtype=torch.int64, device=dev)
+    hist = torch.empty(1024, dtype=torch.int64, device=dev)
+    ref = torch.empty(1, dtype=torch.int64, device=dev)
+    order_host = torch.empty(n, dtype=torch.uint8).pin_memory()
+    order_dev = torch.empty(n, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    spec_all = ko.OrderSpec.all()
+    kernel_ms = []
+
+    def step(timed: bool):
+        order = ko.ko_heuristic_order(w.model, kernels)
+        order_host.copy_(torch.tensor(order, dtype=torch.uint8))
+        order_dev.copy_(order_host, non_blocking=True)
+        ko.ko_simulate_batch(w.model, kernels, off, ko.OrderSpec.explicit(order_dev, [1]),
+                             makespans=ref, stream=stream)
+        ev0.record(stream)
+        ko.ko_simulate_batch(w.model, kernels, off, spec_all, ref_makespan=ref, makespans=ms,
+                             stats=st, hist=hist, n_bins=1024, stream=stream)
+        ev1.record(stream)
+        if timed:
+            kernel_ms.append((ev0, ev1))
+        return order
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+
+    # kernel-level timing: the same step again, events around the enumeration
+    # call on the stream it is launched on (reported separately from `value`)
+    durs = []
+    for _ in range(max(1, min(args.steps, 5))):
+        step(True)
+        torch.cuda.synchronize()
+        a, b = kernel_ms[-1]
+        durs.append(a.elapsed_time(b) / 1e3)
+    ko.ko_sync()
+    kernel_s = float(np.mean(durs))
+
+    rec = ko.stats_records(st)[0]
+    assert rec["n_orders"] == N
+    assert rec["n_less"] + rec["n_equal"] + rec["n_greater"] == N
+    assert int(hist.cpu().numpy().view(np.uint64).sum()) == N
+    pct = 100.0 * (rec["n_greater"] + rec["n_equal"]) / N
+
+    ops_per_order = OPS_PER_BLOCK * b_total
+    achieved = ops_per_order * N / kernel_s / 1e12
+    out = {
+        "metric": "exact launch-order evals/s; surrogate speedup to exact top-1% order",
+        "value": N * args.steps / elapsed,
+        "unit": "orders/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_kernels": n, "orders_per_step": N, "blocks_per_order": b_total,
+                   "cu_model": w.model.n_cu, "seed": f"SeedSequence([20151123, {w.index}, 0])",
+                   "histogram_bins": 1024},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "Top/s",
+                     "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "ko::simulate_kernel<4>", "kernel_ms": 1e3 * kernel_s,
+                     "ops_per_order": ops_per_order},
+        "heuristic": {"order": ko.ko_heuristic_order(w.model, kernels), "pct_inclusive": pct,
+                      "min_makespan": int(rec["min_makespan"]), "max_makespan": int(rec["max_makespan"])},
+    }
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(w.model, ks, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+/*
+ * ko.h — exact evaluation of GPU kernel launch orders on MI355X (gfx950).
+ *
+ * C ABI of libko.so.  The library evaluates, for a set of independent kernels
+ * described by the kernel parameters of Table 1 of Li, Narayana & El-Ghazawi,
+ * "Reordering GPU Kernel Launches to Enable Efficient Concurrent Execution"
+ * (2015), the total execution time of launch orders under a discrete-event
+ * model of thread-block dispatch, and derives the launch order of the paper's
+ * Algorithm 1.  The input is the kernel set with its profile (Algorithm 1's
+ * input), the output is a launch order (Algorithm 1's output), its total
+ * execution time and its percentile rank among all orders (Table 3).
+ *
+ * Dispatch model (Section 2, read as follows; makespans are int64 cycles):
+ *   - the blocks of all kernels form one stream in launch order, kernel by
+ *     kernel; the stream is never reordered: while its front block fits on no
+ *     CU, no later block is placed;
+ *   - placement is round-robin: a cyclic CU pointer, starting at CU 0 and
+ *     never reset; a block goes to the first CU at or after the pointer whose
+ *     free registers, LDS bytes, waves and block slots all cover the block's
+ *     use, and the pointer moves to the next CU;
+ *   - a block of kernel i holds regs_thr * waves_blk * wave_size lane
+ *     registers, lds_blk bytes, waves_blk waves and one block slot for
+ *     ceil(n_inst * max(r_milli, rb_milli) / r_milli) cycles (Section 4: a
+ *     kernel below the balanced ratio R_B is memory bound and its blocks
+ *     stretch by R_B / R_i); blocks of co-resident kernels do not slow each
+ *     other;
+ *   - all blocks finishing at a cycle release before placement resumes at
+ *     that cycle; the makespan is the cycle at which the last block ends.
+ *
+ * Orders and ranks: order[j] is the 0-based input index of the kernel launched
+ * at position j.  Ranks are lexicographic over these sequences (rank 0 is the
+ * identity order, rank n!-1 the reversed one).
+ *
+ * Conventions:
+ *   - every function returns 0 (KO_OK) or a negative KO_E* code; no C++
+ *     exception crosses the ABI; ko_last_error() describes the last failure;
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *     device allocations on the current device (for example the data_ptr()
+ *     of a torch tensor on cuda:N under ROCm); the caller owns every buffer
+ *     it passes in and the library never frees or retains one past the call;
+ *   - hip_stream is a hipStream_t (0 = the null stream);
+ *   - the library keeps a lazily grown per-device workspace that
+ *     ko_shutdown() releases (it is also released at process exit).
+ */
+#ifndef KO_H
+#define KO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KO_OK 0
+#define KO_EINVAL (-1) /* bad argument: see each function */
+#define KO_ERANGE (-2) /* an order count or rank outside uint64, or n too large for the mode */
+#define KO_ENOMEM (-3) /* host or device allocation failed */
+#define KO_EHIP (-4)   /* HIP runtime error, or a device status error from an earlier call */
+
+/* The per-CU limits of Table 1 (first three rows).  40 bytes. */
+typedef struct ko_gpu_model {
+    int32_t n_cu;      /* N_SM: CUs (SMs); 1 .. 256 */
+    int32_t wave_size; /* lanes per wave (warp); >= 1 */
+    int32_t wave_cu;   /* N_warp_SM: resident waves per CU; 1 .. 2^24 */
+    int32_t blk_cu;    /* N_blk_SM: resident blocks per CU; 1 .. 255 */
+    int64_t reg_cu;    /* N_reg_SM: lane registers per CU; 1 .. 2^24 */
+    int64_t lds_cu;    /* N_shm_SM: LDS / shared-memory bytes per CU; 1 .. 2^24 */
+    int32_t rb_milli;  /* R_B, the balanced instruction/memory ratio, times 1000; >= 1 */
+    int32_t reserved;  /* must be 0 */
+} ko_gpu_model;
+
+/* The per-kernel parameters of Table 1 (last three rows).  40 bytes. */
+typedef struct ko_kernel {
+    int64_t n_tblk;    /* N_tblk_i: blocks in the grid; >= 1 */
+    int64_t n_inst;    /* N_inst_i: instructions per block (cycles when R_i >= R_B); >= 1 */
+    int64_t lds_blk;   /* N_shm_i: LDS bytes per block; >= 0 */
+    int32_t waves_blk; /* N_warp_i: waves per block; >= 1 */
+    int32_t regs_thr;  /* N_reg_i as registers per thread; >= 1 */
+    int32_t r_milli;   /* R_i, the kernel's instruction/memory ratio, times 1000; >= 1 */
+    int32_t reserved;  /* must be 0 */
+} ko_kernel;
+
+/* Per-set statistics over the evaluated orders (Table 3 columns, Figure 1).  64 bytes.
+ * argmin/argmax: for KO_ORDERS_ALL and KO_ORDERS_RANK_RANGE the lexicographic rank,
+ * for KO_ORDERS_EXPLICIT and KO_ORDERS_SAMPLED the index of the order within the
+ * set's list; ties go to the smallest.  The three counts compare each makespan
+ * with the set's reference makespan and are 0 when no reference is given. */
+typedef struct ko_set_stats {
+    int64_t min_makespan;
+    int64_t max_makespan;
+    uint64_t argmin;
+    uint64_t argmax;
+    uint64_t n_less;
+    uint64_t n_equal;
+    uint64_t n_greater;
+    uint64_t n_orders;
+} ko_set_stats;
+
+/* Percentile rank of one order (Table 3, "Percentile rank").  The counts are
+ * exact; the three percentages are 100 * (n_greater + n_equal) / n_total
+ * (inclusive, the headline), 100 * n_greater / n_total (strict) and
+ * 100 * (n_greater + n_equal / 2) / n_total (mid-rank). */
+typedef struct ko_rank_result {
+    int64_t makespan;      /* of the given order */
+    int64_t min_makespan;  /* best ("optimal") over the evaluated orders */
+    int64_t max_makespan;  /* worst over the evaluated orders */
+    uint64_t n_less;
+    uint64_t n_equal;
+    uint64_t n_greater;
+    uint64_t n_total;
+    double pct_inclusive;
+    double pct_strict;
+    double pct_mid;
+} ko_rank_result;
+
+#define KO_ORDERS_ALL 0        /* every order, ranks 0 .. n!-1; n <= 20 */
+#define KO_ORDERS_RANK_RANGE 1 /* ranks lo .. hi-1 per set */
+#define KO_ORDERS_EXPLICIT 2   /* orders given in device memory */
+#define KO_ORDERS_SAMPLED 3    /* uniform ranks with replacement, counter-based */
+
+/* Which orders of each set to evaluate.
+ * SAMPLED: sample i of set s has rank floor(x * n! / 2^64) where x is output
+ * number (s << 40) | i of SplitMix64 (Steele, Lea & Flood 2014) seeded with
+ * `seed`, i.e. the SplitMix64 mix of seed + (c + 1) * 0x9E3779B97F4A7C15. */
+typedef struct ko_order_spec {
+    int32_t mode;                  /* KO_ORDERS_* */
+    int32_t reserved;              /* must be 0 */
+    const uint64_t *rank_lo_hi;    /* RANK_RANGE: host, 2 per set: [lo, hi), lo <= hi <= n! */
+    const uint8_t *orders_dev;     /* EXPLICIT: device, the sets' orders back to back, each
+                                      order n_s bytes (kernel indices); must be permutations */
+    const int64_t *orders_per_set; /* EXPLICIT and SAMPLED: host, one count >= 0 per set */
+    uint64_t seed;                 /* SAMPLED */
+} ko_order_spec;
+
+/* Heuristic flags (readings of Algorithm 1 where the paper is open). */
+#define KO_HEUR_PER_BLOCK 1u /* ScoreGen on one block's use (default: ceil(N_tblk/N_SM) blocks) */
+#define KO_HEUR_FULL_SORT 2u /* stably re-sort a round by decreasing LDS after each insertion
+                                (default: the new kernel goes before the round iff its LDS
+                                 exceeds the round's combined LDS, else after it) */
+
+/*
+ * ko_heuristic_order — the launch order of Algorithm 1 (ScoreGen,
+ * ProfileCombine, execution rounds; Section 5).  Host only, synchronous.
+ *   gpu, k      host; k[0..n-1] the kernel set
+ *   n           1 .. 20
+ *   flags       KO_HEUR_* bits
+ *   order_out   host int32[n]: the order
+ *   round_out   host int32[n] or NULL: the execution round (0-based) of each position
+ * Scores are binary64 evaluated in a fixed order with exact ties resolved to
+ * the first candidate in index order.  Errors: KO_EINVAL for a NULL required
+ * pointer, n out of range, an invalid model or kernel, unknown flags.
+ */
+int ko_heuristic_order(const ko_gpu_model *gpu, const ko_kernel *k, int32_t n, uint32_t flags,
+                       int32_t *order_out, int32_t *round_out);
+
+/*
+ * ko_count_orders — how many orders each set of a batch evaluates under a spec,
+ * and where each set's makespans start in the output array.  Host only.
+ *   set_offsets  host int32[n_sets+1], set s = kernels set_offsets[s] .. set_offsets[s+1]-1
+ *   per_set_out  host uint64[n_sets] or NULL
+ *   total_out    host uint64[1]: the sum (the length of the makespan output)
+ * Errors: KO_EINVAL (bad offsets, set size outside 1..20, bad spec), KO_ERANGE
+ * (n! or the total does not fit in uint64).
+ */
+int ko_count_orders(const int32_t *set_offsets, int32_t n_sets, const ko_order_spec *spec,
+                    uint64_t *per_set_out, uint64_t *total_out);
+
+/*
+ * ko_simulate_batch — makespans of many launch orders of many kernel sets on
+ * one GPU model (the exhaustive or sampled evaluation behind Table 3 and
+ * Figure 1).  Stream-ordered and asynchronous: argument validation happens
+ * before anything is enqueued and returns synchronously; a device status
+ * error of this call is reported by the next call (or by ko_sync).
+ *   gpu              host
+ *   kernels          host ko_kernel[set_offsets[n_sets]], all sets back to back
+ *   set_offsets      host int32[n_sets+1], nondecreasing from 0; each set has 1..20 kernels
+ *   n_sets           >= 1
+ *   spec             host; which orders (see ko_order_spec)
+ *   ref_makespan_dev device int64[n_sets] or NULL: reference makespan per set for the counts
+ *   makespans_dev    device int64[total] or NULL: makespan of every evaluated order, set by
+ *                    set, within a set in rank order (ALL, RANK_RANGE) or list order
+ *   stats_dev        device ko_set_stats[n_sets] or NULL
+ *   hist_dev         device uint64[n_sets * n_bins] or NULL: per set, bin of a makespan M is
+ *                    floor((M - min) * n_bins / (max - min + 1)); needs makespans_dev and
+ *                    stats_dev
+ *   n_bins           1 .. 65536 when hist_dev is given
+ *   hip_stream       hipStream_t
+ * A set with zero orders gets min = INT64_MAX, max = INT64_MIN, argmin = argmax = 0.
+ * Errors: KO_EINVAL (bad pointers, sizes, models, kernels, or a block that does not
+ * fit an empty CU), KO_ERANGE (counts), KO_ENOMEM, KO_EHIP.
+ */
+int ko_simulate_batch(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *set_offsets,
+                      int32_t n_sets, const ko_order_spec *spec, const int64_t *ref_makespan_dev,
+                      int64_t *makespans_dev, ko_set_stats *stats_dev, uint64_t *hist_dev,
+                      int32_t n_bins, void *hip_stream);
+
+/*
+ * ko_rank_percentile — the makespan of one order and its percentile rank
+ * among all n! orders (n_samples = 0) or among n_samples sampled orders
+ * (KO_ORDERS_SAMPLED with `seed`, set index 0).  Synchronous: waits on
+ * hip_stream before returning.
+ *   gpu, k, n   host; n in 1 .. 20
+ *   order       host int32[n], a permutation of 0..n-1
+ *   out         host
+ * Errors: KO_EINVAL, KO_ERANGE, KO_ENOMEM, KO_EHIP.
+ */
+int ko_rank_percentile(const ko_gpu_model *gpu, const ko_kernel *k, int32_t n, const int32_t *order,
+                       uint64_t n_samples, uint64_t seed, ko_rank_result *out, void *hip_stream);
+
+/* ko_sync — wait for hip_stream and report any device status error of earlier calls. */
+int ko_sync(void *hip_stream);
+
+/* ko_shutdown — release the per-device workspaces.  Later calls recreate them. */
+int ko_shutdown(void);
+
+/* ko_last_error — text of the last failure on this thread; owned by the library,
+ * valid until the next call on this thread.  Never NULL. */
+const char *ko_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KO_H */

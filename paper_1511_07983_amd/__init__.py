@@ -1,0 +1,306 @@
+"""Python binding of libko.so (include/ko.h): exact kernel-launch-order evaluation.
+
+Argument marshalling only.  Every step of the evaluation runs in the library:
+the launch-order heuristic on the host, the makespan enumeration, statistics
+and histograms in its gfx950 kernels.  PyTorch supplies device memory and the
+current HIP stream.  Importing this package fails loudly when libko.so has not
+been built (``python paper_1511_07983_amd/build.py``); there is no fallback.
+
+Names mirror the C ABI: ko_heuristic_order, ko_count_orders,
+ko_simulate_batch, ko_rank_percentile, ko_sync, ko_shutdown, ko_last_error.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libko.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1511_07983_amd/build.py`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+KO_OK = 0
+KO_EINVAL = -1
+KO_ERANGE = -2
+KO_ENOMEM = -3
+KO_EHIP = -4
+
+KO_ORDERS_ALL = 0
+KO_ORDERS_RANK_RANGE = 1
+KO_ORDERS_EXPLICIT = 2
+KO_ORDERS_SAMPLED = 3
+
+KO_HEUR_PER_BLOCK = 1
+KO_HEUR_FULL_SORT = 2
+
+EXPORTED = ("ko_heuristic_order", "ko_count_orders", "ko_simulate_batch", "ko_rank_percentile",
+            "ko_sync", "ko_shutdown", "ko_last_error")
+
+
+class KoGpuModel(ctypes.Structure):
+    _fields_ = [("n_cu", ctypes.c_int32), ("wave_size", ctypes.c_int32),
+                ("wave_cu", ctypes.c_int32), ("blk_cu", ctypes.c_int32),
+                ("reg_cu", ctypes.c_int64), ("lds_cu", ctypes.c_int64),
+                ("rb_milli", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class KoKernel(ctypes.Structure):
+    _fields_ = [("n_tblk", ctypes.c_int64), ("n_inst", ctypes.c_int64),
+                ("lds_blk", ctypes.c_int64), ("waves_blk", ctypes.c_int32),
+                ("regs_thr", ctypes.c_int32), ("r_milli", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class KoSetStats(ctypes.Structure):
+    _fields_ = [("min_makespan", ctypes.c_int64), ("max_makespan", ctypes.c_int64),
+                ("argmin", ctypes.c_uint64), ("argmax", ctypes.c_uint64),
+                ("n_less", ctypes.c_uint64), ("n_equal", ctypes.c_uint64),
+                ("n_greater", ctypes.c_uint64), ("n_orders", ctypes.c_uint64)]
+
+
+class KoRankResult(ctypes.Structure):
+    _fields_ = [("makespan", ctypes.c_int64), ("min_makespan", ctypes.c_int64),
+                ("max_makespan", ctypes.c_int64), ("n_less", ctypes.c_uint64),
+                ("n_equal", ctypes.c_uint64), ("n_greater", ctypes.c_uint64),
+                ("n_total", ctypes.c_uint64), ("pct_inclusive", ctypes.c_double),
+                ("pct_strict", ctypes.c_double), ("pct_mid", ctypes.c_double)]
+
+
+class KoOrderSpec(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rank_lo_hi", ctypes.POINTER(ctypes.c_uint64)),
+                ("orders_dev", ctypes.c_void_p),
+                ("orders_per_set", ctypes.POINTER(ctypes.c_int64)),
+                ("seed", ctypes.c_uint64)]
+
+
+# numpy views of the ABI records (same layout as the C structs)
+SET_STATS_DTYPE = np.dtype([("min_makespan", "<i8"), ("max_makespan", "<i8"), ("argmin", "<u8"),
+                            ("argmax", "<u8"), ("n_less", "<u8"), ("n_equal", "<u8"),
+                            ("n_greater", "<u8"), ("n_orders", "<u8")])
+KERNEL_DTYPE = np.dtype([("n_tblk", "<i8"), ("n_inst", "<i8"), ("lds_blk", "<i8"),
+                         ("waves_blk", "<i4"), ("regs_thr", "<i4"), ("r_milli", "<i4"),
+                         ("reserved", "<i4")])
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+_lib.ko_heuristic_order.argtypes = [ctypes.POINTER(KoGpuModel), ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.c_uint32, _i32p, _i32p]
+_lib.ko_heuristic_order.restype = ctypes.c_int
+_lib.ko_count_orders.argtypes = [_i32p, ctypes.c_int32, ctypes.POINTER(KoOrderSpec), _u64p, _u64p]
+_lib.ko_count_orders.restype = ctypes.c_int
+_lib.ko_simulate_batch.argtypes = [ctypes.POINTER(KoGpuModel), ctypes.c_void_p, _i32p,
+                                   ctypes.c_int32, ctypes.POINTER(KoOrderSpec), ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int32, ctypes.c_void_p]
+_lib.ko_simulate_batch.restype = ctypes.c_int
+_lib.ko_rank_percentile.argtypes = [ctypes.POINTER(KoGpuModel), ctypes.c_void_p, ctypes.c_int32,
+                                    _i32p, ctypes.c_uint64, ctypes.c_uint64,
+                                    ctypes.POINTER(KoRankResult), ctypes.c_void_p]
+_lib.ko_rank_percentile.restype = ctypes.c_int
+_lib.ko_sync.argtypes = [ctypes.c_void_p]
+_lib.ko_sync.restype = ctypes.c_int
+_lib.ko_shutdown.argtypes = []
+_lib.ko_shutdown.restype = ctypes.c_int
+_lib.ko_last_error.argtypes = []
+_lib.ko_last_error.restype = ctypes.c_char_p
+
+
+class KoError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{message} (code {code})")
+        self.code = code
+
+
+def ko_last_error() -> str:
+    return _lib.ko_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != KO_OK:
+        raise KoError(rc, ko_last_error())
+
+
+def gpu_model(model) -> KoGpuModel:
+    """A KoGpuModel from a mapping or an object with the same field names."""
+    if isinstance(model, KoGpuModel):
+        return model
+    get = model.get if isinstance(model, dict) else (lambda f: getattr(model, f))
+    return KoGpuModel(int(get("n_cu")), int(get("wave_size")), int(get("wave_cu")),
+                      int(get("blk_cu")), int(get("reg_cu")), int(get("lds_cu")),
+                      int(get("rb_milli")), 0)
+
+
+def kernel_array(kernels) -> np.ndarray:
+    """ko_kernel records (KERNEL_DTYPE) from a structured array or a list of mappings."""
+    if isinstance(kernels, np.ndarray) and kernels.dtype == KERNEL_DTYPE:
+        return np.ascontiguousarray(kernels)
+    if isinstance(kernels, np.ndarray) and kernels.dtype.names:
+        rows = [{f: kernels[f][i] for f in kernels.dtype.names} for i in range(len(kernels))]
+    else:
+        rows = list(kernels)
+    out = np.zeros(len(rows), dtype=KERNEL_DTYPE)
+    for i, r in enumerate(rows):
+        for f in ("n_tblk", "n_inst", "lds_blk", "waves_blk", "regs_thr", "r_milli"):
+            out[f][i] = int(r[f])
+    return out
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev_ptr(t, dtype, numel: int, name: str):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {numel}")
+    return t.data_ptr()
+
+
+def ko_heuristic_order(gpu, kernels, flags: int = 0, *, with_rounds: bool = False):
+    """Launch order of Algorithm 1 (host).  Returns the order, or (order, rounds)."""
+    g = gpu_model(gpu)
+    k = kernel_array(kernels)
+    n = len(k)
+    order = np.zeros(max(n, 1), dtype=np.int32)
+    rounds = np.zeros(max(n, 1), dtype=np.int32)
+    _check(_lib.ko_heuristic_order(ctypes.byref(g), k.ctypes.data if n else None, n, flags,
+                                   order.ctypes.data_as(_i32p), rounds.ctypes.data_as(_i32p)))
+    if with_rounds:
+        return order[:n].tolist(), rounds[:n].tolist()
+    return order[:n].tolist()
+
+
+class OrderSpec:
+    """Which orders of each set to evaluate (mirrors ko_order_spec)."""
+
+    def __init__(self, mode: int, rank_lo_hi=None, orders_dev=None, orders_per_set=None,
+                 seed: int = 0):
+        self.mode = mode
+        self._rank = None if rank_lo_hi is None else np.ascontiguousarray(rank_lo_hi, dtype=np.uint64).ravel()
+        self._per = None if orders_per_set is None else np.ascontiguousarray(orders_per_set, dtype=np.int64)
+        self.orders_dev = orders_dev
+        self.seed = int(seed) & ((1 << 64) - 1)
+
+    def c_struct(self) -> KoOrderSpec:
+        s = KoOrderSpec()
+        s.mode = self.mode
+        s.reserved = 0
+        s.rank_lo_hi = self._rank.ctypes.data_as(_u64p) if self._rank is not None else None
+        if self.orders_dev is not None:
+            s.orders_dev = _dev_ptr(self.orders_dev, __import__("torch").uint8, 0, "orders_dev")
+        s.orders_per_set = (self._per.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+                            if self._per is not None else None)
+        s.seed = self.seed
+        return s
+
+    @staticmethod
+    def all():
+        return OrderSpec(KO_ORDERS_ALL)
+
+    @staticmethod
+    def rank_range(lo_hi):
+        return OrderSpec(KO_ORDERS_RANK_RANGE, rank_lo_hi=lo_hi)
+
+    @staticmethod
+    def explicit(orders_dev, orders_per_set):
+        return OrderSpec(KO_ORDERS_EXPLICIT, orders_dev=orders_dev, orders_per_set=orders_per_set)
+
+    @staticmethod
+    def sampled(orders_per_set, seed: int):
+        return OrderSpec(KO_ORDERS_SAMPLED, orders_per_set=orders_per_set, seed=seed)
+
+
+def _offsets(set_offsets) -> np.ndarray:
+    return np.ascontiguousarray(set_offsets, dtype=np.int32)
+
+
+def ko_count_orders(set_offsets, spec: OrderSpec):
+    """(per-set order counts, total) for a batch."""
+    off = _offsets(set_offsets)
+    n_sets = len(off) - 1
+    per = np.zeros(max(n_sets, 1), dtype=np.uint64)
+    total = np.zeros(1, dtype=np.uint64)
+    sp = spec.c_struct()
+    _check(_lib.ko_count_orders(off.ctypes.data_as(_i32p), n_sets, ctypes.byref(sp),
+                                per.ctypes.data_as(_u64p), total.ctypes.data_as(_u64p)))
+    return per[:n_sets], int(total[0])
+
+
+def ko_simulate_batch(gpu, kernels, set_offsets, spec: OrderSpec, *, ref_makespan=None,
+                      makespans=None, stats=None, hist=None, n_bins: int = 0, stream=None):
+    """Enqueue the evaluation of a batch on the current HIP stream (asynchronous).
+
+    ``kernels``/``set_offsets`` are host data; ``ref_makespan`` (int64[n_sets]),
+    ``makespans`` (int64[total]), ``stats`` (uint8[n_sets*64] or a tensor of
+    n_sets*8 int64) and ``hist`` (int64[n_sets*n_bins], read as uint64) are
+    device tensors or None.
+    """
+    import torch
+    g = gpu_model(gpu)
+    k = kernel_array(kernels)
+    off = _offsets(set_offsets)
+    n_sets = len(off) - 1
+    sp = spec.c_struct()
+    per, total = ko_count_orders(off, spec) if n_sets >= 1 else (None, 0)
+    if spec.mode == KO_ORDERS_EXPLICIT and spec.orders_dev is not None:
+        need = int(sum(int(per[s]) * int(off[s + 1] - off[s]) for s in range(n_sets)))
+        if spec.orders_dev.numel() < need:
+            raise ValueError(f"orders_dev holds {spec.orders_dev.numel()} bytes, needs {need}")
+    ref_p = _dev_ptr(ref_makespan, torch.int64, n_sets, "ref_makespan")
+    ms_p = _dev_ptr(makespans, torch.int64, total, "makespans")
+    st_p = _dev_ptr(stats, torch.int64, 8 * n_sets, "stats")
+    h_p = _dev_ptr(hist, torch.int64, n_sets * max(n_bins, 0), "hist")
+    _check(_lib.ko_simulate_batch(ctypes.byref(g), k.ctypes.data if len(k) else None,
+                                  off.ctypes.data_as(_i32p), n_sets, ctypes.byref(sp), ref_p,
+                                  ms_p, st_p, h_p, n_bins, _stream_handle(stream)))
+    return per, total
+
+
+def stats_records(stats_tensor) -> np.ndarray:
+    """Host copy of a device stats tensor as SET_STATS_DTYPE records."""
+    return stats_tensor.detach().cpu().numpy().view(SET_STATS_DTYPE)
+
+
+def ko_rank_percentile(gpu, kernels, order, n_samples: int = 0, seed: int = 0, stream=None) -> dict:
+    """Makespan and percentile rank of one order (synchronous)."""
+    g = gpu_model(gpu)
+    k = kernel_array(kernels)
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    res = KoRankResult()
+    _check(_lib.ko_rank_percentile(ctypes.byref(g), k.ctypes.data if len(k) else None, len(k),
+                                   o.ctypes.data_as(_i32p), int(n_samples), int(seed) & ((1 << 64) - 1),
+                                   ctypes.byref(res), _stream_handle(stream)))
+    return {f: getattr(res, f) for f, _ in KoRankResult._fields_}
+
+
+def ko_sync(stream=None):
+    _check(_lib.ko_sync(_stream_handle(stream)))
+
+
+def ko_shutdown():
+    _check(_lib.ko_shutdown())
+
+
+def library_handle():
+    return _lib

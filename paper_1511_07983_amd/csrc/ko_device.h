@@ -1,0 +1,103 @@
+// Records shared by the host side of libko and its gfx950 kernels.
+// Internal to the library: none of these types cross the C ABI.
+#pragma once
+
+#include <stdint.h>
+
+namespace ko {
+
+// Largest kernel set the device path handles.  Live block groups never
+// exceed the set size (see ko_sim.hip), so the per-wave group ring has
+// kMaxSet slots, one per lane of the lower half-wave.
+constexpr int kMaxSet = 20;
+constexpr int kGroupSlots = 32;
+constexpr int kWave = 64;
+
+// One kernel of a set, derived on the host from ko_kernel and the GPU model.
+// 32 bytes, read with scalar loads.
+struct KernelRec {
+    uint32_t u_reg;     // lane registers per block
+    uint32_t u_lds;     // LDS bytes per block (0 = none)
+    uint32_t u_wave;    // waves per block
+    uint32_t tblk;      // blocks in the grid
+    float inv_reg;      // reciprocals of u_*, rounded up by 3 ulps (see cap_of)
+    float inv_lds;
+    float inv_wave;
+    uint32_t dur;       // cycles per block, < 2^31
+};
+
+// One set of a batch.  48 bytes.
+struct SetRec {
+    uint32_t n;          // kernels in the set
+    uint32_t kbase;      // index of its first KernelRec
+    uint64_t n_orders;   // orders evaluated for this set
+    uint64_t out_base;   // index of its first makespan in the output array
+    uint64_t rank_lo;    // ALL / RANK_RANGE: rank of its first order
+    uint64_t item_base;  // its first work item
+    uint64_t list_base;  // EXPLICIT: byte offset of its first order
+};
+
+// Per-work-item partial statistics, reduced per set by ko_reduce_sets.  64 bytes.
+struct Partial {
+    int64_t min_ms;
+    int64_t max_ms;
+    uint64_t argmin;
+    uint64_t argmax;
+    uint64_t n_less;
+    uint64_t n_equal;
+    uint64_t n_greater;
+    uint64_t count;
+};
+
+enum : int32_t { kModeAll = 0, kModeRange = 1, kModeExplicit = 2, kModeSampled = 3 };
+
+// Device status bits (OR-ed into the workspace status word).
+enum : uint32_t { kStatusGroupOverflow = 1u, kStatusBadOrder = 2u };
+
+struct SimArgs {
+    const KernelRec *krec;
+    const SetRec *sets;
+    int32_t n_sets;
+    int32_t mode;
+    uint64_t n_items;
+    uint64_t chunk;          // orders per work item
+    uint64_t seed;           // SAMPLED
+    const uint8_t *orders;   // EXPLICIT
+    const int64_t *ref;      // per set, or null
+    int64_t *makespans;      // or null
+    Partial *partials;       // per item
+    unsigned long long *item_counter;
+    uint32_t *status;
+    // GPU model
+    uint32_t n_cu;
+    uint32_t cap_reg, cap_lds, cap_wave, cap_blk;
+};
+
+struct ReduceArgs {
+    const SetRec *sets;
+    int32_t n_sets;
+    uint64_t chunk;
+    const Partial *partials;
+    void *stats;             // ko_set_stats[n_sets] (layout-compatible with Partial)
+};
+
+struct HistArgs {
+    const SetRec *sets;
+    int32_t n_sets;
+    const int64_t *makespans;
+    const void *stats;       // ko_set_stats[n_sets]
+    uint64_t *hist;
+    int32_t n_bins;
+    uint64_t per_block;      // orders per workgroup
+    const uint64_t *block_base;  // per set: first workgroup (n_sets+1 entries)
+};
+
+// Launchers (ko_sim.hip).  Each returns a hipError_t value as int.
+int launch_simulate(const SimArgs &a, int slots_per_lane, uint32_t group_slots, int grid,
+                    void *stream);
+int launch_reduce(const ReduceArgs &a, void *stream);
+int launch_hist(const HistArgs &a, uint64_t n_blocks, void *stream);
+int launch_zero_u64(uint64_t *p, uint64_t count, void *stream);
+int device_cu_count(int *out);
+
+}  // namespace ko

@@ -1,0 +1,874 @@
+// Host side of libko: the C ABI declared in include/ko.h.
+//
+// Argument validation, per-block derivation of the kernel records, the
+// launch-order heuristic (Algorithm 1), order counting, the per-device
+// workspace, and the launches of the gfx950 kernels in ko_sim.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ko.h"
+#include "ko_device.h"
+
+namespace {
+
+thread_local std::string g_error = "no error";
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(KO_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define KO_HIP(call, what)                \
+    do {                                  \
+        hipError_t e_ = (call);           \
+        if (e_ != hipSuccess)             \
+            return hip_fail(e_, what);    \
+    } while (0)
+
+constexpr int64_t kCapLimit = (int64_t(1) << 24) - 1;  // resources must stay exact in float
+constexpr int64_t kDurLimit = (int64_t(1) << 31) - 1;
+constexpr int64_t kSerialLimit = int64_t(1) << 46;
+
+// ---------------------------------------------------------------- validation
+
+int check_gpu(const ko_gpu_model *g)
+{
+    if (!g)
+        return fail(KO_EINVAL, "gpu model is NULL");
+    if (g->reserved != 0)
+        return fail(KO_EINVAL, "gpu model: reserved field must be 0");
+    if (g->n_cu < 1 || g->n_cu > 256)
+        return fail(KO_EINVAL, "gpu model: n_cu %d outside 1..256", g->n_cu);
+    if (g->wave_size < 1)
+        return fail(KO_EINVAL, "gpu model: wave_size must be >= 1");
+    if (g->wave_cu < 1 || g->wave_cu > kCapLimit)
+        return fail(KO_EINVAL, "gpu model: wave_cu outside 1..2^24-1");
+    if (g->blk_cu < 1 || g->blk_cu > 255)
+        return fail(KO_EINVAL, "gpu model: blk_cu %d outside 1..255", g->blk_cu);
+    if (g->reg_cu < 1 || g->reg_cu > kCapLimit)
+        return fail(KO_EINVAL, "gpu model: reg_cu outside 1..2^24-1");
+    if (g->lds_cu < 1 || g->lds_cu > kCapLimit)
+        return fail(KO_EINVAL, "gpu model: lds_cu outside 1..2^24-1");
+    if (g->rb_milli < 1)
+        return fail(KO_EINVAL, "gpu model: rb_milli must be >= 1");
+    return KO_OK;
+}
+
+struct Derived {
+    int64_t u_reg, u_lds, u_wave;
+    int64_t dur;
+};
+
+// Per-block use and duration of one kernel (Table 1; Section 4 for the
+// duration: a kernel below the balanced ratio is memory bound and its blocks
+// stretch by R_B / R_i).
+int derive_kernel(const ko_gpu_model &g, const ko_kernel &k, int idx, Derived *d)
+{
+    if (k.reserved != 0)
+        return fail(KO_EINVAL, "kernel %d: reserved field must be 0", idx);
+    if (k.n_tblk < 1 || k.n_tblk > kDurLimit)
+        return fail(KO_EINVAL, "kernel %d: n_tblk outside 1..2^31-1", idx);
+    if (k.n_inst < 1)
+        return fail(KO_EINVAL, "kernel %d: n_inst must be >= 1", idx);
+    if (k.lds_blk < 0)
+        return fail(KO_EINVAL, "kernel %d: lds_blk must be >= 0", idx);
+    if (k.waves_blk < 1 || k.regs_thr < 1 || k.r_milli < 1)
+        return fail(KO_EINVAL, "kernel %d: waves_blk, regs_thr and r_milli must be >= 1", idx);
+    const __int128 ureg = (__int128)k.regs_thr * k.waves_blk * g.wave_size;
+    if (ureg > g.reg_cu || k.lds_blk > g.lds_cu || k.waves_blk > g.wave_cu)
+        return fail(KO_EINVAL, "kernel %d: one block does not fit an empty CU", idx);
+    const int64_t hi = std::max<int64_t>(k.r_milli, g.rb_milli);
+    const __int128 dur = ((__int128)k.n_inst * hi + k.r_milli - 1) / k.r_milli;
+    if (dur > kDurLimit)
+        return fail(KO_EINVAL, "kernel %d: block duration exceeds 2^31-1 cycles", idx);
+    d->u_reg = (int64_t)ureg;
+    d->u_lds = k.lds_blk;
+    d->u_wave = k.waves_blk;
+    d->dur = (int64_t)dur;
+    return KO_OK;
+}
+
+// 1/u rounded up by three ulps: float(fr) * inv then never falls below fr/u.
+float inv_up(int64_t u)
+{
+    if (u <= 0)
+        return 0.0f;
+    float f = (float)(1.0 / (double)u);
+    for (int i = 0; i < 3; i++)
+        f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+int derive_set(const ko_gpu_model &g, const ko_kernel *k, int32_t n, int32_t first_idx,
+               std::vector<ko::KernelRec> *out)
+{
+    __int128 serial = 0;
+    for (int32_t i = 0; i < n; i++) {
+        Derived d;
+        int rc = derive_kernel(g, k[i], first_idx + i, &d);
+        if (rc)
+            return rc;
+        serial += (__int128)k[i].n_tblk * d.dur;
+        ko::KernelRec r;
+        r.u_reg = (uint32_t)d.u_reg;
+        r.u_lds = (uint32_t)d.u_lds;
+        r.u_wave = (uint32_t)d.u_wave;
+        r.tblk = (uint32_t)k[i].n_tblk;
+        r.inv_reg = inv_up(d.u_reg);
+        r.inv_lds = inv_up(d.u_lds);
+        r.inv_wave = inv_up(d.u_wave);
+        r.dur = (uint32_t)d.dur;
+        out->push_back(r);
+    }
+    if (serial >= kSerialLimit)
+        return fail(KO_EINVAL, "set starting at kernel %d: total block time reaches 2^46 cycles",
+                    first_idx);
+    return KO_OK;
+}
+
+uint64_t factorial(int n)
+{
+    uint64_t f = 1;
+    for (int i = 2; i <= n; i++)
+        f *= (uint64_t)i;
+    return f;
+}
+
+int count_orders(const int32_t *off, int32_t n_sets, const ko_order_spec *spec,
+                 std::vector<uint64_t> *per_set, uint64_t *total)
+{
+    if (!off || !spec)
+        return fail(KO_EINVAL, "set_offsets and spec must not be NULL");
+    if (n_sets < 1)
+        return fail(KO_EINVAL, "n_sets must be >= 1");
+    if (off[0] != 0)
+        return fail(KO_EINVAL, "set_offsets[0] must be 0");
+    if (spec->reserved != 0)
+        return fail(KO_EINVAL, "spec: reserved field must be 0");
+    if (spec->mode < KO_ORDERS_ALL || spec->mode > KO_ORDERS_SAMPLED)
+        return fail(KO_EINVAL, "spec: unknown mode %d", spec->mode);
+    if (spec->mode == KO_ORDERS_RANK_RANGE && !spec->rank_lo_hi)
+        return fail(KO_EINVAL, "spec: RANK_RANGE needs rank_lo_hi");
+    if ((spec->mode == KO_ORDERS_EXPLICIT || spec->mode == KO_ORDERS_SAMPLED) &&
+        !spec->orders_per_set)
+        return fail(KO_EINVAL, "spec: EXPLICIT and SAMPLED need orders_per_set");
+    per_set->assign(n_sets, 0);
+    unsigned __int128 sum = 0;
+    for (int32_t s = 0; s < n_sets; s++) {
+        const int32_t n = off[s + 1] - off[s];
+        if (n < 1 || n > ko::kMaxSet)
+            return fail(KO_EINVAL, "set %d has %d kernels (must be 1..%d)", s, n, ko::kMaxSet);
+        const uint64_t nf = factorial(n);
+        uint64_t c = 0;
+        switch (spec->mode) {
+        case KO_ORDERS_ALL:
+            c = nf;
+            break;
+        case KO_ORDERS_RANK_RANGE: {
+            const uint64_t lo = spec->rank_lo_hi[2 * s], hi = spec->rank_lo_hi[2 * s + 1];
+            if (lo > hi || hi > nf)
+                return fail(KO_EINVAL, "set %d: rank range [%llu, %llu) outside 0..n!", s,
+                            (unsigned long long)lo, (unsigned long long)hi);
+            c = hi - lo;
+            break;
+        }
+        default:
+            if (spec->orders_per_set[s] < 0)
+                return fail(KO_EINVAL, "set %d: negative order count", s);
+            c = (uint64_t)spec->orders_per_set[s];
+        }
+        (*per_set)[s] = c;
+        sum += c;
+    }
+    if (sum > (unsigned __int128)UINT64_MAX)
+        return fail(KO_ERANGE, "total order count exceeds 2^64-1");
+    *total = (uint64_t)sum;
+    return KO_OK;
+}
+
+// ------------------------------------------------------------- Algorithm 1
+
+struct Prof {
+    int64_t F[4];  // reg, lds, wave, blk footprints
+    double W;      // instruction weight
+    double R;      // instruction/memory ratio
+};
+enum { kReg = 0, kLds = 1, kWaveR = 2, kBlk = 3 };
+
+bool fits(const int64_t cap[4], const Prof &X, const Prof &Y)
+{
+    for (int x = 0; x < 4; x++)
+        if (X.F[x] + Y.F[x] > cap[x])
+            return false;
+    return true;
+}
+
+// ProfileCombine's ratio: the instruction-weighted harmonic mean.
+double combined_ratio(const Prof &X, const Prof &Y)
+{
+    return (X.W + Y.W) / (X.W / X.R + Y.W / Y.R);
+}
+
+// ScoreGen for one pair: leftover shared memory, registers and warps (each
+// clamped at 0), plus the balance term when R_B lies between the two ratios.
+double score(const int64_t cap[4], double rb, const Prof &X, const Prof &Y)
+{
+    if (!fits(cap, X, Y))
+        return 0.0;
+    double s = 0.0;
+    s += std::max((double)(cap[kLds] - X.F[kLds] - Y.F[kLds]) / (double)cap[kLds], 0.0);
+    s += std::max((double)(cap[kReg] - X.F[kReg] - Y.F[kReg]) / (double)cap[kReg], 0.0);
+    s += std::max((double)(cap[kWaveR] - X.F[kWaveR] - Y.F[kWaveR]) / (double)cap[kWaveR], 0.0);
+    if ((X.R <= rb && rb <= Y.R) || (Y.R <= rb && rb <= X.R)) {
+        const double rc = combined_ratio(X, Y);
+        s += std::max(1.0 - std::fabs(rc - rb) / rb, 0.0);
+    }
+    return s;
+}
+
+Prof combine(const Prof &X, const Prof &Y)
+{
+    Prof c;
+    for (int x = 0; x < 4; x++)
+        c.F[x] = X.F[x] + Y.F[x];
+    c.W = X.W + Y.W;
+    c.R = combined_ratio(X, Y);
+    return c;
+}
+
+int heuristic(const ko_gpu_model &g, const ko_kernel *k, int32_t n, uint32_t flags,
+              int32_t *order_out, int32_t *round_out)
+{
+    const int64_t cap[4] = {g.reg_cu, g.lds_cu, (int64_t)g.wave_cu, (int64_t)g.blk_cu};
+    const double rb = (double)g.rb_milli / 1000.0;
+    std::vector<Prof> P(n);
+    for (int32_t i = 0; i < n; i++) {
+        Derived d;
+        int rc = derive_kernel(g, k[i], i, &d);
+        if (rc)
+            return rc;
+        const int64_t b = (flags & KO_HEUR_PER_BLOCK) ? 1 : (k[i].n_tblk + g.n_cu - 1) / g.n_cu;
+        P[i].F[kReg] = b * d.u_reg;
+        P[i].F[kLds] = b * d.u_lds;
+        P[i].F[kWaveR] = b * d.u_wave;
+        P[i].F[kBlk] = b;
+        P[i].W = (double)((__int128)b * k[i].n_inst);
+        P[i].R = (double)k[i].r_milli / 1000.0;
+    }
+    // ScoreMatrix over all pairs, computed once
+    std::vector<double> S((size_t)n * n, 0.0);
+    for (int32_t i = 0; i < n; i++)
+        for (int32_t j = i + 1; j < n; j++)
+            S[(size_t)i * n + j] = score(cap, rb, P[i], P[j]);
+
+    std::vector<int32_t> remaining(n);
+    for (int32_t i = 0; i < n; i++)
+        remaining[i] = i;
+    int32_t out = 0, round = 0;
+    auto emit = [&](const std::vector<int32_t> &members) {
+        for (int32_t m : members) {
+            order_out[out] = m;
+            if (round_out)
+                round_out[out] = round;
+            out++;
+        }
+        round++;
+    };
+    auto erase = [&](int32_t v) {
+        remaining.erase(std::find(remaining.begin(), remaining.end(), v));
+    };
+    while (!remaining.empty()) {
+        if (remaining.size() == 1) {
+            emit({remaining[0]});
+            remaining.clear();
+            break;
+        }
+        // the pair with the highest score; the first in i < j scan order on ties
+        int32_t a = -1, b = -1;
+        double best = 0.0;
+        for (size_t ai = 0; ai < remaining.size(); ai++)
+            for (size_t bj = ai + 1; bj < remaining.size(); bj++) {
+                const int32_t i = remaining[ai], j = remaining[bj];
+                const double s = S[(size_t)i * n + j];
+                if (a < 0 || s > best) {
+                    a = i;
+                    b = j;
+                    best = s;
+                }
+            }
+        if (P[b].F[kLds] > P[a].F[kLds])
+            std::swap(a, b);  // decreasing shared memory, lower index first on ties
+        std::vector<int32_t> members = {a, b};
+        erase(a);
+        erase(b);
+        Prof comb = combine(P[a], P[b]);
+        for (;;) {
+            int32_t c = -1;
+            double cs = 0.0;
+            for (int32_t r : remaining) {
+                if (!fits(cap, comb, P[r]))
+                    continue;
+                const double s = score(cap, rb, comb, P[r]);
+                if (c < 0 || s > cs) {
+                    c = r;
+                    cs = s;
+                }
+            }
+            if (c < 0)
+                break;
+            if (flags & KO_HEUR_FULL_SORT) {
+                members.push_back(c);
+                std::stable_sort(members.begin(), members.end(), [&](int32_t x, int32_t y) {
+                    return P[x].F[kLds] > P[y].F[kLds];
+                });
+            } else if (P[c].F[kLds] > comb.F[kLds]) {
+                members.insert(members.begin(), c);
+            } else {
+                members.push_back(c);
+            }
+            comb = combine(comb, P[c]);
+            erase(c);
+        }
+        emit(members);
+    }
+    return KO_OK;
+}
+
+// ---------------------------------------------------------------- workspace
+
+struct Workspace {
+    int device = -1;
+    bool ready = false;
+    int cu_count = 0;
+    // device buffers
+    ko::KernelRec *krec = nullptr;
+    size_t krec_cap = 0;
+    ko::SetRec *sets = nullptr;
+    size_t sets_cap = 0;
+    ko::Partial *partials = nullptr;
+    size_t partials_cap = 0;
+    uint64_t *block_base = nullptr;
+    size_t block_base_cap = 0;
+    unsigned long long *counter = nullptr;  // [0] item counter, [1] status word
+    int64_t *scratch_i64 = nullptr;          // rank_percentile: reference makespan
+    uint8_t *scratch_order = nullptr;        // rank_percentile: the order
+    ko_set_stats *scratch_stats = nullptr;   // rank_percentile: stats
+    // pinned host staging
+    void *stage = nullptr;
+    size_t stage_cap = 0;
+    uint32_t *status_host = nullptr;
+    ko_set_stats *stats_host = nullptr;
+    int64_t *ref_host = nullptr;
+    hipEvent_t staged = nullptr;  // after the last upload from `stage`
+    hipEvent_t done = nullptr;    // after the last call's work
+    bool pending_status = false;
+    bool clear_status = false;  // a reported device status must be cleared before the next launch
+};
+
+std::mutex g_mutex;
+std::vector<Workspace> g_ws;
+
+int grow_device(void **p, size_t *cap, size_t need)
+{
+    if (need <= *cap)
+        return KO_OK;
+    if (*p)
+        (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    size_t sz = std::max<size_t>(need, 4096);
+    hipError_t e = hipMalloc(p, sz);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(KO_ENOMEM, "device allocation of %zu bytes failed: %s", sz, hipGetErrorString(e));
+    }
+    *cap = sz;
+    return KO_OK;
+}
+
+int get_workspace(Workspace **out)
+{
+    int dev = 0;
+    KO_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if ((int)g_ws.size() <= dev)
+        g_ws.resize(dev + 1);
+    Workspace &w = g_ws[dev];
+    if (!w.ready) {
+        w.device = dev;
+        KO_HIP(hipDeviceGetAttribute(&w.cu_count, hipDeviceAttributeMultiprocessorCount, dev),
+               "hipDeviceGetAttribute");
+        KO_HIP(hipMalloc((void **)&w.counter, 2 * sizeof(unsigned long long)), "hipMalloc");
+        KO_HIP(hipMalloc((void **)&w.scratch_i64, sizeof(int64_t)), "hipMalloc");
+        KO_HIP(hipMalloc((void **)&w.scratch_order, 64), "hipMalloc");
+        KO_HIP(hipMalloc((void **)&w.scratch_stats, sizeof(ko_set_stats)), "hipMalloc");
+        KO_HIP(hipHostMalloc((void **)&w.status_host, sizeof(uint32_t), hipHostMallocDefault),
+               "hipHostMalloc");
+        KO_HIP(hipHostMalloc((void **)&w.stats_host, sizeof(ko_set_stats), hipHostMallocDefault),
+               "hipHostMalloc");
+        KO_HIP(hipHostMalloc((void **)&w.ref_host, sizeof(int64_t), hipHostMallocDefault),
+               "hipHostMalloc");
+        KO_HIP(hipMemset(w.counter, 0, 2 * sizeof(unsigned long long)), "hipMemset");
+        KO_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        *w.status_host = 0;
+        KO_HIP(hipEventCreateWithFlags(&w.staged, hipEventDisableTiming), "hipEventCreate");
+        KO_HIP(hipEventCreateWithFlags(&w.done, hipEventDisableTiming), "hipEventCreate");
+        KO_HIP(hipEventRecord(w.staged, 0), "hipEventRecord");
+        KO_HIP(hipEventRecord(w.done, 0), "hipEventRecord");
+        w.ready = true;
+    }
+    *out = &w;
+    return KO_OK;
+}
+
+void release_workspace(Workspace &w)
+{
+    if (!w.ready)
+        return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(w.device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(w.krec);
+    (void)hipFree(w.sets);
+    (void)hipFree(w.partials);
+    (void)hipFree(w.block_base);
+    (void)hipFree(w.counter);
+    (void)hipFree(w.scratch_i64);
+    (void)hipFree(w.scratch_order);
+    (void)hipFree(w.scratch_stats);
+    (void)hipHostFree(w.stage);
+    (void)hipHostFree(w.status_host);
+    (void)hipHostFree(w.stats_host);
+    (void)hipHostFree(w.ref_host);
+    (void)hipEventDestroy(w.staged);
+    (void)hipEventDestroy(w.done);
+    (void)hipSetDevice(prev);
+    w = Workspace();
+}
+
+// Device status of earlier calls: the status word is copied to pinned host
+// memory at the end of every simulate call; a nonzero value is an error.
+int check_status(Workspace &w, bool wait)
+{
+    if (!w.pending_status)
+        return KO_OK;
+    if (wait) {
+        KO_HIP(hipEventSynchronize(w.done), "hipEventSynchronize");
+    } else if (hipEventQuery(w.done) != hipSuccess) {
+        return KO_OK;  // still running: reported by a later call
+    }
+    w.pending_status = false;
+    const uint32_t st = *w.status_host;
+    if (st)
+        w.clear_status = true;
+    if (st & ko::kStatusBadOrder)
+        return fail(KO_EHIP, "device status: an explicit order was not a permutation");
+    if (st)
+        return fail(KO_EHIP, "device status: internal inconsistency (0x%x)", st);
+    return KO_OK;
+}
+
+int stage_upload(Workspace &w, hipStream_t stream, void *dst, const void *src, size_t bytes,
+                 size_t stage_off)
+{
+    std::memcpy((char *)w.stage + stage_off, src, bytes);
+    KO_HIP(hipMemcpyAsync(dst, (char *)w.stage + stage_off, bytes, hipMemcpyHostToDevice, stream),
+           "hipMemcpyAsync");
+    return KO_OK;
+}
+
+uint64_t pow2_at_least(uint64_t v)
+{
+    uint64_t p = 1;
+    while (p < v)
+        p <<= 1;
+    return p;
+}
+
+// Every check of a batch that needs no device.
+int validate_batch(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *set_offsets,
+                   int32_t n_sets, const ko_order_spec *spec, const int64_t *makespans_dev,
+                   const ko_set_stats *stats_dev, const uint64_t *hist_dev, int32_t n_bins)
+{
+    int rc = check_gpu(gpu);
+    if (rc)
+        return rc;
+    std::vector<uint64_t> per;
+    uint64_t total = 0;
+    rc = count_orders(set_offsets, n_sets, spec, &per, &total);
+    if (rc)
+        return rc;
+    if (!kernels)
+        return fail(KO_EINVAL, "kernels is NULL");
+    if (spec->mode == KO_ORDERS_EXPLICIT && total > 0 && !spec->orders_dev)
+        return fail(KO_EINVAL, "spec: EXPLICIT needs orders_dev");
+    if (hist_dev) {
+        if (!makespans_dev || !stats_dev)
+            return fail(KO_EINVAL, "a histogram needs makespans_dev and stats_dev");
+        if (n_bins < 1 || n_bins > 65536)
+            return fail(KO_EINVAL, "n_bins %d outside 1..65536", n_bins);
+    }
+    std::vector<ko::KernelRec> tmp;
+    for (int32_t s = 0; s < n_sets; s++)
+        if ((rc = derive_set(*gpu, kernels + set_offsets[s], set_offsets[s + 1] - set_offsets[s],
+                             set_offsets[s], &tmp)))
+            return rc;
+    return KO_OK;
+}
+
+struct BatchPlan {
+    std::vector<ko::KernelRec> krec;
+    std::vector<ko::SetRec> sets;
+    std::vector<uint64_t> block_base;
+    uint64_t total = 0, n_items = 0, chunk = 0, hist_blocks = 0;
+    uint32_t max_n = 0;
+};
+
+constexpr uint64_t kHistPerBlock = 1 << 16;
+
+int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernels,
+                  const int32_t *set_offsets, int32_t n_sets, const ko_order_spec *spec,
+                  const int64_t *ref_dev, int64_t *makespans_dev, ko_set_stats *stats_dev,
+                  uint64_t *hist_dev, int32_t n_bins, hipStream_t stream)
+{
+    int rc = validate_batch(gpu, kernels, set_offsets, n_sets, spec, makespans_dev, stats_dev,
+                            hist_dev, n_bins);
+    if (rc)
+        return rc;
+    std::vector<uint64_t> per_set;
+    BatchPlan plan;
+    rc = count_orders(set_offsets, n_sets, spec, &per_set, &plan.total);
+    if (rc)
+        return rc;
+    plan.krec.reserve(set_offsets[n_sets]);
+    for (int32_t s = 0; s < n_sets; s++) {
+        const int32_t n = set_offsets[s + 1] - set_offsets[s];
+        rc = derive_set(*gpu, kernels + set_offsets[s], n, set_offsets[s], &plan.krec);
+        if (rc)
+            return rc;
+        plan.max_n = std::max<uint32_t>(plan.max_n, (uint32_t)n);
+    }
+    rc = check_status(w, false);
+    if (rc)
+        return rc;
+
+    // work decomposition: chunks of consecutive orders, enough of them to
+    // balance the persistent waves, few enough to keep the partials small
+    const int slots = (gpu->n_cu + ko::kWave - 1) / ko::kWave == 3 ? 4
+                                                                   : (gpu->n_cu + ko::kWave - 1) / ko::kWave;
+    const int grid = std::max(1, w.cu_count * 8);
+    const uint64_t waves = (uint64_t)grid * 4;
+    uint64_t chunk = pow2_at_least(std::max<uint64_t>(1, plan.total / (waves * 8)));
+    chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, 16), 8192);
+    const uint64_t max_items = uint64_t(1) << 22;
+    if (plan.total / chunk > max_items)
+        chunk = pow2_at_least((plan.total + max_items - 1) / max_items);
+    plan.chunk = chunk;
+    uint64_t out_base = 0, item_base = 0, list_base = 0, hist_base = 0;
+    plan.sets.resize(n_sets);
+    plan.block_base.resize(n_sets + 1);
+    for (int32_t s = 0; s < n_sets; s++) {
+        ko::SetRec &r = plan.sets[s];
+        const int32_t n = set_offsets[s + 1] - set_offsets[s];
+        r.n = (uint32_t)n;
+        r.kbase = (uint32_t)set_offsets[s];
+        r.n_orders = per_set[s];
+        r.out_base = out_base;
+        r.rank_lo = spec->mode == KO_ORDERS_RANK_RANGE ? spec->rank_lo_hi[2 * s] : 0;
+        r.item_base = item_base;
+        r.list_base = list_base;
+        out_base += per_set[s];
+        item_base += (per_set[s] + chunk - 1) / chunk;
+        list_base += per_set[s] * (uint64_t)n;
+        plan.block_base[s] = hist_base;
+        hist_base += (per_set[s] + kHistPerBlock - 1) / kHistPerBlock;
+    }
+    plan.block_base[n_sets] = hist_base;
+    plan.n_items = item_base;
+    plan.hist_blocks = hist_base;
+
+    // device buffers
+    const size_t kbytes = plan.krec.size() * sizeof(ko::KernelRec);
+    const size_t sbytes = plan.sets.size() * sizeof(ko::SetRec);
+    const size_t bbytes = plan.block_base.size() * sizeof(uint64_t);
+    if ((rc = grow_device((void **)&w.krec, &w.krec_cap, kbytes)) ||
+        (rc = grow_device((void **)&w.sets, &w.sets_cap, sbytes)) ||
+        (rc = grow_device((void **)&w.block_base, &w.block_base_cap, bbytes)) ||
+        (rc = grow_device((void **)&w.partials, &w.partials_cap,
+                          std::max<uint64_t>(plan.n_items, 1) * sizeof(ko::Partial))))
+        return rc;
+    // the previous call on any stream must be done with the workspace
+    KO_HIP(hipStreamWaitEvent(stream, w.done, 0), "hipStreamWaitEvent");
+    const size_t stage_need = kbytes + sbytes + bbytes + 64;
+    if (stage_need > w.stage_cap) {
+        KO_HIP(hipEventSynchronize(w.staged), "hipEventSynchronize");
+        if (w.stage)
+            (void)hipHostFree(w.stage);
+        w.stage = nullptr;
+        w.stage_cap = 0;
+        KO_HIP(hipHostMalloc(&w.stage, stage_need * 2, hipHostMallocDefault), "hipHostMalloc");
+        w.stage_cap = stage_need * 2;
+    } else {
+        KO_HIP(hipEventSynchronize(w.staged), "hipEventSynchronize");
+    }
+    if ((rc = stage_upload(w, stream, w.krec, plan.krec.data(), kbytes, 0)) ||
+        (rc = stage_upload(w, stream, w.sets, plan.sets.data(), sbytes, kbytes)) ||
+        (rc = stage_upload(w, stream, w.block_base, plan.block_base.data(), bbytes, kbytes + sbytes)))
+        return rc;
+    KO_HIP(hipEventRecord(w.staged, stream), "hipEventRecord");
+
+    // the item counter restarts every call; the status word only once reported
+    int e = ko::launch_zero_u64((uint64_t *)w.counter, w.clear_status ? 2 : 1, stream);
+    w.clear_status = false;
+    if (e)
+        return hip_fail((hipError_t)e, "zero counters");
+    if (plan.n_items > 0) {
+        ko::SimArgs a;
+        a.krec = w.krec;
+        a.sets = w.sets;
+        a.n_sets = n_sets;
+        a.mode = spec->mode;
+        a.n_items = plan.n_items;
+        a.chunk = plan.chunk;
+        a.seed = spec->seed;
+        a.orders = spec->orders_dev;
+        a.ref = ref_dev;
+        a.makespans = makespans_dev;
+        a.partials = w.partials;
+        a.item_counter = w.counter;
+        a.status = (uint32_t *)(w.counter + 1);
+        a.n_cu = (uint32_t)gpu->n_cu;
+        a.cap_reg = (uint32_t)gpu->reg_cu;
+        a.cap_lds = (uint32_t)gpu->lds_cu;
+        a.cap_wave = (uint32_t)gpu->wave_cu;
+        a.cap_blk = (uint32_t)gpu->blk_cu;
+        const int g = (int)std::min<uint64_t>((uint64_t)grid, (plan.n_items + 3) / 4);
+        e = ko::launch_simulate(a, slots, plan.max_n, g, stream);
+        if (e)
+            return hip_fail((hipError_t)e, "simulate kernel launch");
+    }
+    if (stats_dev) {
+        ko::ReduceArgs r;
+        r.sets = w.sets;
+        r.n_sets = n_sets;
+        r.chunk = plan.chunk;
+        r.partials = w.partials;
+        r.stats = stats_dev;
+        e = ko::launch_reduce(r, stream);
+        if (e)
+            return hip_fail((hipError_t)e, "reduce kernel launch");
+    }
+    if (hist_dev) {
+        e = ko::launch_zero_u64(hist_dev, (uint64_t)n_sets * (uint64_t)n_bins, stream);
+        if (e)
+            return hip_fail((hipError_t)e, "zero histogram");
+        ko::HistArgs h;
+        h.sets = w.sets;
+        h.n_sets = n_sets;
+        h.makespans = makespans_dev;
+        h.stats = stats_dev;
+        h.hist = hist_dev;
+        h.n_bins = n_bins;
+        h.per_block = kHistPerBlock;
+        h.block_base = w.block_base;
+        e = ko::launch_hist(h, plan.hist_blocks, stream);
+        if (e)
+            return hip_fail((hipError_t)e, "histogram kernel launch");
+    }
+    KO_HIP(hipMemcpyAsync(w.status_host, (const void *)(w.counter + 1), sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, stream),
+           "hipMemcpyAsync");
+    KO_HIP(hipEventRecord(w.done, stream), "hipEventRecord");
+    w.pending_status = true;
+    return KO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ko_heuristic_order(const ko_gpu_model *gpu, const ko_kernel *k, int32_t n, uint32_t flags,
+                       int32_t *order_out, int32_t *round_out)
+{
+    int rc = check_gpu(gpu);
+    if (rc)
+        return rc;
+    if (!k || !order_out)
+        return fail(KO_EINVAL, "kernels and order_out must not be NULL");
+    if (n < 1 || n > ko::kMaxSet)
+        return fail(KO_EINVAL, "n %d outside 1..%d", n, ko::kMaxSet);
+    if (flags & ~(KO_HEUR_PER_BLOCK | KO_HEUR_FULL_SORT))
+        return fail(KO_EINVAL, "unknown heuristic flags 0x%x", flags);
+    try {
+        return heuristic(*gpu, k, n, flags, order_out, round_out);
+    } catch (const std::bad_alloc &) {
+        return fail(KO_ENOMEM, "host allocation failed");
+    }
+}
+
+int ko_count_orders(const int32_t *set_offsets, int32_t n_sets, const ko_order_spec *spec,
+                    uint64_t *per_set_out, uint64_t *total_out)
+{
+    if (!total_out)
+        return fail(KO_EINVAL, "total_out must not be NULL");
+    try {
+        std::vector<uint64_t> per;
+        uint64_t total = 0;
+        int rc = count_orders(set_offsets, n_sets, spec, &per, &total);
+        if (rc)
+            return rc;
+        if (per_set_out)
+            std::copy(per.begin(), per.end(), per_set_out);
+        *total_out = total;
+        return KO_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(KO_ENOMEM, "host allocation failed");
+    }
+}
+
+int ko_simulate_batch(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *set_offsets,
+                      int32_t n_sets, const ko_order_spec *spec, const int64_t *ref_makespan_dev,
+                      int64_t *makespans_dev, ko_set_stats *stats_dev, uint64_t *hist_dev,
+                      int32_t n_bins, void *hip_stream)
+{
+    try {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        Workspace *w = nullptr;
+        // validate everything that needs no device before touching the runtime
+        int rc = validate_batch(gpu, kernels, set_offsets, n_sets, spec, makespans_dev, stats_dev,
+                                hist_dev, n_bins);
+        if (rc)
+            return rc;
+        rc = get_workspace(&w);
+        if (rc)
+            return rc;
+        return simulate_impl(*w, gpu, kernels, set_offsets, n_sets, spec, ref_makespan_dev,
+                             makespans_dev, stats_dev, hist_dev, n_bins, (hipStream_t)hip_stream);
+    } catch (const std::bad_alloc &) {
+        return fail(KO_ENOMEM, "host allocation failed");
+    }
+}
+
+int ko_rank_percentile(const ko_gpu_model *gpu, const ko_kernel *k, int32_t n, const int32_t *order,
+                       uint64_t n_samples, uint64_t seed, ko_rank_result *out, void *hip_stream)
+{
+    try {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        int rc = check_gpu(gpu);
+        if (rc)
+            return rc;
+        if (!k || !order || !out)
+            return fail(KO_EINVAL, "k, order and out must not be NULL");
+        if (n < 1 || n > ko::kMaxSet)
+            return fail(KO_EINVAL, "n %d outside 1..%d", n, ko::kMaxSet);
+        if (n_samples > (uint64_t)INT64_MAX)
+            return fail(KO_ERANGE, "n_samples too large");
+        uint32_t seen = 0;
+        uint8_t ord8[64];
+        for (int32_t j = 0; j < n; j++) {
+            if (order[j] < 0 || order[j] >= n || (seen >> order[j]) & 1u)
+                return fail(KO_EINVAL, "order is not a permutation of 0..n-1");
+            seen |= 1u << order[j];
+            ord8[j] = (uint8_t)order[j];
+        }
+        {
+            std::vector<ko::KernelRec> tmp;
+            if ((rc = derive_set(*gpu, k, n, 0, &tmp)))
+                return rc;
+        }
+        Workspace *w = nullptr;
+        rc = get_workspace(&w);
+        if (rc)
+            return rc;
+        hipStream_t stream = (hipStream_t)hip_stream;
+        KO_HIP(hipStreamWaitEvent(stream, w->done, 0), "hipStreamWaitEvent");
+        KO_HIP(hipMemcpyAsync(w->scratch_order, ord8, (size_t)n, hipMemcpyHostToDevice, stream),
+               "hipMemcpyAsync");
+        KO_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        const int32_t off[2] = {0, n};
+        // 1) the makespan of the given order
+        const int64_t one = 1;
+        ko_order_spec sp1 = {KO_ORDERS_EXPLICIT, 0, nullptr, w->scratch_order, &one, 0};
+        rc = simulate_impl(*w, gpu, k, off, 1, &sp1, nullptr, w->scratch_i64, nullptr, nullptr, 0,
+                           stream);
+        if (rc)
+            return rc;
+        // 2) counts against it over all (or sampled) orders
+        const int64_t ns = (int64_t)n_samples;
+        ko_order_spec sp2 = {n_samples ? KO_ORDERS_SAMPLED : KO_ORDERS_ALL, 0, nullptr, nullptr,
+                             &ns, seed};
+        rc = simulate_impl(*w, gpu, k, off, 1, &sp2, w->scratch_i64, nullptr, w->scratch_stats,
+                           nullptr, 0, stream);
+        if (rc)
+            return rc;
+        KO_HIP(hipMemcpyAsync(w->stats_host, w->scratch_stats, sizeof(ko_set_stats),
+                              hipMemcpyDeviceToHost, stream),
+               "hipMemcpyAsync");
+        KO_HIP(hipMemcpyAsync(w->ref_host, w->scratch_i64, sizeof(int64_t), hipMemcpyDeviceToHost,
+                              stream),
+               "hipMemcpyAsync");
+        KO_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        const int64_t ms = *w->ref_host;
+        rc = check_status(*w, true);
+        if (rc)
+            return rc;
+        const ko_set_stats st = *w->stats_host;
+        out->makespan = ms;
+        out->min_makespan = st.min_makespan;
+        out->max_makespan = st.max_makespan;
+        out->n_less = st.n_less;
+        out->n_equal = st.n_equal;
+        out->n_greater = st.n_greater;
+        out->n_total = st.n_orders;
+        const double N = (double)st.n_orders;
+        out->pct_inclusive = N > 0 ? 100.0 * (double)(st.n_greater + st.n_equal) / N : 0.0;
+        out->pct_strict = N > 0 ? 100.0 * (double)st.n_greater / N : 0.0;
+        out->pct_mid = N > 0 ? 100.0 * ((double)st.n_greater + 0.5 * (double)st.n_equal) / N : 0.0;
+        return KO_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(KO_ENOMEM, "host allocation failed");
+    }
+}
+
+int ko_sync(void *hip_stream)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    KO_HIP(hipStreamSynchronize((hipStream_t)hip_stream), "hipStreamSynchronize");
+    int dev = 0;
+    KO_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < (int)g_ws.size() && g_ws[dev].ready)
+        return check_status(g_ws[dev], true);
+    return KO_OK;
+}
+
+int ko_shutdown(void)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    for (Workspace &w : g_ws)
+        release_workspace(w);
+    g_ws.clear();
+    return KO_OK;
+}
+
+const char *ko_last_error(void) { return g_error.c_str(); }
+
+}  // extern "C"
