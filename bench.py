@@ -70,6 +70,11 @@ def main():
               "(every evaluation shards by rank range; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
+    from __graft_entry__ import DEVICE_PATH_DISABLED
+    if DEVICE_PATH_DISABLED:
+        print(f"bench.py: {DEVICE_PATH_DISABLED}", file=sys.stderr)
+        sys.exit(3)
+
     import numpy as np
     import torch
 

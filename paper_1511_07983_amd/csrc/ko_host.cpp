@@ -387,12 +387,18 @@ struct Workspace {
 std::mutex g_mutex;
 std::vector<Workspace> g_ws;
 
-int grow_device(void **p, size_t *cap, size_t need)
+// Grow a workspace buffer.  Kernels of an earlier call may still read the old
+// buffer, so the previous call's completion event is awaited before freeing.
+int grow_device(hipEvent_t done, void **p, size_t *cap, size_t need)
 {
     if (need <= *cap)
         return KO_OK;
-    if (*p)
+    if (*p) {
+        hipError_t e = hipEventSynchronize(done);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipEventSynchronize");
         (void)hipFree(*p);
+    }
     *p = nullptr;
     *cap = 0;
     size_t sz = std::max<size_t>(need, 4096);
@@ -610,10 +616,10 @@ int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernel
     const size_t kbytes = plan.krec.size() * sizeof(ko::KernelRec);
     const size_t sbytes = plan.sets.size() * sizeof(ko::SetRec);
     const size_t bbytes = plan.block_base.size() * sizeof(uint64_t);
-    if ((rc = grow_device((void **)&w.krec, &w.krec_cap, kbytes)) ||
-        (rc = grow_device((void **)&w.sets, &w.sets_cap, sbytes)) ||
-        (rc = grow_device((void **)&w.block_base, &w.block_base_cap, bbytes)) ||
-        (rc = grow_device((void **)&w.partials, &w.partials_cap,
+    if ((rc = grow_device(w.done, (void **)&w.krec, &w.krec_cap, kbytes)) ||
+        (rc = grow_device(w.done, (void **)&w.sets, &w.sets_cap, sbytes)) ||
+        (rc = grow_device(w.done, (void **)&w.block_base, &w.block_base_cap, bbytes)) ||
+        (rc = grow_device(w.done, (void **)&w.partials, &w.partials_cap,
                           std::max<uint64_t>(plan.n_items, 1) * sizeof(ko::Partial))))
         return rc;
     // the previous call on any stream must be done with the workspace
