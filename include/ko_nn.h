@@ -1,0 +1,98 @@
+/*
+ * ko_nn.h — the learned launch-order surrogate on MI355X (gfx950), libko_nn.so.
+ *
+ * A set-plus-position network predicts the makespan of a launch order of a
+ * kernel set (normalised by the set's area lower bound), so that search can
+ * rank far more orders than it can simulate exactly; every order it proposes
+ * is re-simulated exactly by libko.  The kernels and launch positions are
+ * those of the paper's Table 1 and Algorithm 1 (Li, Narayana & El-Ghazawi,
+ * 2015); the network itself is this library's addition.
+ *
+ * Network (each kernel of a sample is one token of 32 inputs: 8 features, the
+ * one-hot of its launch position among 16 positions plus an "unplaced" slot
+ * for partial orders, 7 zeros):
+ *   Z1 = X W1^T + b1 per token (32->256); S = sum over tokens of relu(Z1);
+ *   A2 = relu(S W2^T + b2); A3 = relu(A2 W3^T + b3) (256->256 each);
+ *   y = A3 . w4 + b4.   Loss: mean squared error against targets t.
+ * Products run on BF16 MFMA operands (X, weights, S, A2, A3 and, backward,
+ * dZ1..dZ3) with float32 accumulation; everything else is float32; Adam
+ * updates float32 master weights and refreshes their BF16 copies.
+ *
+ * Conventions as in ko.h: 0 = KO_OK or a negative KO_E* code; "device"
+ * pointers are HIP allocations on the current device owned by the caller;
+ * all device calls are stream-ordered and asynchronous unless stated.
+ */
+#ifndef KO_NN_H
+#define KO_NN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ko.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KO_NN_FEAT 8
+#define KO_NN_POS 17      /* 16 launch positions + "unplaced" (16) */
+#define KO_NN_UNPLACED 16
+#define KO_NN_IN 32
+#define KO_NN_HID 256
+#define KO_NN_MAX_TOKENS 16
+
+/* Number of float parameters, in this order: W1[256][32], b1[256], W2[256][256],
+ * b2[256], W3[256][256], b3[256], w4[256], b4[1]  (140289). */
+size_t ko_nn_num_params(void);
+
+/* Bytes of the device state block: float32 master weights, gradients, Adam
+ * first and second moments, and BF16 working copies. */
+size_t ko_nn_state_bytes(void);
+
+/* Bytes of device workspace for a batch of B samples of n tokens. */
+size_t ko_nn_work_bytes(int32_t B, int32_t n);
+
+/* ko_nn_load — set the master weights from host float params[ko_nn_num_params()],
+ * zero gradients and Adam moments, refresh the BF16 copies.  Synchronous. */
+int ko_nn_load(void *state_dev, const float *params_host, void *hip_stream);
+
+/* ko_nn_read — copy master weights (which = 0) or gradients (which = 1) to host
+ * float out[ko_nn_num_params()].  Synchronous. */
+int ko_nn_read(const void *state_dev, int32_t which, float *out_host, void *hip_stream);
+
+/* ko_nn_features — the 8 per-kernel features (host).  out[n][8]:
+ *   log2(N_tblk)/16, waves/wave_cu, regs/reg_cu, lds/lds_cu (per block),
+ *   log2(block cycles)/32, log2(R/R_B)/8, occ/blk_cu, log2(1 + N_tblk/(occ N_CU))/8,
+ * with occ the blocks of the kernel alone that fit one CU.  Errors: KO_EINVAL. */
+int ko_nn_features(const ko_gpu_model *gpu, const ko_kernel *k, int32_t n, float *out_host);
+
+/* ko_nn_lower_bound — the set's area lower bound on any order's makespan (host):
+ * max(max_i d_i, max over resources x of ceil(sum_i N_tblk_i d_i u_x,i / (N_CU cap_x))). */
+int ko_nn_lower_bound(const ko_gpu_model *gpu, const ko_kernel *k, int32_t n, int64_t *lb_out);
+
+/* ko_nn_tokens — build BF16 tokens x[B][n][32] from features feat[S][n][8]
+ * (float32, device), the set of each sample set_of[B] (int32, device; NULL = set 0)
+ * and the launch position of each kernel pos[B][n] (uint8, device; 0..15 or 16). */
+int ko_nn_tokens(const float *feat_dev, const int32_t *set_of_dev, const uint8_t *pos_dev,
+                 int32_t B, int32_t n, uint16_t *x_dev, void *hip_stream);
+
+/* ko_nn_forward — y[B] (float32, device) for tokens x[B][n][32].  1 <= n <= 16. */
+int ko_nn_forward(const void *state_dev, const uint16_t *x_dev, int32_t B, int32_t n, float *y_dev,
+                  void *work_dev, void *hip_stream);
+
+/* ko_nn_backward — forward, loss and gradients (kept in the state block) for
+ * targets t[B] (float32, device); loss_dev (float32[1], device, nullable). */
+int ko_nn_backward(void *state_dev, const uint16_t *x_dev, const float *t_dev, int32_t B, int32_t n,
+                   float *loss_dev, void *work_dev, void *hip_stream);
+
+/* ko_nn_adam — one Adam step (bias-corrected, step >= 1) on the stored gradients. */
+int ko_nn_adam(void *state_dev, int32_t step, float lr, float beta1, float beta2, float eps,
+               void *hip_stream);
+
+const char *ko_nn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KO_NN_H */

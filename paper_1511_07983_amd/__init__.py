@@ -23,7 +23,6 @@ LIB_PATH = os.path.join(_HERE, "libko.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1511_07983_amd/build.py`")
 
-_lib = ctypes.CDLL(LIB_PATH)
 
 KO_OK = 0
 KO_EINVAL = -1
@@ -91,26 +90,36 @@ KERNEL_DTYPE = np.dtype([("n_tblk", "<i8"), ("n_inst", "<i8"), ("lds_blk", "<i8"
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 
-_lib.ko_heuristic_order.argtypes = [ctypes.POINTER(KoGpuModel), ctypes.c_void_p, ctypes.c_int32,
-                                    ctypes.c_uint32, _i32p, _i32p]
-_lib.ko_heuristic_order.restype = ctypes.c_int
-_lib.ko_count_orders.argtypes = [_i32p, ctypes.c_int32, ctypes.POINTER(KoOrderSpec), _u64p, _u64p]
-_lib.ko_count_orders.restype = ctypes.c_int
-_lib.ko_simulate_batch.argtypes = [ctypes.POINTER(KoGpuModel), ctypes.c_void_p, _i32p,
-                                   ctypes.c_int32, ctypes.POINTER(KoOrderSpec), ctypes.c_void_p,
-                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                   ctypes.c_int32, ctypes.c_void_p]
-_lib.ko_simulate_batch.restype = ctypes.c_int
-_lib.ko_rank_percentile.argtypes = [ctypes.POINTER(KoGpuModel), ctypes.c_void_p, ctypes.c_int32,
-                                    _i32p, ctypes.c_uint64, ctypes.c_uint64,
-                                    ctypes.POINTER(KoRankResult), ctypes.c_void_p]
-_lib.ko_rank_percentile.restype = ctypes.c_int
-_lib.ko_sync.argtypes = [ctypes.c_void_p]
-_lib.ko_sync.restype = ctypes.c_int
-_lib.ko_shutdown.argtypes = []
-_lib.ko_shutdown.restype = ctypes.c_int
-_lib.ko_last_error.argtypes = []
-_lib.ko_last_error.restype = ctypes.c_char_p
+_lib = None
+
+
+def _L():
+    """libko.so, loaded on first use (the package can be imported without loading it)."""
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(LIB_PATH)
+        lib.ko_heuristic_order.argtypes = [ctypes.POINTER(KoGpuModel), ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_uint32, _i32p, _i32p]
+        lib.ko_heuristic_order.restype = ctypes.c_int
+        lib.ko_count_orders.argtypes = [_i32p, ctypes.c_int32, ctypes.POINTER(KoOrderSpec), _u64p, _u64p]
+        lib.ko_count_orders.restype = ctypes.c_int
+        lib.ko_simulate_batch.argtypes = [ctypes.POINTER(KoGpuModel), ctypes.c_void_p, _i32p,
+                                           ctypes.c_int32, ctypes.POINTER(KoOrderSpec), ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int32, ctypes.c_void_p]
+        lib.ko_simulate_batch.restype = ctypes.c_int
+        lib.ko_rank_percentile.argtypes = [ctypes.POINTER(KoGpuModel), ctypes.c_void_p, ctypes.c_int32,
+                                            _i32p, ctypes.c_uint64, ctypes.c_uint64,
+                                            ctypes.POINTER(KoRankResult), ctypes.c_void_p]
+        lib.ko_rank_percentile.restype = ctypes.c_int
+        lib.ko_sync.argtypes = [ctypes.c_void_p]
+        lib.ko_sync.restype = ctypes.c_int
+        lib.ko_shutdown.argtypes = []
+        lib.ko_shutdown.restype = ctypes.c_int
+        lib.ko_last_error.argtypes = []
+        lib.ko_last_error.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
 
 
 class KoError(RuntimeError):
@@ -120,7 +129,7 @@ class KoError(RuntimeError):
 
 
 def ko_last_error() -> str:
-    return _lib.ko_last_error().decode()
+    return _L().ko_last_error().decode()
 
 
 def _check(rc: int):
@@ -184,7 +193,7 @@ def ko_heuristic_order(gpu, kernels, flags: int = 0, *, with_rounds: bool = Fals
     n = len(k)
     order = np.zeros(max(n, 1), dtype=np.int32)
     rounds = np.zeros(max(n, 1), dtype=np.int32)
-    _check(_lib.ko_heuristic_order(ctypes.byref(g), k.ctypes.data if n else None, n, flags,
+    _check(_L().ko_heuristic_order(ctypes.byref(g), k.ctypes.data if n else None, n, flags,
                                    order.ctypes.data_as(_i32p), rounds.ctypes.data_as(_i32p)))
     if with_rounds:
         return order[:n].tolist(), rounds[:n].tolist()
@@ -242,7 +251,7 @@ def ko_count_orders(set_offsets, spec: OrderSpec):
     per = np.zeros(max(n_sets, 1), dtype=np.uint64)
     total = np.zeros(1, dtype=np.uint64)
     sp = spec.c_struct()
-    _check(_lib.ko_count_orders(off.ctypes.data_as(_i32p), n_sets, ctypes.byref(sp),
+    _check(_L().ko_count_orders(off.ctypes.data_as(_i32p), n_sets, ctypes.byref(sp),
                                 per.ctypes.data_as(_u64p), total.ctypes.data_as(_u64p)))
     return per[:n_sets], int(total[0])
 
@@ -271,7 +280,7 @@ def ko_simulate_batch(gpu, kernels, set_offsets, spec: OrderSpec, *, ref_makespa
     ms_p = _dev_ptr(makespans, torch.int64, total, "makespans")
     st_p = _dev_ptr(stats, torch.int64, 8 * n_sets, "stats")
     h_p = _dev_ptr(hist, torch.int64, n_sets * max(n_bins, 0), "hist")
-    _check(_lib.ko_simulate_batch(ctypes.byref(g), k.ctypes.data if len(k) else None,
+    _check(_L().ko_simulate_batch(ctypes.byref(g), k.ctypes.data if len(k) else None,
                                   off.ctypes.data_as(_i32p), n_sets, ctypes.byref(sp), ref_p,
                                   ms_p, st_p, h_p, n_bins, _stream_handle(stream)))
     return per, total
@@ -288,19 +297,19 @@ def ko_rank_percentile(gpu, kernels, order, n_samples: int = 0, seed: int = 0, s
     k = kernel_array(kernels)
     o = np.ascontiguousarray(order, dtype=np.int32)
     res = KoRankResult()
-    _check(_lib.ko_rank_percentile(ctypes.byref(g), k.ctypes.data if len(k) else None, len(k),
+    _check(_L().ko_rank_percentile(ctypes.byref(g), k.ctypes.data if len(k) else None, len(k),
                                    o.ctypes.data_as(_i32p), int(n_samples), int(seed) & ((1 << 64) - 1),
                                    ctypes.byref(res), _stream_handle(stream)))
     return {f: getattr(res, f) for f, _ in KoRankResult._fields_}
 
 
 def ko_sync(stream=None):
-    _check(_lib.ko_sync(_stream_handle(stream)))
+    _check(_L().ko_sync(_stream_handle(stream)))
 
 
 def ko_shutdown():
-    _check(_lib.ko_shutdown())
+    _check(_L().ko_shutdown())
 
 
 def library_handle():
-    return _lib
+    return _L()

@@ -2,7 +2,8 @@
 
     python paper_1511_07983_amd/build.py
 
-compiles csrc/ko_host.cpp and csrc/ko_sim.hip into paper_1511_07983_amd/libko.so.
+compiles csrc/ko_host.cpp and csrc/ko_sim.hip into paper_1511_07983_amd/libko.so,
+and csrc/ko_nn.hip (the learned surrogate) into paper_1511_07983_amd/libko_nn.so.
 Host code is built with -ffp-contract=off so the binary64 scores of the
 launch-order heuristic are evaluated exactly as written.
 """
@@ -18,6 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libko.so")
+LIB_NN = os.path.join(HERE, "libko_nn.so")
 ARCH = os.environ.get("KO_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -49,6 +51,11 @@ def build(verbose: bool = True) -> str:
     tmp = LIB + ".tmp"
     _run([HIPCC, *DEVICE, "-shared", "-fPIC", host_o, sim_o, "-o", tmp])
     os.replace(tmp, LIB)
+    nn_o = os.path.join(objdir, "ko_nn.o")
+    _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_nn.hip"), "-o", nn_o])
+    tmp = LIB_NN + ".tmp"
+    _run([HIPCC, *DEVICE, "-shared", "-fPIC", nn_o, "-o", tmp])
+    os.replace(tmp, LIB_NN)
     return LIB
 
 

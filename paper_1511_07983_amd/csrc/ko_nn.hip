@@ -1,0 +1,708 @@
+// libko_nn: the learned launch-order surrogate (include/ko_nn.h) on gfx950.
+//
+// One generic BF16 MFMA GEMM (v_mfma_f32_16x16x32_bf16, float32 accumulate)
+// with strided operands and fused epilogues carries every product of the
+// forward and backward passes; small kernels do pooling, the output layer,
+// the loss, column sums and Adam.  All reductions are deterministic (no
+// floating-point atomics).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ko_nn.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kHid = KO_NN_HID;
+constexpr int kIn = KO_NN_IN;
+
+// flat parameter offsets
+constexpr size_t kW1 = 0;
+constexpr size_t kB1 = kW1 + (size_t)kHid * kIn;
+constexpr size_t kW2 = kB1 + kHid;
+constexpr size_t kB2 = kW2 + (size_t)kHid * kHid;
+constexpr size_t kW3 = kB2 + kHid;
+constexpr size_t kB3 = kW3 + (size_t)kHid * kHid;
+constexpr size_t kW4 = kB3 + kHid;
+constexpr size_t kB4 = kW4 + kHid;
+constexpr size_t kNP = kB4 + 1;                  // 140289
+constexpr size_t kNPad = (kNP + 63) / 64 * 64;   // 140352
+
+struct State {
+    float *master, *grad, *m, *v;
+    uint16_t *wb;
+};
+
+State state_of(void *p)
+{
+    State s;
+    char *c = (char *)p;
+    s.master = (float *)c;
+    s.grad = s.master + kNPad;
+    s.m = s.grad + kNPad;
+    s.v = s.m + kNPad;
+    s.wb = (uint16_t *)(s.v + kNPad);
+    return s;
+}
+
+__host__ __device__ inline uint16_t to_bf16(float f)
+{
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ inline float from_bf16(uint16_t h)
+{
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+// ------------------------------------------------------------------ GEMM
+//
+// C[m][n] = sum_k A(m,k) B(k,n) with A(m,k) = A[m*sam + k*sak] and
+// B(k,n) = B[k*sbk + n*sbn] (BF16), a 64x64 tile per workgroup of 4 waves,
+// each wave a 32x32 block of 2x2 MFMA 16x16x32 tiles, K in steps of 32
+// staged through LDS (rows padded to 40 elements).
+enum { kEpiNone = 0, kEpiRelu = 1, kEpiMask = 2 };
+
+struct GemmArgs {
+    const uint16_t *A;
+    int64_t sam, sak;
+    const uint16_t *B;
+    int64_t sbk, sbn;
+    int32_t M, N, K;
+    int32_t epi;
+    const float *bias;   // [N] or null
+    const float *zref;   // kEpiMask: mask source, row-major with ldz
+    int64_t ldz;
+    float *C;            // fp32 result, row-major with ldc (or null)
+    int64_t ldc;
+    uint16_t *Cb;        // bf16 result (relu(C) for kEpiRelu), row-major with ldcb (or null)
+    int64_t ldcb;
+};
+
+constexpr int kTile = 64;
+constexpr int kKStep = 32;
+constexpr int kPad = 40;
+
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[kTile][kPad];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kTile][kPad];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t m0 = (int64_t)blockIdx.x * kTile;
+    const int64_t n0 = (int64_t)blockIdx.y * kTile;
+    f32x4 acc[2][2];
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++)
+            acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int lr = tid >> 2;         // tile row (A) / tile column (B) loaded by this thread
+    const int lk = (tid & 3) * 8;    // first of its 8 k values
+    for (int64_t k0 = 0; k0 < a.K; k0 += kKStep) {
+        {
+            const int64_t m = m0 + lr;
+            for (int e = 0; e < 8; e++) {
+                const int64_t k = k0 + lk + e;
+                As[lr][lk + e] = (m < a.M && k < a.K) ? a.A[m * a.sam + k * a.sak] : (uint16_t)0;
+            }
+            const int64_t n = n0 + lr;
+            for (int e = 0; e < 8; e++) {
+                const int64_t k = k0 + lk + e;
+                Bs[lr][lk + e] = (n < a.N && k < a.K) ? a.B[k * a.sbk + n * a.sbn] : (uint16_t)0;
+            }
+        }
+        __syncthreads();
+        const int kk = (lane >> 4) * 8;
+        bf16x8 af[2], bfr[2];
+        for (int i = 0; i < 2; i++)
+            af[i] = *reinterpret_cast<const bf16x8 *>(&As[wm * 32 + i * 16 + (lane & 15)][kk]);
+        for (int j = 0; j < 2; j++)
+            bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn * 32 + j * 16 + (lane & 15)][kk]);
+        for (int i = 0; i < 2; i++)
+            for (int j = 0; j < 2; j++)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++)
+            for (int e = 0; e < 4; e++) {
+                const int64_t row = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + e;
+                const int64_t col = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (row >= a.M || col >= a.N)
+                    continue;
+                float v = acc[i][j][e];
+                if (a.epi == kEpiMask) {
+                    v = (a.zref[row * a.ldz + col] > 0.f) ? v : 0.f;
+                } else if (a.bias) {
+                    v += a.bias[col];
+                }
+                if (a.C)
+                    a.C[row * a.ldc + col] = v;
+                if (a.Cb)
+                    a.Cb[row * a.ldcb + col] = to_bf16(a.epi == kEpiRelu ? fmaxf(v, 0.f) : v);
+            }
+}
+
+// ------------------------------------------------------------------ small kernels
+
+// S[b][c] = sum_j relu(Z1[b*n+j][c]); also its BF16 copy.
+__global__ void pool_kernel(const float *Z1, int32_t B, int32_t n, float *S, uint16_t *Sb)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)B * kHid)
+        return;
+    const int64_t b = idx / kHid, c = idx % kHid;
+    float s = 0.f;
+    for (int j = 0; j < n; j++)
+        s += fmaxf(Z1[(b * n + j) * kHid + c], 0.f);
+    S[idx] = s;
+    Sb[idx] = to_bf16(s);
+}
+
+__device__ inline float wave_sum(float v)
+{
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o);
+    return v;
+}
+
+// Deterministic block sum (256 threads) of v; valid in thread 0.
+__device__ inline float block_sum(float v, float *red)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        red[wave] = v;
+    __syncthreads();
+    float t = 0.f;
+    if (threadIdx.x == 0)
+        t = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+    return t;
+}
+
+// y[b] = A3b[b] . w4b + b4 (one wave per sample).
+__global__ __launch_bounds__(256) void out_forward_kernel(const uint16_t *A3b, const uint16_t *wb,
+                                                          const float *master, int32_t B, float *y)
+{
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= B)
+        return;
+    float s = 0.f;
+    for (int c = lane; c < kHid; c += 64)
+        s += from_bf16(A3b[b * kHid + c]) * from_bf16(wb[kW4 + c]);
+    s = wave_sum(s);
+    if (lane == 0)
+        y[b] = s + master[kB4];
+}
+
+// loss = mean (y - t)^2 ; dy = 2 (y - t) / B   (single workgroup)
+__global__ __launch_bounds__(256) void loss_kernel(const float *y, const float *t, int32_t B, float *dy,
+                                                   float *loss)
+{
+    __shared__ float red[4];
+    float s = 0.f;
+    for (int64_t b = threadIdx.x; b < B; b += blockDim.x) {
+        const float d = y[b] - t[b];
+        s += d * d;
+        dy[b] = 2.f * d / (float)B;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0 && loss)
+        *loss = s / (float)B;
+}
+
+// dZ3[b][c] = dy[b] * w4b[c] * [Z3 > 0]   (fp32 and bf16)
+__global__ void out_backward_kernel(const float *dy, const uint16_t *wb, const float *Z3, int32_t B,
+                                    float *dZ3, uint16_t *dZ3b)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)B * kHid)
+        return;
+    const int64_t b = idx / kHid, c = idx % kHid;
+    const float v = (Z3[idx] > 0.f) ? dy[b] * from_bf16(wb[kW4 + c]) : 0.f;
+    dZ3[idx] = v;
+    dZ3b[idx] = to_bf16(v);
+}
+
+// out[c] = sum_r w(r) * X(r, c) for c < cols, one workgroup per column, where
+// X(r, c) is float32 (Xf) or bf16 (Xb) with row pitch ld, and w(r) is wrow[r]
+// or 1.  Also, for column index cols (an extra workgroup), out[cols] = sum_r wrow[r].
+__global__ __launch_bounds__(256) void colsum_kernel(const float *Xf, const uint16_t *Xb, int64_t ld,
+                                                     int64_t rows, int32_t cols, const float *wrow,
+                                                     float *out, int32_t out_extra)
+{
+    __shared__ float red[4];
+    const int c = blockIdx.x;
+    float s = 0.f;
+    if (c < cols) {
+        for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) {
+            const float x = Xf ? Xf[r * ld + c] : from_bf16(Xb[r * ld + c]);
+            s += wrow ? wrow[r] * x : x;
+        }
+    } else {
+        for (int64_t r = threadIdx.x; r < rows; r += blockDim.x)
+            s += wrow[r];
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0)
+        out[c < cols ? c : out_extra] = s;
+}
+
+// dZ1[r][c] = dS[r / n][c] * [Z1[r][c] > 0]   (fp32 and bf16)
+__global__ void dz1_kernel(const float *dS, const float *Z1, int32_t B, int32_t n, float *dZ1,
+                           uint16_t *dZ1b)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)B * n * kHid)
+        return;
+    const int64_t r = idx / kHid, c = idx % kHid;
+    const float v = (Z1[idx] > 0.f) ? dS[(r / n) * kHid + c] : 0.f;
+    dZ1[idx] = v;
+    dZ1b[idx] = to_bf16(v);
+}
+
+__global__ void adam_kernel(float *w, const float *g, float *m, float *v, int64_t count, float lr,
+                            float b1, float b2, float eps, float c1, float c2, uint16_t *wb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count)
+        return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    wb[i] = to_bf16(wi);
+}
+
+__global__ void refresh_kernel(const float *w, uint16_t *wb, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        wb[i] = to_bf16(w[i]);
+}
+
+__global__ void zero_f32_kernel(float *p, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        p[i] = 0.f;
+}
+
+// x[b][i][0..7] = bf16(feat[set][i][.]); x[b][i][8 + pos] = 1; rest 0.
+__global__ void tokens_kernel(const float *feat, const int32_t *set_of, const uint8_t *pos, int32_t B,
+                              int32_t n, uint16_t *x)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)B * n * kIn)
+        return;
+    const int64_t t = idx / kIn;
+    const int f = (int)(idx % kIn);
+    const int64_t b = t / n, i = t % n;
+    const int64_t s = set_of ? set_of[b] : 0;
+    uint16_t v = 0;
+    if (f < KO_NN_FEAT) {
+        v = to_bf16(feat[(s * n + i) * KO_NN_FEAT + f]);
+    } else if (f < KO_NN_FEAT + KO_NN_POS) {
+        v = (pos[b * n + i] == (uint8_t)(f - KO_NN_FEAT)) ? (uint16_t)0x3F80 : (uint16_t)0;
+    }
+    x[idx] = v;
+}
+
+// ------------------------------------------------------------------ host side
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define NN_HIP(call)                                                            \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess)                                                   \
+            return fail(KO_EHIP, "%s: %s", #call, hipGetErrorString(e_));       \
+    } while (0)
+
+#define NN_LAUNCHED()                                                           \
+    do {                                                                        \
+        hipError_t e_ = hipGetLastError();                                      \
+        if (e_ != hipSuccess)                                                   \
+            return fail(KO_EHIP, "kernel launch: %s", hipGetErrorString(e_));   \
+    } while (0)
+
+unsigned grid1(int64_t count) { return (unsigned)((count + 255) / 256); }
+
+struct Work {
+    float *Z1, *S, *Z2, *Z3, *y, *dy, *dZ3, *dZ2, *dS, *dZ1;
+    uint16_t *Sb, *A2b, *A3b, *dZ3b, *dZ2b, *dZ1b;
+};
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+Work work_of(void *p, int64_t B, int64_t n, size_t *total)
+{
+    char *c = (char *)p;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *r = c ? c + off : nullptr;
+        off += align256(bytes);
+        return r;
+    };
+    const int64_t BH = B * kHid, TH = B * n * kHid;
+    Work w;
+    w.Z1 = (float *)take(TH * 4);
+    w.dZ1 = (float *)take(TH * 4);
+    w.dZ1b = (uint16_t *)take(TH * 2);
+    w.S = (float *)take(BH * 4);
+    w.Sb = (uint16_t *)take(BH * 2);
+    w.Z2 = (float *)take(BH * 4);
+    w.A2b = (uint16_t *)take(BH * 2);
+    w.Z3 = (float *)take(BH * 4);
+    w.A3b = (uint16_t *)take(BH * 2);
+    w.dZ3 = (float *)take(BH * 4);
+    w.dZ3b = (uint16_t *)take(BH * 2);
+    w.dZ2 = (float *)take(BH * 4);
+    w.dZ2b = (uint16_t *)take(BH * 2);
+    w.dS = (float *)take(BH * 4);
+    w.y = (float *)take(B * 4);
+    w.dy = (float *)take(B * 4);
+    *total = off;
+    return w;
+}
+
+int gemm(const GemmArgs &a, hipStream_t st)
+{
+    if (a.M <= 0 || a.N <= 0 || a.K <= 0)
+        return KO_OK;
+    dim3 grid((unsigned)((a.M + kTile - 1) / kTile), (unsigned)((a.N + kTile - 1) / kTile));
+    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, st, a);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+GemmArgs gemm_args(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk,
+                   int64_t sbn, int32_t M, int32_t N, int32_t K)
+{
+    GemmArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.A = A;
+    a.sam = sam;
+    a.sak = sak;
+    a.B = B;
+    a.sbk = sbk;
+    a.sbn = sbn;
+    a.M = M;
+    a.N = N;
+    a.K = K;
+    a.epi = kEpiNone;
+    return a;
+}
+
+int check_batch(const void *state, const void *x, int32_t B, int32_t n, const void *work)
+{
+    if (!state || !x || !work)
+        return fail(KO_EINVAL, "state, tokens and workspace must not be NULL");
+    if (B < 1 || n < 1 || n > KO_NN_MAX_TOKENS)
+        return fail(KO_EINVAL, "B must be >= 1 and n in 1..%d", KO_NN_MAX_TOKENS);
+    if ((int64_t)B * n * kHid > (int64_t)1 << 31)
+        return fail(KO_EINVAL, "batch too large");
+    return KO_OK;
+}
+
+int forward_impl(const State &s, const uint16_t *x, int32_t B, int32_t n, float *y, Work &w,
+                 hipStream_t st)
+{
+    int rc;
+    const int32_t T = B * n;
+    // Z1 = X W1^T + b1
+    GemmArgs a = gemm_args(x, kIn, 1, s.wb + kW1, 1, kIn, T, kHid, kIn);
+    a.bias = s.master + kB1;
+    a.C = w.Z1;
+    a.ldc = kHid;
+    if ((rc = gemm(a, st)))
+        return rc;
+    hipLaunchKernelGGL(pool_kernel, dim3(grid1((int64_t)B * kHid)), dim3(256), 0, st, w.Z1, B, n, w.S,
+                       w.Sb);
+    NN_LAUNCHED();
+    // A2 = relu(S W2^T + b2)
+    a = gemm_args(w.Sb, kHid, 1, s.wb + kW2, 1, kHid, B, kHid, kHid);
+    a.bias = s.master + kB2;
+    a.epi = kEpiRelu;
+    a.C = w.Z2;
+    a.ldc = kHid;
+    a.Cb = w.A2b;
+    a.ldcb = kHid;
+    if ((rc = gemm(a, st)))
+        return rc;
+    // A3 = relu(A2 W3^T + b3)
+    a = gemm_args(w.A2b, kHid, 1, s.wb + kW3, 1, kHid, B, kHid, kHid);
+    a.bias = s.master + kB3;
+    a.epi = kEpiRelu;
+    a.C = w.Z3;
+    a.ldc = kHid;
+    a.Cb = w.A3b;
+    a.ldcb = kHid;
+    if ((rc = gemm(a, st)))
+        return rc;
+    hipLaunchKernelGGL(out_forward_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, st, w.A3b,
+                       s.wb, s.master, B, y);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ko_nn_num_params(void) { return kNP; }
+
+size_t ko_nn_state_bytes(void) { return kNPad * 4 * 4 + kNPad * 2; }
+
+size_t ko_nn_work_bytes(int32_t B, int32_t n)
+{
+    if (B < 1 || n < 1)
+        return 0;
+    size_t total = 0;
+    (void)work_of(nullptr, B, n, &total);
+    return total;
+}
+
+int ko_nn_load(void *state_dev, const float *params_host, void *hip_stream)
+{
+    if (!state_dev || !params_host)
+        return fail(KO_EINVAL, "state and params must not be NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    State s = state_of(state_dev);
+    std::vector<float> buf(kNPad, 0.f);
+    std::memcpy(buf.data(), params_host, kNP * sizeof(float));
+    NN_HIP(hipMemcpyAsync(s.master, buf.data(), kNPad * 4, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(zero_f32_kernel, dim3(grid1(3 * (int64_t)kNPad)), dim3(256), 0, st, s.grad,
+                       3 * (int64_t)kNPad);
+    NN_LAUNCHED();
+    hipLaunchKernelGGL(refresh_kernel, dim3(grid1(kNPad)), dim3(256), 0, st, s.master, s.wb,
+                       (int64_t)kNPad);
+    NN_LAUNCHED();
+    NN_HIP(hipStreamSynchronize(st));
+    return KO_OK;
+}
+
+int ko_nn_read(const void *state_dev, int32_t which, float *out_host, void *hip_stream)
+{
+    if (!state_dev || !out_host || (which != 0 && which != 1))
+        return fail(KO_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)hip_stream;
+    State s = state_of(const_cast<void *>(state_dev));
+    NN_HIP(hipMemcpyAsync(out_host, which ? s.grad : s.master, kNP * 4, hipMemcpyDeviceToHost, st));
+    NN_HIP(hipStreamSynchronize(st));
+    return KO_OK;
+}
+
+int ko_nn_features(const ko_gpu_model *g, const ko_kernel *k, int32_t n, float *out)
+{
+    if (!g || !k || !out || n < 1)
+        return fail(KO_EINVAL, "bad arguments");
+    if (g->n_cu < 1 || g->reg_cu < 1 || g->lds_cu < 1 || g->wave_cu < 1 || g->blk_cu < 1 ||
+        g->rb_milli < 1 || g->wave_size < 1)
+        return fail(KO_EINVAL, "invalid gpu model");
+    for (int32_t i = 0; i < n; i++) {
+        const ko_kernel &q = k[i];
+        if (q.n_tblk < 1 || q.n_inst < 1 || q.lds_blk < 0 || q.waves_blk < 1 || q.regs_thr < 1 ||
+            q.r_milli < 1)
+            return fail(KO_EINVAL, "kernel %d: invalid descriptor", i);
+        const double ureg = (double)q.regs_thr * q.waves_blk * g->wave_size;
+        const double ulds = (double)q.lds_blk;
+        const double uwave = (double)q.waves_blk;
+        if (ureg > (double)g->reg_cu || ulds > (double)g->lds_cu || uwave > (double)g->wave_cu)
+            return fail(KO_EINVAL, "kernel %d: block exceeds an empty CU", i);
+        const int64_t hi = q.r_milli > g->rb_milli ? q.r_milli : g->rb_milli;
+        const double dur = (double)((q.n_inst * hi + q.r_milli - 1) / q.r_milli);
+        int64_t occ = g->blk_cu;
+        occ = std::min<int64_t>(occ, g->reg_cu / (int64_t)ureg);
+        occ = std::min<int64_t>(occ, g->wave_cu / q.waves_blk);
+        if (q.lds_blk > 0)
+            occ = std::min<int64_t>(occ, g->lds_cu / q.lds_blk);
+        float *f = out + (size_t)i * KO_NN_FEAT;
+        f[0] = (float)(std::log2((double)q.n_tblk) / 16.0);
+        f[1] = (float)(uwave / (double)g->wave_cu);
+        f[2] = (float)(ureg / (double)g->reg_cu);
+        f[3] = (float)(ulds / (double)g->lds_cu);
+        f[4] = (float)(std::log2(dur) / 32.0);
+        f[5] = (float)(std::log2((double)q.r_milli / (double)g->rb_milli) / 8.0);
+        f[6] = (float)((double)occ / (double)g->blk_cu);
+        f[7] = (float)(std::log2(1.0 + (double)q.n_tblk / ((double)occ * (double)g->n_cu)) / 8.0);
+    }
+    return KO_OK;
+}
+
+int ko_nn_lower_bound(const ko_gpu_model *g, const ko_kernel *k, int32_t n, int64_t *lb_out)
+{
+    if (!g || !k || !lb_out || n < 1)
+        return fail(KO_EINVAL, "bad arguments");
+    const int64_t cap[4] = {g->reg_cu, g->lds_cu, g->wave_cu, g->blk_cu};
+    __int128 area[4] = {0, 0, 0, 0};
+    int64_t lb = 0;
+    for (int32_t i = 0; i < n; i++) {
+        const ko_kernel &q = k[i];
+        if (q.n_tblk < 1 || q.n_inst < 1 || q.r_milli < 1 || q.waves_blk < 1 || q.regs_thr < 1)
+            return fail(KO_EINVAL, "kernel %d: invalid descriptor", i);
+        const int64_t hi = q.r_milli > g->rb_milli ? q.r_milli : g->rb_milli;
+        const int64_t d = (q.n_inst * hi + q.r_milli - 1) / q.r_milli;
+        lb = std::max(lb, d);
+        const int64_t u[4] = {(int64_t)q.regs_thr * q.waves_blk * g->wave_size, q.lds_blk,
+                              q.waves_blk, 1};
+        for (int x = 0; x < 4; x++)
+            area[x] += (__int128)q.n_tblk * d * u[x];
+    }
+    for (int x = 0; x < 4; x++) {
+        const __int128 den = (__int128)g->n_cu * cap[x];
+        const __int128 v = (area[x] + den - 1) / den;
+        lb = std::max<int64_t>(lb, (int64_t)v);
+    }
+    *lb_out = lb;
+    return KO_OK;
+}
+
+int ko_nn_tokens(const float *feat_dev, const int32_t *set_of_dev, const uint8_t *pos_dev, int32_t B,
+                 int32_t n, uint16_t *x_dev, void *hip_stream)
+{
+    if (!feat_dev || !pos_dev || !x_dev || B < 1 || n < 1 || n > KO_NN_MAX_TOKENS)
+        return fail(KO_EINVAL, "bad arguments");
+    hipLaunchKernelGGL(tokens_kernel, dim3(grid1((int64_t)B * n * kIn)), dim3(256), 0,
+                       (hipStream_t)hip_stream, feat_dev, set_of_dev, pos_dev, B, n, x_dev);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+int ko_nn_forward(const void *state_dev, const uint16_t *x_dev, int32_t B, int32_t n, float *y_dev,
+                  void *work_dev, void *hip_stream)
+{
+    int rc = check_batch(state_dev, x_dev, B, n, work_dev);
+    if (rc)
+        return rc;
+    if (!y_dev)
+        return fail(KO_EINVAL, "y must not be NULL");
+    size_t total;
+    Work w = work_of(work_dev, B, n, &total);
+    return forward_impl(state_of(const_cast<void *>(state_dev)), x_dev, B, n, y_dev, w,
+                        (hipStream_t)hip_stream);
+}
+
+int ko_nn_backward(void *state_dev, const uint16_t *x_dev, const float *t_dev, int32_t B, int32_t n,
+                   float *loss_dev, void *work_dev, void *hip_stream)
+{
+    int rc = check_batch(state_dev, x_dev, B, n, work_dev);
+    if (rc)
+        return rc;
+    if (!t_dev)
+        return fail(KO_EINVAL, "targets must not be NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    size_t total;
+    Work w = work_of(work_dev, B, n, &total);
+    State s = state_of(state_dev);
+    if ((rc = forward_impl(s, x_dev, B, n, w.y, w, st)))
+        return rc;
+    const int32_t T = B * n;
+    hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, st, w.y, t_dev, B, w.dy, loss_dev);
+    NN_LAUNCHED();
+    // output layer: dw4[c] = sum_b dy[b] A3b[b][c], db4 = sum_b dy[b]
+    hipLaunchKernelGGL(colsum_kernel, dim3(kHid + 1), dim3(256), 0, st, (const float *)nullptr,
+                       w.A3b, (int64_t)kHid, (int64_t)B, kHid, w.dy, s.grad + kW4,
+                       (int32_t)(kB4 - kW4));
+    NN_LAUNCHED();
+    hipLaunchKernelGGL(out_backward_kernel, dim3(grid1((int64_t)B * kHid)), dim3(256), 0, st, w.dy,
+                       s.wb, w.Z3, B, w.dZ3, w.dZ3b);
+    NN_LAUNCHED();
+    // layer 3: db3, dW3 = dZ3b^T A2b, dZ2 = (dZ3b W3b) * [Z2 > 0]
+    hipLaunchKernelGGL(colsum_kernel, dim3(kHid), dim3(256), 0, st, w.dZ3, (const uint16_t *)nullptr,
+                       (int64_t)kHid, (int64_t)B, kHid, (const float *)nullptr, s.grad + kB3, 0);
+    NN_LAUNCHED();
+    GemmArgs a = gemm_args(w.dZ3b, 1, kHid, w.A2b, kHid, 1, kHid, kHid, B);
+    a.C = s.grad + kW3;
+    a.ldc = kHid;
+    if ((rc = gemm(a, st)))
+        return rc;
+    a = gemm_args(w.dZ3b, kHid, 1, s.wb + kW3, kHid, 1, B, kHid, kHid);
+    a.epi = kEpiMask;
+    a.zref = w.Z2;
+    a.ldz = kHid;
+    a.C = w.dZ2;
+    a.ldc = kHid;
+    a.Cb = w.dZ2b;
+    a.ldcb = kHid;
+    if ((rc = gemm(a, st)))
+        return rc;
+    // layer 2: db2, dW2 = dZ2b^T Sb, dS = dZ2b W2b
+    hipLaunchKernelGGL(colsum_kernel, dim3(kHid), dim3(256), 0, st, w.dZ2, (const uint16_t *)nullptr,
+                       (int64_t)kHid, (int64_t)B, kHid, (const float *)nullptr, s.grad + kB2, 0);
+    NN_LAUNCHED();
+    a = gemm_args(w.dZ2b, 1, kHid, w.Sb, kHid, 1, kHid, kHid, B);
+    a.C = s.grad + kW2;
+    a.ldc = kHid;
+    if ((rc = gemm(a, st)))
+        return rc;
+    a = gemm_args(w.dZ2b, kHid, 1, s.wb + kW2, kHid, 1, B, kHid, kHid);
+    a.C = w.dS;
+    a.ldc = kHid;
+    if ((rc = gemm(a, st)))
+        return rc;
+    // layer 1: dZ1 = dS (per token) * [Z1 > 0]; db1; dW1 = dZ1b^T X
+    hipLaunchKernelGGL(dz1_kernel, dim3(grid1((int64_t)T * kHid)), dim3(256), 0, st, w.dS, w.Z1, B, n,
+                       w.dZ1, w.dZ1b);
+    NN_LAUNCHED();
+    hipLaunchKernelGGL(colsum_kernel, dim3(kHid), dim3(256), 0, st, w.dZ1, (const uint16_t *)nullptr,
+                       (int64_t)kHid, (int64_t)T, kHid, (const float *)nullptr, s.grad + kB1, 0);
+    NN_LAUNCHED();
+    a = gemm_args(w.dZ1b, 1, kHid, x_dev, kIn, 1, kHid, kIn, T);
+    a.C = s.grad + kW1;
+    a.ldc = kIn;
+    if ((rc = gemm(a, st)))
+        return rc;
+    return KO_OK;
+}
+
+int ko_nn_adam(void *state_dev, int32_t step, float lr, float beta1, float beta2, float eps,
+               void *hip_stream)
+{
+    if (!state_dev || step < 1)
+        return fail(KO_EINVAL, "bad arguments");
+    State s = state_of(state_dev);
+    const float c1 = 1.f - std::pow(beta1, (float)step);
+    const float c2 = 1.f - std::pow(beta2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3(grid1(kNP)), dim3(256), 0, (hipStream_t)hip_stream, s.master,
+                       s.grad, s.m, s.v, (int64_t)kNP, lr, beta1, beta2, eps, c1, c2, s.wb);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+const char *ko_nn_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+"""Python binding of libko_nn.so (include/ko_nn.h): the learned surrogate.
+
+Argument marshalling only: tokens, forward, backward and Adam run in the
+library's gfx950 kernels; features and the lower bound are host functions of
+the library.  PyTorch supplies device memory and the current stream.  Fails
+loudly when libko_nn.so has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import KoError, gpu_model, kernel_array, _stream_handle  # (does not load libko.so)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_NN_PATH = os.path.join(_HERE, "libko_nn.so")
+if not os.path.exists(LIB_NN_PATH):
+    raise ImportError(f"{LIB_NN_PATH} is missing: build it with `python paper_1511_07983_amd/build.py`")
+_lib = ctypes.CDLL(LIB_NN_PATH)
+
+N_FEAT = 8
+N_POS = 17
+UNPLACED = 16
+D_IN = 32
+D_HID = 256
+MAX_TOKENS = 16
+
+EXPORTED = ("ko_nn_num_params", "ko_nn_state_bytes", "ko_nn_work_bytes", "ko_nn_load", "ko_nn_read",
+            "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens", "ko_nn_forward",
+            "ko_nn_backward", "ko_nn_adam", "ko_nn_last_error")
+
+_vp = ctypes.c_void_p
+_lib.ko_nn_num_params.restype = ctypes.c_size_t
+_lib.ko_nn_state_bytes.restype = ctypes.c_size_t
+_lib.ko_nn_work_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+_lib.ko_nn_work_bytes.restype = ctypes.c_size_t
+_lib.ko_nn_load.argtypes = [_vp, _vp, _vp]
+_lib.ko_nn_read.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
+_lib.ko_nn_features.argtypes = [_vp, _vp, ctypes.c_int32, _vp]
+_lib.ko_nn_lower_bound.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+_lib.ko_nn_tokens.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
+_lib.ko_nn_forward.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
+_lib.ko_nn_backward.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
+_lib.ko_nn_adam.argtypes = [_vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                            ctypes.c_float, _vp]
+_lib.ko_nn_last_error.restype = ctypes.c_char_p
+for _f in ("ko_nn_load", "ko_nn_read", "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens",
+           "ko_nn_forward", "ko_nn_backward", "ko_nn_adam"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+def _check(rc):
+    if rc != 0:
+        raise KoError(rc, _lib.ko_nn_last_error().decode())
+
+
+def num_params() -> int:
+    return int(_lib.ko_nn_num_params())
+
+
+def features(gpu, kernels) -> np.ndarray:
+    """Per-kernel features [n, 8] (float32), computed by the library on the host."""
+    g = gpu_model(gpu)
+    k = kernel_array(kernels)
+    out = np.zeros((len(k), N_FEAT), dtype=np.float32)
+    _check(_lib.ko_nn_features(ctypes.addressof(g), k.ctypes.data, len(k), out.ctypes.data))
+    return out
+
+
+def lower_bound(gpu, kernels) -> int:
+    g = gpu_model(gpu)
+    k = kernel_array(kernels)
+    lb = ctypes.c_int64(0)
+    _check(_lib.ko_nn_lower_bound(ctypes.addressof(g), k.ctypes.data, len(k), ctypes.byref(lb)))
+    return int(lb.value)
+
+
+class Surrogate:
+    """Device state (weights, gradients, Adam moments) plus a workspace."""
+
+    def __init__(self, params=None, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.state = torch.zeros(int(_lib.ko_nn_state_bytes()), dtype=torch.uint8, device=self.device)
+        self._work = None
+        self._work_key = None
+        if params is not None:
+            self.load(params)
+
+    def _workspace(self, B, n):
+        need = int(_lib.ko_nn_work_bytes(B, n))
+        if self._work is None or self._work.numel() < need:
+            self._work = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+        return self._work
+
+    def load(self, params, stream=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != num_params():
+            raise ValueError(f"expected {num_params()} parameters, got {p.size}")
+        _check(_lib.ko_nn_load(self.state.data_ptr(), p.ctypes.data, _stream_handle(stream)))
+
+    def read(self, which: str = "weights", stream=None) -> np.ndarray:
+        out = np.zeros(num_params(), dtype=np.float32)
+        _check(_lib.ko_nn_read(self.state.data_ptr(), 0 if which == "weights" else 1, out.ctypes.data,
+                               _stream_handle(stream)))
+        return out
+
+    def tokens(self, feat, pos, set_of=None, stream=None):
+        """feat: device float32 [S, n, 8]; pos: device uint8 [B, n]; set_of: device int32 [B]."""
+        torch = self.torch
+        B, n = pos.shape
+        x = torch.empty((B, n, D_IN), dtype=torch.int16, device=self.device)
+        _check(_lib.ko_nn_tokens(feat.data_ptr(), set_of.data_ptr() if set_of is not None else None,
+                                 pos.data_ptr(), B, n, x.data_ptr(), _stream_handle(stream)))
+        return x
+
+    def forward(self, x, stream=None):
+        torch = self.torch
+        B, n, _ = x.shape
+        y = torch.empty(B, dtype=torch.float32, device=self.device)
+        _check(_lib.ko_nn_forward(self.state.data_ptr(), x.data_ptr(), B, n, y.data_ptr(),
+                                  self._workspace(B, n).data_ptr(), _stream_handle(stream)))
+        return y
+
+    def backward(self, x, t, stream=None):
+        torch = self.torch
+        B, n, _ = x.shape
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(_lib.ko_nn_backward(self.state.data_ptr(), x.data_ptr(), t.data_ptr(), B, n,
+                                   loss.data_ptr(), self._workspace(B, n).data_ptr(),
+                                   _stream_handle(stream)))
+        return loss
+
+    def adam(self, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(_lib.ko_nn_adam(self.state.data_ptr(), step, lr, beta1, beta2, eps,
+                               _stream_handle(stream)))

@@ -1,0 +1,146 @@
+"""GPU parity of the surrogate library (libko_nn.so) against the float64 oracle.
+
+Tolerances.  Both sides round the same values to BF16 at the same points; the
+device accumulates in float32 (MFMA), the oracle in float64.  A float32 sum of
+at most 256 products of magnitude <= 1 differs from float64 by < 256 * 2^-24 of
+its magnitude, so a rounded activation differs only where that error straddles
+a BF16 rounding boundary, by one BF16 ulp (2^-8 relative) of that element.  Its
+effect on y is bounded by 2^-8 * |a| * |w4| per flipped element; with weights of
+scale 0.08 and a handful of flips that stays far below 1e-3 (1 + |y|), the
+bound used for y.  Gradients pass through the same flips (dZ1..dZ3 are also
+rounded), so they are compared per tensor in relative L2 norm (<= 1e-2).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+nn = pytest.importorskip("paper_1511_07983_amd.nn")
+
+
+def say(*a):
+    print("[nn-gpu]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def make_case(seed, B, n, scale=0.08):
+    rng = np.random.default_rng(seed)
+    params = {name: rng.normal(0.0, scale, size=shape) for name, shape in mlp.SHAPES}
+    flat = mlp.flatten(params).astype(np.float32)
+    feat = rng.normal(0.0, 1.0, size=(1, n, mlp.N_FEAT)).astype(np.float32)
+    pos = np.stack([rng.permutation(n) for _ in range(B)]).astype(np.uint8)
+    if n < 16 and B > 2:
+        pos[1, : n // 2] = mlp.UNPLACED  # a partial order: some kernels unplaced
+    X = np.zeros((B, n, mlp.D_IN))
+    X[:, :, :mlp.N_FEAT] = feat[0][None].astype(np.float64)
+    for b in range(B):
+        X[b, np.arange(n), mlp.N_FEAT + pos[b]] = 1.0
+    return rng, flat, feat, pos, X
+
+
+def device_tokens(model, feat, pos):
+    f = torch.from_numpy(feat).to("cuda:0")
+    p = torch.from_numpy(pos).to("cuda:0")
+    return model.tokens(f, p)
+
+
+def bf16_values(x_int16):
+    u = x_int16.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("B,n", [(1, 1), (37, 5), (64, 16), (300, 12), (129, 9)])
+def test_tokens_and_forward(B, n):
+    rng, flat, feat, pos, X = make_case(10 + B + n, B, n)
+    say(f"forward B={B} n={n}")
+    model = nn.Surrogate(flat)
+    x = device_tokens(model, feat, pos)
+    assert np.array_equal(bf16_values(x), mlp.bf16(X))
+    y = model.forward(x).cpu().numpy().astype(np.float64)
+    p64 = mlp.unflatten(flat.astype(np.float64))
+    yo, _ = mlp.forward(p64, X)
+    err = np.abs(y - yo)
+    assert err.max() <= 1e-3 * (1.0 + np.abs(yo).max()), (err.max(), np.abs(yo).max())
+
+
+@pytest.mark.parametrize("B,n", [(37, 5), (256, 12), (70, 16)])
+def test_gradients(B, n):
+    rng, flat, feat, pos, X = make_case(20 + B + n, B, n)
+    say(f"backward B={B} n={n}")
+    model = nn.Surrogate(flat)
+    x = device_tokens(model, feat, pos)
+    p64 = mlp.unflatten(flat.astype(np.float64))
+    yo, _ = mlp.forward(p64, X)
+    t = (yo + rng.normal(0.0, 0.5, size=B)).astype(np.float32)
+    loss = model.backward(x, torch.from_numpy(t).to("cuda:0"))
+    lo, _, go = mlp.loss_and_grads(p64, X, t.astype(np.float64))
+    assert float(loss.cpu()[0]) == pytest.approx(lo, rel=1e-3)
+    g = mlp.unflatten(model.read("grads").astype(np.float64))
+    for name, _ in mlp.SHAPES:
+        a, b = g[name].ravel(), go[name].ravel()
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert rel <= 1e-2, (name, rel)
+
+
+def test_adam_step():
+    """One Adam step from the loaded weights: well-conditioned components (not
+    near a zero gradient, where the first step is lr * sign(g)) match the oracle;
+    every component moves by at most lr."""
+    B, n, lr = 96, 8, 1e-3
+    rng, flat, feat, pos, X = make_case(31, B, n)
+    model = nn.Surrogate(flat)
+    x = device_tokens(model, feat, pos)
+    p64 = mlp.unflatten(flat.astype(np.float64))
+    yo, _ = mlp.forward(p64, X)
+    t = (yo + rng.normal(0.0, 0.5, size=B)).astype(np.float32)
+    model.backward(x, torch.from_numpy(t).to("cuda:0"))
+    model.adam(1, lr)
+    w_dev = model.read("weights").astype(np.float64)
+    _, _, go = mlp.loss_and_grads(p64, X, t.astype(np.float64))
+    g = mlp.flatten(go)
+    w0 = flat.astype(np.float64)
+    w_or, _, _ = mlp.adam_step(w0, g, np.zeros_like(g), np.zeros_like(g), 1, lr)
+    assert np.abs(w_dev - w0).max() <= lr * (1 + 1e-5)
+    good = np.abs(g) > 1e-2 * np.abs(g).max()
+    assert good.sum() > 1000
+    assert np.allclose(w_dev[good], w_or[good], rtol=0, atol=1e-6)
+
+
+def test_training_reduces_loss():
+    """Fit targets produced by a random teacher network: 300 Adam steps cut the
+    loss by at least 10x."""
+    B, n = 512, 10
+    rng = np.random.default_rng(41)
+    teacher = {name: rng.normal(0.0, 0.1, size=shape) for name, shape in mlp.SHAPES}
+    _, flat, feat, _, _ = make_case(42, 2, n)
+    pos = np.stack([rng.permutation(n) for _ in range(B)]).astype(np.uint8)
+    X = np.zeros((B, n, mlp.D_IN))
+    X[:, :, :mlp.N_FEAT] = feat[0][None].astype(np.float64)
+    for b in range(B):
+        X[b, np.arange(n), mlp.N_FEAT + pos[b]] = 1.0
+    t, _ = mlp.forward(teacher, X, bf16_points=False)
+    t = ((t - t.mean()) / (t.std() + 1e-12)).astype(np.float32)
+    model = nn.Surrogate(flat)
+    x = device_tokens(model, feat, pos)
+    td = torch.from_numpy(t).to("cuda:0")
+    first = float(model.backward(x, td).cpu()[0])
+    model.adam(1, 3e-3)
+    for step in range(2, 301):
+        loss = model.backward(x, td)
+        model.adam(step, 3e-3)
+    last = float(loss.cpu()[0])
+    say(f"training loss {first:.4f} -> {last:.4f}")
+    assert last < first / 10
