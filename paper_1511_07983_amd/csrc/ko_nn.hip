@@ -202,7 +202,9 @@ __device__ inline float block_sum(float v, float *red)
 __global__ __launch_bounds__(256) void out_forward_kernel(const uint16_t *A3b, const uint16_t *wb,
                                                           const float *master, int32_t B, float *y)
 {
-    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the wave index is uniform across the wave: the early return stays a
+    // scalar branch and the shuffles of wave_sum run with all lanes active
+    const int64_t b = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (b >= B)
         return;

@@ -67,6 +67,15 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Sets status bits from a wave without a lane-dependent branch: every lane
+// issues the atomic, only lane 0 with a nonzero operand.  Code between wave
+// collectives (ballot, readlane, shuffles) stays free of lane-0-only branches,
+// whose reconvergence point the compiler does not guarantee.
+__device__ __forceinline__ void flag_status(uint32_t *status, uint32_t bits)
+{
+    atomicOr(status, lane_id() == 0 ? bits : 0u);
+}
+
 __device__ __forceinline__ uint32_t wave_min(uint32_t v)
 {
     for (int o = 32; o >= 1; o >>= 1)
@@ -259,8 +268,7 @@ __device__ int64_t simulate_order(const SimArgs &a, const KernelRec *__restrict_
             }
             const uint64_t free_slots = ballot(lane < gslots && rel == 0xFFFFFFFFu);
             if (free_slots == 0) {
-                if (lane == 0)
-                    atomicOr(a.status, kStatusGroupOverflow);
+                flag_status(a.status, kStatusGroupOverflow);
                 return -1;
             }
             const uint32_t g = (uint32_t)__builtin_ctzll(free_slots);
@@ -285,8 +293,7 @@ __device__ int64_t simulate_order(const SimArgs &a, const KernelRec *__restrict_
         // ---- next event: the earliest group end ----
         const uint32_t dt = uniform(wave_min(rel));
         if (dt == 0xFFFFFFFFu) {  // nothing running yet the front block does not fit
-            if (lane == 0)
-                atomicOr(a.status, kStatusGroupOverflow);
+            flag_status(a.status, kStatusGroupOverflow);
             return -1;
         }
         t += dt;
@@ -323,10 +330,12 @@ __global__ __launch_bounds__(256) void simulate_kernel(SimArgs a, uint32_t gslot
     uint32_t *ring = lds_ring + wid * gslots * kWave;
 
     for (;;) {
-        uint64_t item = 0;
-        if (lane == 0)
-            item = atomicAdd(a.item_counter, 1ull);
-        item = uniform64(item);
+        // All lanes execute the fetch (lane 0 adds one, the rest zero) and
+        // lane 0's old value is broadcast.  No lane-dependent branch may sit
+        // at the top of this loop: the lane-0 branch that stores the Partial
+        // at the bottom can then be threaded around it, and lanes 1..63 would
+        // re-enter the loop without lane 0 (and without a fetched item).
+        const uint64_t item = uniform64(atomicAdd(a.item_counter, lane == 0 ? 1ull : 0ull));
         if (item >= a.n_items)
             break;
         // the set owning this item: the last set whose first item <= item
@@ -368,8 +377,7 @@ __global__ __launch_bounds__(256) void simulate_kernel(SimArgs a, uint32_t gslot
                     seen |= 1u << (read_lane(perm, j) & 31u);
                 const uint32_t want = (n >= 32) ? 0xFFFFFFFFu : ((1u << n) - 1u);
                 if (seen_any || seen != want) {
-                    if (lane == 0)
-                        atomicOr(a.status, kStatusBadOrder);
+                    flag_status(a.status, kStatusBadOrder);
                     perm = unrank_lanes(0, n);
                 }
             } else if (a.mode == kModeSampled) {
@@ -422,7 +430,9 @@ __global__ __launch_bounds__(256) void simulate_kernel(SimArgs a, uint32_t gslot
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
 {
     const uint32_t lane = lane_id();
-    const int set = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    // the wave index is uniform across the wave; saying so keeps the early
+    // return a scalar branch, so the shuffles below run with all lanes active
+    const int set = (int)(blockIdx.x * 4 + uniform(threadIdx.x >> 6));
     if (set >= a.n_sets)
         return;
     const SetRec st = a.sets[set];

@@ -1,0 +1,273 @@
+"""Static check of gfx950 kernel assembly: cross-lane reads under full exec.
+
+The wave-per-order kernels exchange values between lanes (readlane,
+readfirstlane, DPP, ds_bpermute/swizzle) on the assumption that all 64 lanes
+are active there.  The compiler keeps that assumption only where control flow
+reconverges the way the source suggests; where it does not (a lane-dependent
+branch threaded around another one, for example), the wave reaches a
+collective with some lanes masked off and reads stale registers of the masked
+lanes.  This module parses the assembly text that hipcc emits, builds each
+kernel's control-flow graph and runs a small dataflow analysis of the EXEC
+mask:
+
+  * exec is FULL at kernel entry (workgroups are whole waves);
+  * s_and_saveexec / s_andn2_saveexec / writes of exec make it PARTIAL;
+  * an SGPR pair that saved exec (or holds the complementary lanes of an
+    if/else, or accumulates the lanes leaving a divergent loop) remembers the
+    exec state that OR-ing it back restores;
+  * at control-flow joins PARTIAL wins and disagreeing saved masks are lost.
+
+A cross-lane instruction reached with exec possibly PARTIAL is reported.
+Readlane of the VGPRs that hold SGPR spills is exempt (spill code is
+independent of exec), as are writelanes.
+"""
+
+from __future__ import annotations
+
+import re
+from dataclasses import dataclass, field
+
+FULL, PARTIAL = "full", "partial"
+
+_LABEL = re.compile(r"^(\.LBB\d+_\d+):")
+_FUNC = re.compile(r"^([A-Za-z_$][\w.$]*):")
+_SPILL = re.compile(r"\$vgpr(\d+) : SGPR spill to VGPR lane")
+_DPP = ("quad_perm:", "row_shl:", "row_shr:", "row_ror:", "wave_shl", "wave_rol", "wave_shr",
+        "wave_ror", "row_mirror", "row_half_mirror", "row_bcast", "row_newbcast")
+_XLANE = ("v_readlane_b32", "v_readfirstlane_b32", "ds_bpermute_b32", "ds_permute_b32",
+          "ds_swizzle_b32", "v_permlane16_swap_b32", "v_permlane32_swap_b32")
+_NO_SDST = ("s_cmp", "s_bitcmp", "s_cbranch", "s_branch", "s_waitcnt", "s_nop", "s_setprio",
+            "s_barrier", "s_sendmsg", "s_endpgm", "s_dcache", "s_sleep", "s_trap", "s_icache",
+            "s_setpc", "s_set_gpr_idx")
+
+
+def _sregs(op: str):
+    """SGPR numbers named by one operand (sN or s[a:b]); vcc is 106/107."""
+    m = re.fullmatch(r"s\[(\d+):(\d+)\]", op)
+    if m:
+        return list(range(int(m.group(1)), int(m.group(2)) + 1))
+    m = re.fullmatch(r"s(\d+)", op)
+    if m:
+        return [int(m.group(1))]
+    if op in ("vcc", "vcc_lo", "vcc_hi"):
+        return [106, 107] if op == "vcc" else [106 if op == "vcc_lo" else 107]
+    return []
+
+
+def _pair(op: str):
+    r = _sregs(op)
+    return r[0] if len(r) == 2 else None
+
+
+@dataclass
+class Inst:
+    line: int
+    text: str
+    mnem: str
+    ops: list
+
+
+@dataclass
+class Block:
+    name: str
+    insts: list = field(default_factory=list)
+    succ: list = field(default_factory=list)
+
+
+@dataclass
+class Function:
+    name: str
+    blocks: list
+    spill_vgprs: set
+
+
+def parse(asm: str):
+    """Split assembly text into functions made of basic blocks."""
+    funcs = []
+    cur = None
+    spill = set()
+    blocks = []
+    blk = None
+    lines = asm.splitlines()
+
+    def new_block(name):
+        nonlocal blk
+        blk = Block(name)
+        blocks.append(blk)
+
+    for no, raw in enumerate(lines, 1):
+        line = raw.split(";")[0].rstrip() if not raw.lstrip().startswith(";") else ""
+        sm = _SPILL.search(raw)
+        if sm and cur is not None:
+            spill.add(int(sm.group(1)))
+        if not line.strip():
+            continue
+        if cur is None:
+            fm = _FUNC.match(line)
+            if fm and not line.startswith(".") and not line.startswith("__hip"):
+                cur = fm.group(1)
+                blocks, spill = [], set()
+                new_block(cur)
+            continue
+        if line.startswith(".Lfunc_end"):
+            funcs.append(Function(cur, blocks, spill))
+            cur = None
+            continue
+        lm = _LABEL.match(line)
+        if lm:
+            if blk.insts or blk.name != cur:
+                new_block(lm.group(1))
+            else:
+                new_block(lm.group(1))
+            continue
+        s = line.strip()
+        if s.startswith("."):
+            continue
+        parts = s.split(None, 1)
+        mnem = parts[0]
+        ops = [o.strip() for o in parts[1].split(",")] if len(parts) > 1 else []
+        blk.insts.append(Inst(no, s, mnem, ops))
+        if mnem in ("s_endpgm", "s_branch") or mnem.startswith("s_cbranch") or mnem == "s_setpc_b64":
+            new_block(f"{blk.name}+{no}")
+    # successors
+    for f in funcs:
+        names = {b.name: i for i, b in enumerate(f.blocks)}
+        for i, b in enumerate(f.blocks):
+            last = b.insts[-1] if b.insts else None
+            nxt = [f.blocks[i + 1].name] if i + 1 < len(f.blocks) else []
+            if last is None:
+                b.succ = nxt
+            elif last.mnem == "s_endpgm" or last.mnem == "s_setpc_b64":
+                b.succ = []
+            elif last.mnem == "s_branch":
+                b.succ = [last.ops[0]]
+            elif last.mnem.startswith("s_cbranch"):
+                b.succ = [last.ops[0]] + nxt
+            else:
+                b.succ = nxt
+            for s in b.succ:
+                if s not in names:
+                    raise ValueError(f"{f.name}: branch to unknown label {s}")
+    return funcs
+
+
+def _transfer(inst: Inst, exec_state: str, tok: dict):
+    """Apply one instruction to (exec, saved-mask tokens); returns new exec."""
+    m, ops = inst.mnem, inst.ops
+    if m.endswith("saveexec_b64") and ops:
+        d = _pair(ops[0])
+        src = _pair(ops[1]) if len(ops) > 1 else None
+        if m == "s_and_saveexec_b64":
+            new_tok = exec_state
+        elif m == "s_andn2_saveexec_b64":
+            # exec = S & ~exec, D = old exec: D and the new exec partition what S restored
+            new_tok = tok.get(src, PARTIAL)
+        else:
+            new_tok = PARTIAL
+        for r in (d, d + 1) if d is not None else ():
+            tok.pop(r, None)
+        if d is not None:
+            tok[d] = new_tok
+        return PARTIAL
+    if ops and ops[0] == "exec":
+        if m == "s_or_b64" and len(ops) == 3 and "exec" in ops[1:]:
+            other = ops[2] if ops[1] == "exec" else ops[1]
+            p = _pair(other)
+            return FULL if (p is not None and tok.get(p) == FULL) else (
+                exec_state if exec_state == FULL else PARTIAL)
+        if m == "s_mov_b64" and len(ops) == 2 and _pair(ops[1]) is not None:
+            return PARTIAL if tok.get(("copy", _pair(ops[1]))) != FULL else FULL
+        return PARTIAL
+    # writes to SGPRs: keep or drop tokens
+    if m.startswith("s_") and ops and not m.startswith(_NO_SDST):
+        d = _pair(ops[0])
+        regs = _sregs(ops[0])
+        keep = None
+        if m == "s_mov_b64" and d is not None and len(ops) == 2:
+            if ops[1] == "exec":
+                keep = ("copy", exec_state)
+            elif ops[1] in ("0", "0x0"):
+                keep = ("tok", exec_state)
+            elif _pair(ops[1]) is not None and _pair(ops[1]) in tok:
+                keep = ("tok", tok[_pair(ops[1])])
+        elif m == "s_or_b64" and d is not None and len(ops) == 3 and ops[0] in ops[1:] and d in tok:
+            keep = ("tok", tok[d])
+        elif m == "s_xor_b64" and d is not None and len(ops) == 3 and "exec" in ops[1:]:
+            other = ops[2] if ops[1] == "exec" else ops[1]
+            if _pair(other) in tok:
+                keep = ("tok", tok[_pair(other)])
+        for r in regs:
+            for k in [k for k in tok if k == r or k == r - 1 or (isinstance(k, tuple) and k[1] in (r, r - 1))]:
+                tok.pop(k, None)
+        if keep is not None:
+            tok[d] = keep[1]
+            if keep[0] == "copy":
+                tok[("copy", d)] = keep[1]
+        return exec_state
+    if m.startswith("v_") or m.startswith("s_load") or m.startswith("s_buffer_load"):
+        for op in ops:
+            regs = _sregs(op)
+            if regs and (op is ops[0] or "_co_" in m or m.startswith("v_cmp") or m.startswith("v_div_scale")):
+                for r in regs:
+                    for k in [k for k in tok if k == r or k == r - 1 or (isinstance(k, tuple) and k[1] in (r, r - 1))]:
+                        tok.pop(k, None)
+    return exec_state
+
+
+def _is_xlane(inst: Inst, spill: set) -> bool:
+    if inst.mnem in _XLANE:
+        if inst.mnem == "v_readlane_b32" and len(inst.ops) > 1:
+            m = re.fullmatch(r"v(\d+)", inst.ops[1])
+            if m and int(m.group(1)) in spill:
+                return False
+        return True
+    return any(d in inst.text for d in _DPP)
+
+
+def _merge(a, b):
+    if a is None:
+        return b
+    ea, ta = a
+    eb, tb = b
+    e = FULL if (ea == FULL and eb == FULL) else PARTIAL
+    t = {k: v for k, v in ta.items() if k in tb and tb[k] == v}
+    return e, t
+
+
+def analyse(func: Function):
+    """Returns (cross-lane instructions under possibly partial exec, divergent loop exits)."""
+    idx = {b.name: i for i, b in enumerate(func.blocks)}
+    state_in = [None] * len(func.blocks)
+    state_in[0] = (FULL, {})
+    work = [0]
+    while work:
+        i = work.pop()
+        e, t = state_in[i]
+        t = dict(t)
+        for inst in func.blocks[i].insts:
+            e = _transfer(inst, e, t)
+        for s in func.blocks[i].succ:
+            j = idx[s]
+            new = _merge(state_in[j], (e, t))
+            if new != state_in[j]:
+                state_in[j] = new
+                work.append(j)
+    bad = []
+    div_loops = 0
+    for i, b in enumerate(func.blocks):
+        if state_in[i] is None:
+            continue
+        e, t = state_in[i]
+        t = dict(t)
+        for inst in b.insts:
+            if inst.mnem == "s_andn2_b64" and inst.ops[:2] == ["exec", "exec"]:
+                div_loops += 1
+            if e != FULL and _is_xlane(inst, func.spill_vgprs):
+                bad.append((inst.line, inst.text))
+            e = _transfer(inst, e, t)
+    return bad, div_loops
+
+
+def check(asm: str):
+    """{function name: (bad cross-lane instructions, divergent loop exits)}."""
+    return {f.name: analyse(f) for f in parse(asm)}

@@ -17,12 +17,7 @@ from oracle import stats as ostats
 from oracle.heuristic import heuristic_order as oracle_heuristic
 from oracle.sampling import sampled_rank
 
-FAULT_REASON = (
-    "the first GPU run of this evaluation path left the GPU faulted (illegal address) and its "
-    "cause has not been shown yet: CPU emulation of the same library sources under ASan/UBSan "
-    "matches the oracle on the failing inputs; the path stays off the GPU until a cause is found")
-
-pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason=FAULT_REASON)]
+pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 ko = pytest.importorskip("paper_1511_07983_amd")
