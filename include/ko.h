@@ -213,6 +213,19 @@ int ko_sync(void *hip_stream);
 /* ko_shutdown — release the per-device workspaces.  Later calls recreate them. */
 int ko_shutdown(void);
 
+/* ko_set_kernel_timing — measurement aid, not part of the method: while enabled
+ * (enable != 0), ko_simulate_batch on the current device records two timing
+ * events on its stream, immediately before and after the simulate kernel (the
+ * makespan evaluation itself: no staging, reduction or histogram).  Enabling
+ * or disabling forgets any earlier measurement. */
+int ko_set_kernel_timing(int32_t enable);
+
+/* ko_last_kernel_ms — duration in milliseconds of the simulate kernel of the
+ * last timed ko_simulate_batch on the current device.  Blocks until that
+ * kernel has finished.  KO_EINVAL if ms_out is NULL or no timed launch
+ * happened since timing was enabled. */
+int ko_last_kernel_ms(float *ms_out);
+
 /* ko_last_error — text of the last failure on this thread; owned by the library,
  * valid until the next call on this thread.  Never NULL. */
 const char *ko_last_error(void);

@@ -39,7 +39,7 @@ KO_HEUR_PER_BLOCK = 1
 KO_HEUR_FULL_SORT = 2
 
 EXPORTED = ("ko_heuristic_order", "ko_count_orders", "ko_simulate_batch", "ko_rank_percentile",
-            "ko_sync", "ko_shutdown", "ko_last_error")
+            "ko_sync", "ko_shutdown", "ko_set_kernel_timing", "ko_last_kernel_ms", "ko_last_error")
 
 
 class KoGpuModel(ctypes.Structure):
@@ -116,6 +116,10 @@ def _L():
         lib.ko_sync.restype = ctypes.c_int
         lib.ko_shutdown.argtypes = []
         lib.ko_shutdown.restype = ctypes.c_int
+        lib.ko_set_kernel_timing.argtypes = [ctypes.c_int32]
+        lib.ko_set_kernel_timing.restype = ctypes.c_int
+        lib.ko_last_kernel_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
+        lib.ko_last_kernel_ms.restype = ctypes.c_int
         lib.ko_last_error.argtypes = []
         lib.ko_last_error.restype = ctypes.c_char_p
         _lib = lib
@@ -309,6 +313,18 @@ def ko_sync(stream=None):
 
 def ko_shutdown():
     _check(_L().ko_shutdown())
+
+
+def ko_set_kernel_timing(enable: bool):
+    """Time the simulate kernel of later ko_simulate_batch calls (current device)."""
+    _check(_L().ko_set_kernel_timing(1 if enable else 0))
+
+
+def ko_last_kernel_ms() -> float:
+    """Duration (ms) of the simulate kernel of the last timed call; waits for it."""
+    ms = ctypes.c_float(0.0)
+    _check(_L().ko_last_kernel_ms(ctypes.byref(ms)))
+    return float(ms.value)
 
 
 def library_handle():

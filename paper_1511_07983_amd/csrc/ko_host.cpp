@@ -382,6 +382,10 @@ struct Workspace {
     hipEvent_t done = nullptr;    // after the last call's work
     bool pending_status = false;
     bool clear_status = false;  // a reported device status must be cleared before the next launch
+    // optional timing of the simulate kernel (ko_set_kernel_timing)
+    hipEvent_t sim_begin = nullptr, sim_end = nullptr;
+    bool timing = false;
+    bool timed = false;  // sim_begin/sim_end bracket a launch made while timing was on
 };
 
 std::mutex g_mutex;
@@ -437,6 +441,8 @@ int get_workspace(Workspace **out)
         *w.status_host = 0;
         KO_HIP(hipEventCreateWithFlags(&w.staged, hipEventDisableTiming), "hipEventCreate");
         KO_HIP(hipEventCreateWithFlags(&w.done, hipEventDisableTiming), "hipEventCreate");
+        KO_HIP(hipEventCreate(&w.sim_begin), "hipEventCreate");
+        KO_HIP(hipEventCreate(&w.sim_end), "hipEventCreate");
         KO_HIP(hipEventRecord(w.staged, 0), "hipEventRecord");
         KO_HIP(hipEventRecord(w.done, 0), "hipEventRecord");
         w.ready = true;
@@ -467,6 +473,8 @@ void release_workspace(Workspace &w)
     (void)hipHostFree(w.ref_host);
     (void)hipEventDestroy(w.staged);
     (void)hipEventDestroy(w.done);
+    (void)hipEventDestroy(w.sim_begin);
+    (void)hipEventDestroy(w.sim_end);
     (void)hipSetDevice(prev);
     w = Workspace();
 }
@@ -668,9 +676,15 @@ int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernel
         a.cap_wave = (uint32_t)gpu->wave_cu;
         a.cap_blk = (uint32_t)gpu->blk_cu;
         const int g = (int)std::min<uint64_t>((uint64_t)grid, (plan.n_items + 3) / 4);
+        if (w.timing)
+            KO_HIP(hipEventRecord(w.sim_begin, stream), "hipEventRecord");
         e = ko::launch_simulate(a, slots, plan.max_n, g, stream);
         if (e)
             return hip_fail((hipError_t)e, "simulate kernel launch");
+        if (w.timing) {
+            KO_HIP(hipEventRecord(w.sim_end, stream), "hipEventRecord");
+            w.timed = true;
+        }
     }
     if (stats_dev) {
         ko::ReduceArgs r;
@@ -872,6 +886,34 @@ int ko_shutdown(void)
     for (Workspace &w : g_ws)
         release_workspace(w);
     g_ws.clear();
+    return KO_OK;
+}
+
+int ko_set_kernel_timing(int32_t enable)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace *w = nullptr;
+    int rc = get_workspace(&w);
+    if (rc)
+        return rc;
+    w->timing = enable != 0;
+    w->timed = false;
+    return KO_OK;
+}
+
+int ko_last_kernel_ms(float *ms_out)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (!ms_out)
+        return fail(KO_EINVAL, "ms_out must not be NULL");
+    Workspace *w = nullptr;
+    int rc = get_workspace(&w);
+    if (rc)
+        return rc;
+    if (!w->timed)
+        return fail(KO_EINVAL, "no simulate kernel was launched on this device since timing was enabled");
+    KO_HIP(hipEventSynchronize(w->sim_end), "hipEventSynchronize");
+    KO_HIP(hipEventElapsedTime(ms_out, w->sim_begin, w->sim_end), "hipEventElapsedTime");
     return KO_OK;
 }
 

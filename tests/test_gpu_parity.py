@@ -169,7 +169,7 @@ def test_batch_workload_many_sets():
     want = [oracle.makespans_all(gpu, k) for k in sets]
     refs = [int(m[len(m) // 3]) for m in want]
     ms, st, hist, per = run_batch(w.model, sets, ko.OrderSpec.all(), ref=refs, n_bins=32)
-    off = np.concatenate([[0], np.cumsum(per)])
+    off = np.concatenate([[0], np.cumsum(np.asarray(per, dtype=np.int64))])
     for i, m in enumerate(want):
         assert np.array_equal(ms[off[i]:off[i + 1]], m), small[i][0]
         expect_stats(st[i], m, ref=refs[i])
@@ -181,7 +181,7 @@ def test_batch_workload_many_sets():
         N = math.factorial(len(k))
         lohi.append([N // 3, N // 3 + 700])
     ms, st, _, per = run_batch(w.model, sets, ko.OrderSpec.rank_range(lohi))
-    off = np.concatenate([[0], np.cumsum(per)])
+    off = np.concatenate([[0], np.cumsum(np.asarray(per, dtype=np.int64))])
     for i, k in enumerate(sets):
         m = oracle.makespans_range(gpu, k, lohi[i][0], 700)
         assert np.array_equal(ms[off[i]:off[i + 1]], m)
@@ -303,7 +303,8 @@ def test_full_size_n10_all_orders_properties():
     assert int(hist[0].sum()) == N
     assert np.array_equal(hist[0], ostats.histogram(ms, 1024, ms.min(), ms.max()))
     rng = np.random.default_rng(8)
-    idx = np.unique(np.concatenate([rng.integers(0, N, 400), [0, N - 1, rec["argmin"], rec["argmax"]]]))
+    idx = np.unique(np.concatenate([rng.integers(0, N, 400),
+                                    np.array([0, N - 1, int(rec["argmin"]), int(rec["argmax"])], dtype=np.int64)]))
     want = oracle.makespans_ranks(gpu, ks, idx.astype(np.uint64))
     assert np.array_equal(ms[idx], want)
     r = ko.ko_rank_percentile(w.model, ks, h_order)
