@@ -213,6 +213,47 @@ int ko_sync(void *hip_stream);
 /* ko_shutdown — release the per-device workspaces.  Later calls recreate them. */
 int ko_shutdown(void);
 
+/* ko_sample_orders — the launch orders that ko_simulate_batch evaluates in
+ * KO_ORDERS_SAMPLED mode for the set at batch index set_index (seed as in
+ * ko_order_spec.seed): sample i is the order of rank
+ * floor(splitmix64(seed, counter = set_index * 2^40 + i) * n! / 2^64).
+ *   n             kernels in the set, 1..20
+ *   set_index     0 .. 2^24-1
+ *   first, count  samples first .. first+count-1 (first + count <= 2^40) when
+ *                 indices_dev is NULL; otherwise samples indices_dev[0..count)
+ *                 (uint64, device, each < 2^40)
+ *   orders_dev    uint8 [count][n], device, nullable: order[j] = kernel at position j
+ *   positions_dev uint8 [count][n], device, nullable: pos[i] = position of kernel i
+ * At least one output.  Asynchronous on hip_stream.  Used to build the inputs
+ * of a learned scorer for exactly the orders the simulator evaluates.
+ * Errors: KO_EINVAL (n, set_index, both outputs NULL), KO_ERANGE (indices). */
+int ko_sample_orders(int32_t n, int32_t set_index, uint64_t seed, uint64_t first,
+                     const uint64_t *indices_dev, uint64_t count, uint8_t *orders_dev,
+                     uint8_t *positions_dev, void *hip_stream);
+
+/* ko_topk_f32 — the k smallest values of y[count] (float32, device) with their
+ * indices, ascending by (value, index): idx_out[k] (int64, device, nullable)
+ * and val_out[k] (float32, device, nullable; at least one of the two).
+ * Values are ordered as IEEE numbers (-0 before +0; a NaN orders by its bit
+ * pattern, above +inf when its sign is clear).  1 <= count < 2^32,
+ * 1 <= k <= min(count, 16384).  Radix selection on the device; the call
+ * returns once the k-th smallest value is known and the sorted outputs are
+ * enqueued on hip_stream.
+ * Errors: KO_EINVAL (arguments), KO_ERANGE (more than 32768 values at or
+ * below the k-th smallest, i.e. massive ties), KO_EHIP. */
+int ko_topk_f32(const float *y_dev, uint64_t count, int32_t k, int64_t *idx_out_dev, float *val_out_dev,
+                void *hip_stream);
+
+/* ko_kth_smallest_i64 — the k-th smallest (1-based) of v[count] (int64,
+ * device) into *value_out (host) and, if count_le_out is not NULL, the number
+ * of elements <= that value (ties included) into *count_le_out (host).  For
+ * the makespans of a full enumeration with k = ceil(count / 100) this is the
+ * makespan that marks the best 1% of orders and how many orders reach it
+ * (Table 3's percentile ranks, read backwards).  Synchronous.
+ * Errors: KO_EINVAL (NULL v_dev or value_out, k outside 1..count), KO_EHIP. */
+int ko_kth_smallest_i64(const int64_t *v_dev, uint64_t count, uint64_t k, int64_t *value_out,
+                        uint64_t *count_le_out, void *hip_stream);
+
 /* ko_set_kernel_timing — measurement aid, not part of the method: while enabled
  * (enable != 0), ko_simulate_batch on the current device records two timing
  * events on its stream, immediately before and after the simulate kernel (the

@@ -70,11 +70,23 @@ int ko_nn_features(const ko_gpu_model *gpu, const ko_kernel *k, int32_t n, float
  * max(max_i d_i, max over resources x of ceil(sum_i N_tblk_i d_i u_x,i / (N_CU cap_x))). */
 int ko_nn_lower_bound(const ko_gpu_model *gpu, const ko_kernel *k, int32_t n, int64_t *lb_out);
 
-/* ko_nn_tokens — build BF16 tokens x[B][n][32] from features feat[S][n][8]
- * (float32, device), the set of each sample set_of[B] (int32, device; NULL = set 0)
- * and the launch position of each kernel pos[B][n] (uint8, device; 0..15 or 16). */
+/* ko_nn_tokens — build BF16 tokens x[B][n][32] for B samples.  Sample b reads
+ * row r = rows[b] (int64, device; NULL = b) of the sample tables: the set
+ * set_of[r] (int32, device; NULL = set 0) and the launch position of each of
+ * its kernels pos[r][n] (uint8, device; 0..15, 16 = unplaced); features come
+ * from feat[set][n][8] (float32, device).  The row map lets a training loop
+ * draw shuffled minibatches from set-major sample tables without copying them. */
 int ko_nn_tokens(const float *feat_dev, const int32_t *set_of_dev, const uint8_t *pos_dev,
-                 int32_t B, int32_t n, uint16_t *x_dev, void *hip_stream);
+                 const int64_t *rows_dev, int32_t B, int32_t n, uint16_t *x_dev, void *hip_stream);
+
+/* ko_nn_targets — training targets t[b] = (makespan[r] - center[s]) / scale[s]
+ * (float32, device) with r = rows[b] (NULL = b) and s = set_of[r] (NULL = 0):
+ * exact int64 makespans (device) shifted and scaled per set by center[s] and
+ * scale[s] (int64, device; scale > 0), e.g. the set's best sampled makespan
+ * and its area lower bound (ko_nn_lower_bound). */
+int ko_nn_targets(const int64_t *makespans_dev, const int32_t *set_of_dev, const int64_t *center_dev,
+                  const int64_t *scale_dev, const int64_t *rows_dev, int32_t B, float *t_dev,
+                  void *hip_stream);
 
 /* ko_nn_forward — y[B] (float32, device) for tokens x[B][n][32].  1 <= n <= 16. */
 int ko_nn_forward(const void *state_dev, const uint16_t *x_dev, int32_t B, int32_t n, float *y_dev,
@@ -88,6 +100,27 @@ int ko_nn_backward(void *state_dev, const uint16_t *x_dev, const float *t_dev, i
 /* ko_nn_adam — one Adam step (bias-corrected, step >= 1) on the stored gradients. */
 int ko_nn_adam(void *state_dev, int32_t step, float lr, float beta1, float beta2, float eps,
                void *hip_stream);
+
+/* ko_nn_layer1_table — the first layer of one set, tabulated for scoring:
+ * table[i][p][256] (float32, device, n*17*256 floats) = relu of the first
+ * layer's output for kernel i (features feat[n][8], float32, device) at
+ * launch position p (0..15, 16 = unplaced).  Because a token is its kernel's
+ * features plus a one-hot position, this equals the token path's per-token
+ * activation (up to float32 summation order). */
+int ko_nn_layer1_table(const void *state_dev, const float *feat_dev, int32_t n, float *table_dev,
+                       void *hip_stream);
+
+/* Bytes of device workspace for ko_nn_forward_positions on B samples. */
+size_t ko_nn_score_work_bytes(int32_t B);
+
+/* ko_nn_forward_positions — y[B] (float32, device) for B orders of one set
+ * given as positions pos[B][n] (uint8, device: position of kernel i, 0..15,
+ * 16 = unplaced; larger values count as 16), using that set's layer-1 table.
+ * The same network as ko_nn_forward without materialising tokens: S is a
+ * gather-sum of n table rows, then the two 256x256 BF16 MFMA layers and the
+ * output layer.  1 <= n <= 16. */
+int ko_nn_forward_positions(const void *state_dev, const float *table_dev, const uint8_t *pos_dev,
+                            int32_t B, int32_t n, float *y_dev, void *work_dev, void *hip_stream);
 
 const char *ko_nn_last_error(void);
 

@@ -39,7 +39,8 @@ KO_HEUR_PER_BLOCK = 1
 KO_HEUR_FULL_SORT = 2
 
 EXPORTED = ("ko_heuristic_order", "ko_count_orders", "ko_simulate_batch", "ko_rank_percentile",
-            "ko_sync", "ko_shutdown", "ko_set_kernel_timing", "ko_last_kernel_ms", "ko_last_error")
+            "ko_sync", "ko_shutdown", "ko_sample_orders", "ko_topk_f32", "ko_kth_smallest_i64",
+            "ko_set_kernel_timing", "ko_last_kernel_ms", "ko_last_error")
 
 
 class KoGpuModel(ctypes.Structure):
@@ -97,6 +98,9 @@ def _L():
     """libko.so, loaded on first use (the package can be imported without loading it)."""
     global _lib
     if _lib is None:
+        # PyTorch's HIP runtime must be loaded first so that libko.so binds to
+        # the libamdhip64 instance that owns the caller's memory and streams
+        import torch  # noqa: F401
         lib = ctypes.CDLL(LIB_PATH)
         lib.ko_heuristic_order.argtypes = [ctypes.POINTER(KoGpuModel), ctypes.c_void_p, ctypes.c_int32,
                                             ctypes.c_uint32, _i32p, _i32p]
@@ -116,6 +120,17 @@ def _L():
         lib.ko_sync.restype = ctypes.c_int
         lib.ko_shutdown.argtypes = []
         lib.ko_shutdown.restype = ctypes.c_int
+        lib.ko_sample_orders.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]
+        lib.ko_sample_orders.restype = ctypes.c_int
+        lib.ko_topk_f32.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]
+        lib.ko_topk_f32.restype = ctypes.c_int
+        lib.ko_kth_smallest_i64.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64),
+                                             ctypes.c_void_p]
+        lib.ko_kth_smallest_i64.restype = ctypes.c_int
         lib.ko_set_kernel_timing.argtypes = [ctypes.c_int32]
         lib.ko_set_kernel_timing.restype = ctypes.c_int
         lib.ko_last_kernel_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
@@ -305,6 +320,49 @@ def ko_rank_percentile(gpu, kernels, order, n_samples: int = 0, seed: int = 0, s
                                    o.ctypes.data_as(_i32p), int(n_samples), int(seed) & ((1 << 64) - 1),
                                    ctypes.byref(res), _stream_handle(stream)))
     return {f: getattr(res, f) for f, _ in KoRankResult._fields_}
+
+
+def ko_sample_orders(n: int, set_index: int, seed: int, count: int, *, first: int = 0, indices=None,
+                     orders=None, positions=None, stream=None):
+    """Write the SAMPLED-mode orders (uint8 [count][n]) and/or their inverses
+    (positions) into device tensors; samples first..first+count-1, or the
+    sample numbers in `indices` (int64/uint64 device tensor)."""
+    import torch
+    o = _dev_ptr(orders, torch.uint8, count * n, "orders") if orders is not None else None
+    p = _dev_ptr(positions, torch.uint8, count * n, "positions") if positions is not None else None
+    ix = None
+    if indices is not None:
+        if indices.dtype not in (torch.int64, torch.uint64):
+            raise TypeError("indices must be a 64-bit integer tensor")
+        ix = _dev_ptr(indices, indices.dtype, count, "indices")
+    _check(_L().ko_sample_orders(int(n), int(set_index), int(seed) & ((1 << 64) - 1), int(first), ix,
+                                 int(count), o, p, _stream_handle(stream)))
+
+
+def ko_topk_f32(y, k: int, *, idx_out=None, val_out=None, stream=None):
+    """The k smallest of the float32 device tensor y, ascending by (value, index).
+    Returns (idx int64 tensor, val float32 tensor) on y's device."""
+    import torch
+    count = y.numel()
+    if idx_out is None:
+        idx_out = torch.empty(k, dtype=torch.int64, device=y.device)
+    if val_out is None:
+        val_out = torch.empty(k, dtype=torch.float32, device=y.device)
+    _check(_L().ko_topk_f32(_dev_ptr(y, torch.float32, count, "y"), count, int(k),
+                            _dev_ptr(idx_out, torch.int64, k, "idx_out"),
+                            _dev_ptr(val_out, torch.float32, k, "val_out"), _stream_handle(stream)))
+    return idx_out, val_out
+
+
+def ko_kth_smallest_i64(v, k: int, stream=None, *, with_count: bool = False):
+    """The k-th smallest (1-based) of the int64 device tensor v (synchronous);
+    with_count=True returns (value, number of elements <= value)."""
+    import torch
+    out = ctypes.c_int64(0)
+    le = ctypes.c_uint64(0)
+    _check(_L().ko_kth_smallest_i64(_dev_ptr(v, torch.int64, v.numel(), "v"), v.numel(), int(k),
+                                    ctypes.byref(out), ctypes.byref(le), _stream_handle(stream)))
+    return (int(out.value), int(le.value)) if with_count else int(out.value)
 
 
 def ko_sync(stream=None):

@@ -48,8 +48,10 @@ def build(verbose: bool = True) -> str:
     sim_o = os.path.join(objdir, "ko_sim.o")
     _run([HIPCC, *COMMON, "-x", "hip", *DEVICE, "-c", os.path.join(CSRC, "ko_host.cpp"), "-o", host_o])
     _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_sim.hip"), "-o", sim_o])
+    sel_o = os.path.join(objdir, "ko_select.o")
+    _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_select.hip"), "-o", sel_o])
     tmp = LIB + ".tmp"
-    _run([HIPCC, *DEVICE, "-shared", "-fPIC", host_o, sim_o, "-o", tmp])
+    _run([HIPCC, *DEVICE, "-shared", "-fPIC", host_o, sim_o, sel_o, "-o", tmp])
     os.replace(tmp, LIB)
     nn_o = os.path.join(objdir, "ko_nn.o")
     _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_nn.hip"), "-o", nn_o])

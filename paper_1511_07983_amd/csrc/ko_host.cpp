@@ -2,7 +2,8 @@
 //
 // Argument validation, per-block derivation of the kernel records, the
 // launch-order heuristic (Algorithm 1), order counting, the per-device
-// workspace, and the launches of the gfx950 kernels in ko_sim.hip.
+// workspace, and the launches of the gfx950 kernels in ko_sim.hip and
+// ko_select.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,6 +17,7 @@
 
 #include "ko.h"
 #include "ko_device.h"
+#include "ko_select.h"
 
 namespace {
 
@@ -382,6 +384,12 @@ struct Workspace {
     hipEvent_t done = nullptr;    // after the last call's work
     bool pending_status = false;
     bool clear_status = false;  // a reported device status must be cleared before the next launch
+    // selection: 256 digit counters + 1 cursor (device), their host copy
+    // (pinned), and the candidate buffer of a top-k
+    unsigned long long *sel_bins = nullptr;
+    uint64_t *sel_host = nullptr;
+    uint64_t *sel_cand = nullptr;
+    size_t sel_cand_cap = 0;
     // optional timing of the simulate kernel (ko_set_kernel_timing)
     hipEvent_t sim_begin = nullptr, sim_end = nullptr;
     bool timing = false;
@@ -441,6 +449,9 @@ int get_workspace(Workspace **out)
         *w.status_host = 0;
         KO_HIP(hipEventCreateWithFlags(&w.staged, hipEventDisableTiming), "hipEventCreate");
         KO_HIP(hipEventCreateWithFlags(&w.done, hipEventDisableTiming), "hipEventCreate");
+        KO_HIP(hipMalloc((void **)&w.sel_bins, 257 * sizeof(unsigned long long)), "hipMalloc");
+        KO_HIP(hipHostMalloc((void **)&w.sel_host, 257 * sizeof(uint64_t), hipHostMallocDefault),
+               "hipHostMalloc");
         KO_HIP(hipEventCreate(&w.sim_begin), "hipEventCreate");
         KO_HIP(hipEventCreate(&w.sim_end), "hipEventCreate");
         KO_HIP(hipEventRecord(w.staged, 0), "hipEventRecord");
@@ -473,6 +484,9 @@ void release_workspace(Workspace &w)
     (void)hipHostFree(w.ref_host);
     (void)hipEventDestroy(w.staged);
     (void)hipEventDestroy(w.done);
+    (void)hipFree(w.sel_bins);
+    (void)hipFree(w.sel_cand);
+    (void)hipHostFree(w.sel_host);
     (void)hipEventDestroy(w.sim_begin);
     (void)hipEventDestroy(w.sim_end);
     (void)hipSetDevice(prev);
@@ -558,6 +572,44 @@ struct BatchPlan {
 };
 
 constexpr uint64_t kHistPerBlock = 1 << 16;
+
+// ------------------------------------------------------------------ selection
+
+constexpr uint64_t kTopkMax = 16384;         // largest k of ko_topk_f32
+constexpr uint64_t kTopkCandidates = 32768;  // values <= the k-th, ties included
+
+// One radix-select pass: count the next 8-bit digit of the keys that match
+// `prefix` under `mask`, then fix that digit so that the k-th smallest key
+// (1-based `rem` within the class) keeps its place.  Updates prefix, mask and
+// rem; *class_count receives the size of the chosen digit's class.
+template <typename Launch>
+int radix_pass(Workspace &w, hipStream_t stream, uint32_t shift, uint64_t *prefix, uint64_t *mask,
+               uint64_t *rem, uint64_t *class_count, Launch launch)
+{
+    int e = ko::launch_zero_u64((uint64_t *)w.sel_bins, 256, stream);
+    if (e)
+        return hip_fail((hipError_t)e, "zero digit counters");
+    e = launch(*prefix, *mask, shift);
+    if (e)
+        return hip_fail((hipError_t)e, "radix histogram launch");
+    KO_HIP(hipMemcpyAsync(w.sel_host, w.sel_bins, 256 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+           "hipMemcpyAsync");
+    KO_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    uint64_t cum = 0;
+    for (uint32_t d = 0; d < 256; d++) {
+        const uint64_t c = w.sel_host[d];
+        if (cum + c >= *rem) {
+            *prefix |= (uint64_t)d << shift;
+            *mask |= (uint64_t)0xFF << shift;
+            *rem -= cum;
+            *class_count = c;
+            return KO_OK;
+        }
+        cum += c;
+    }
+    return fail(KO_EHIP, "radix selection lost count (%llu of %llu)", (unsigned long long)cum,
+                (unsigned long long)*rem);
+}
 
 int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernels,
                   const int32_t *set_offsets, int32_t n_sets, const ko_order_spec *spec,
@@ -886,6 +938,125 @@ int ko_shutdown(void)
     for (Workspace &w : g_ws)
         release_workspace(w);
     g_ws.clear();
+    return KO_OK;
+}
+
+int ko_sample_orders(int32_t n, int32_t set_index, uint64_t seed, uint64_t first,
+                     const uint64_t *indices_dev, uint64_t count, uint8_t *orders_dev,
+                     uint8_t *positions_dev, void *hip_stream)
+{
+    if (n < 1 || n > ko::kMaxSet)
+        return fail(KO_EINVAL, "n %d outside 1..%d", n, ko::kMaxSet);
+    if (set_index < 0 || set_index >= (1 << 24))
+        return fail(KO_EINVAL, "set_index %d outside 0..2^24-1", set_index);
+    if (!orders_dev && !positions_dev)
+        return fail(KO_EINVAL, "orders_dev and positions_dev are both NULL");
+    const uint64_t kCounters = uint64_t(1) << 40;
+    if (count > kCounters || (!indices_dev && first > kCounters - count))
+        return fail(KO_ERANGE, "sample indices must stay below 2^40");
+    if (count == 0)
+        return KO_OK;
+    int e = ko::launch_sample_orders((uint32_t)n, (uint32_t)set_index, seed, first, indices_dev, count,
+                                     orders_dev, positions_dev, hip_stream);
+    if (e)
+        return hip_fail((hipError_t)e, "sample orders launch");
+    return KO_OK;
+}
+
+int ko_topk_f32(const float *y_dev, uint64_t count, int32_t k, int64_t *idx_out_dev, float *val_out_dev,
+                void *hip_stream)
+{
+    try {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        if (!y_dev)
+            return fail(KO_EINVAL, "y_dev must not be NULL");
+        if (!idx_out_dev && !val_out_dev)
+            return fail(KO_EINVAL, "idx_out_dev and val_out_dev are both NULL");
+        if (count < 1 || count >= (uint64_t(1) << 32))
+            return fail(KO_EINVAL, "count must be in 1..2^32-1");
+        if (k < 1 || (uint64_t)k > std::min<uint64_t>(count, kTopkMax))
+            return fail(KO_EINVAL, "k must be in 1..min(count, %llu)", (unsigned long long)kTopkMax);
+        Workspace *w = nullptr;
+        int rc = get_workspace(&w);
+        if (rc)
+            return rc;
+        rc = check_status(*w, false);
+        if (rc)
+            return rc;
+        hipStream_t stream = (hipStream_t)hip_stream;
+        if ((rc = grow_device(w->done, (void **)&w->sel_cand, &w->sel_cand_cap,
+                              kTopkCandidates * sizeof(uint64_t))))
+            return rc;
+        KO_HIP(hipStreamWaitEvent(stream, w->done, 0), "hipStreamWaitEvent");
+        const int grid = std::max(1, w->cu_count * 8);
+        uint64_t prefix = 0, mask = 0, rem = (uint64_t)k, cls = 0;
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            rc = radix_pass(*w, stream, (uint32_t)shift, &prefix, &mask, &rem, &cls,
+                            [&](uint64_t p, uint64_t m, uint32_t sh) {
+                                return ko::launch_radix_hist_f32(y_dev, count, sh, m, p, w->sel_bins,
+                                                                 grid, stream);
+                            });
+            if (rc)
+                return rc;
+        }
+        // keys < k-th: k - rem of them; keys == k-th: cls
+        const uint64_t total = (uint64_t)k - rem + cls;
+        if (total > kTopkCandidates)
+            return fail(KO_ERANGE, "%llu values tie with the k-th smallest; at most %llu candidates",
+                        (unsigned long long)total, (unsigned long long)kTopkCandidates);
+        unsigned long long *cursor = w->sel_bins + 256;
+        int e = ko::launch_zero_u64((uint64_t *)cursor, 1, stream);
+        if (!e)
+            e = ko::launch_gather_f32(y_dev, count, (uint32_t)prefix, w->sel_cand, kTopkCandidates, cursor,
+                                      grid, stream);
+        uint64_t n_pow2 = 1;
+        while (n_pow2 < total)
+            n_pow2 <<= 1;
+        if (!e)
+            e = ko::launch_bitonic_sort_u64(w->sel_cand, total, n_pow2, stream);
+        if (!e)
+            e = ko::launch_unpack_topk(w->sel_cand, (uint32_t)k, idx_out_dev, val_out_dev, stream);
+        if (e)
+            return hip_fail((hipError_t)e, "top-k launch");
+        KO_HIP(hipEventRecord(w->done, stream), "hipEventRecord");
+        return KO_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(KO_ENOMEM, "host allocation failed");
+    }
+}
+
+int ko_kth_smallest_i64(const int64_t *v_dev, uint64_t count, uint64_t k, int64_t *value_out,
+                        uint64_t *count_le_out, void *hip_stream)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (!v_dev || !value_out)
+        return fail(KO_EINVAL, "v_dev and value_out must not be NULL");
+    if (count < 1 || k < 1 || k > count)
+        return fail(KO_EINVAL, "need 1 <= k <= count");
+    Workspace *w = nullptr;
+    int rc = get_workspace(&w);
+    if (rc)
+        return rc;
+    rc = check_status(*w, false);
+    if (rc)
+        return rc;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    KO_HIP(hipStreamWaitEvent(stream, w->done, 0), "hipStreamWaitEvent");
+    const int grid = std::max(1, w->cu_count * 8);
+    uint64_t prefix = 0, mask = 0, rem = k, cls = 0;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        rc = radix_pass(*w, stream, (uint32_t)shift, &prefix, &mask, &rem, &cls,
+                        [&](uint64_t p, uint64_t m, uint32_t sh) {
+                            return ko::launch_radix_hist_i64(v_dev, count, sh, m, p, w->sel_bins, grid,
+                                                             stream);
+                        });
+        if (rc)
+            return rc;
+    }
+    KO_HIP(hipEventRecord(w->done, stream), "hipEventRecord");
+    *value_out = (int64_t)(prefix ^ 0x8000000000000000ull);
+    if (count_le_out)
+        *count_le_out = k - rem + cls;  // below the k-th value, plus its ties
     return KO_OK;
 }
 

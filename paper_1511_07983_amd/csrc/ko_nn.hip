@@ -92,6 +92,11 @@ struct GemmArgs {
     int64_t ldc;
     uint16_t *Cb;        // bf16 result (relu(C) for kEpiRelu), row-major with ldcb (or null)
     int64_t ldcb;
+    // split-K: workgroup z sums k in [z*kchunk, (z+1)*kchunk) and stores its raw
+    // partial product to P + z*M*N (row-major, N columns); a second kernel adds
+    // the partials in z order, so the result does not depend on scheduling
+    float *P;            // null = no split
+    int64_t kchunk;
 };
 
 constexpr int kTile = 64;
@@ -108,6 +113,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs a)
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t m0 = (int64_t)blockIdx.x * kTile;
     const int64_t n0 = (int64_t)blockIdx.y * kTile;
+    const int64_t kb = a.P ? (int64_t)blockIdx.z * a.kchunk : 0;
+    const int64_t ke = a.P ? min((int64_t)a.K, kb + a.kchunk) : (int64_t)a.K;
     f32x4 acc[2][2];
     for (int i = 0; i < 2; i++)
         for (int j = 0; j < 2; j++)
@@ -115,17 +122,17 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs a)
 
     const int lr = tid >> 2;         // tile row (A) / tile column (B) loaded by this thread
     const int lk = (tid & 3) * 8;    // first of its 8 k values
-    for (int64_t k0 = 0; k0 < a.K; k0 += kKStep) {
+    for (int64_t k0 = kb; k0 < ke; k0 += kKStep) {
         {
             const int64_t m = m0 + lr;
             for (int e = 0; e < 8; e++) {
                 const int64_t k = k0 + lk + e;
-                As[lr][lk + e] = (m < a.M && k < a.K) ? a.A[m * a.sam + k * a.sak] : (uint16_t)0;
+                As[lr][lk + e] = (m < a.M && k < ke) ? a.A[m * a.sam + k * a.sak] : (uint16_t)0;
             }
             const int64_t n = n0 + lr;
             for (int e = 0; e < 8; e++) {
                 const int64_t k = k0 + lk + e;
-                Bs[lr][lk + e] = (n < a.N && k < a.K) ? a.B[k * a.sbk + n * a.sbn] : (uint16_t)0;
+                Bs[lr][lk + e] = (n < a.N && k < ke) ? a.B[k * a.sbk + n * a.sbn] : (uint16_t)0;
             }
         }
         __syncthreads();
@@ -148,6 +155,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs a)
                 if (row >= a.M || col >= a.N)
                     continue;
                 float v = acc[i][j][e];
+                if (a.P) {
+                    a.P[(int64_t)blockIdx.z * a.M * a.N + row * a.N + col] = v;
+                    continue;
+                }
                 if (a.epi == kEpiMask) {
                     v = (a.zref[row * a.ldz + col] > 0.f) ? v : 0.f;
                 } else if (a.bias) {
@@ -158,6 +169,19 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs a)
                 if (a.Cb)
                     a.Cb[row * a.ldcb + col] = to_bf16(a.epi == kEpiRelu ? fmaxf(v, 0.f) : v);
             }
+}
+
+// C[r][c] = sum_z P[z][r][c], z ascending
+__global__ void splitk_reduce_kernel(const float *P, int64_t splits, int32_t M, int32_t N, float *C,
+                                     int64_t ldc)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)M * N)
+        return;
+    float s = 0.f;
+    for (int64_t z = 0; z < splits; z++)
+        s += P[z * M * N + idx];
+    C[(idx / N) * ldc + idx % N] = s;
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -245,28 +269,43 @@ __global__ void out_backward_kernel(const float *dy, const uint16_t *wb, const f
     dZ3b[idx] = to_bf16(v);
 }
 
-// out[c] = sum_r w(r) * X(r, c) for c < cols, one workgroup per column, where
-// X(r, c) is float32 (Xf) or bf16 (Xb) with row pitch ld, and w(r) is wrow[r]
-// or 1.  Also, for column index cols (an extra workgroup), out[cols] = sum_r wrow[r].
-__global__ __launch_bounds__(256) void colsum_kernel(const float *Xf, const uint16_t *Xb, int64_t ld,
-                                                     int64_t rows, int32_t cols, const float *wrow,
-                                                     float *out, int32_t out_extra)
+// Column sums in two deterministic stages.  Stage 1: workgroup g covers rows
+// [g*chunk, (g+1)*chunk) and thread c adds w(r) * X(r, c) down column c
+// (coalesced across threads); thread `cols` adds w(r) alone when `with_w` is
+// set.  X(r, c) is float32 (Xf) or bf16 (Xb) with row pitch ld; w(r) is
+// wrow[r] or 1.  Stage 2 adds the partials of the chunks in order.
+__global__ __launch_bounds__(320) void colsum_partial_kernel(const float *Xf, const uint16_t *Xb,
+                                                             int64_t ld, int64_t rows, int32_t cols,
+                                                             const float *wrow, int32_t with_w,
+                                                             int64_t chunk, float *part)
 {
-    __shared__ float red[4];
-    const int c = blockIdx.x;
+    const int c = threadIdx.x;
+    const int width = cols + (with_w ? 1 : 0);
+    if (c >= width)
+        return;
+    const int64_t r0 = (int64_t)blockIdx.x * chunk;
+    const int64_t r1 = min(rows, r0 + chunk);
     float s = 0.f;
-    if (c < cols) {
-        for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) {
-            const float x = Xf ? Xf[r * ld + c] : from_bf16(Xb[r * ld + c]);
-            s += wrow ? wrow[r] * x : x;
-        }
-    } else {
-        for (int64_t r = threadIdx.x; r < rows; r += blockDim.x)
-            s += wrow[r];
+    for (int64_t r = r0; r < r1; r++) {
+        const float w = wrow ? wrow[r] : 1.f;
+        if (c < cols)
+            s += w * (Xf ? Xf[r * ld + c] : from_bf16(Xb[r * ld + c]));
+        else
+            s += w;
     }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0)
-        out[c < cols ? c : out_extra] = s;
+    part[(int64_t)blockIdx.x * width + c] = s;
+}
+
+__global__ void colsum_finish_kernel(const float *part, int64_t chunks, int32_t width, float *out,
+                                     int32_t cols, int32_t out_extra)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= width)
+        return;
+    float s = 0.f;
+    for (int64_t g = 0; g < chunks; g++)
+        s += part[g * width + c];
+    out[c < cols ? c : out_extra] = s;
 }
 
 // dZ1[r][c] = dS[r / n][c] * [Z1[r][c] > 0]   (fp32 and bf16)
@@ -313,8 +352,8 @@ __global__ void zero_f32_kernel(float *p, int64_t count)
 }
 
 // x[b][i][0..7] = bf16(feat[set][i][.]); x[b][i][8 + pos] = 1; rest 0.
-__global__ void tokens_kernel(const float *feat, const int32_t *set_of, const uint8_t *pos, int32_t B,
-                              int32_t n, uint16_t *x)
+__global__ void tokens_kernel(const float *feat, const int32_t *set_of, const uint8_t *pos,
+                              const int64_t *rows, int32_t B, int32_t n, uint16_t *x)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)B * n * kIn)
@@ -322,14 +361,65 @@ __global__ void tokens_kernel(const float *feat, const int32_t *set_of, const ui
     const int64_t t = idx / kIn;
     const int f = (int)(idx % kIn);
     const int64_t b = t / n, i = t % n;
-    const int64_t s = set_of ? set_of[b] : 0;
+    const int64_t r = rows ? rows[b] : b;
+    const int64_t s = set_of ? set_of[r] : 0;
     uint16_t v = 0;
     if (f < KO_NN_FEAT) {
         v = to_bf16(feat[(s * n + i) * KO_NN_FEAT + f]);
     } else if (f < KO_NN_FEAT + KO_NN_POS) {
-        v = (pos[b * n + i] == (uint8_t)(f - KO_NN_FEAT)) ? (uint16_t)0x3F80 : (uint16_t)0;
+        v = (pos[r * n + i] == (uint8_t)(f - KO_NN_FEAT)) ? (uint16_t)0x3F80 : (uint16_t)0;
     }
     x[idx] = v;
+}
+
+// t[b] = (makespan[r] - center[s]) / scale[s] with r = rows[b] (or b), s = set_of[r]
+__global__ void targets_kernel(const int64_t *makespans, const int32_t *set_of, const int64_t *center,
+                               const int64_t *scale, const int64_t *rows, int32_t B, float *t)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B)
+        return;
+    const int64_t r = rows ? rows[b] : b;
+    const int64_t s = set_of ? set_of[r] : 0;
+    t[b] = (float)((double)(makespans[r] - center[s]) / (double)scale[s]);
+}
+
+// Layer 1 for one set, tabulated over launch positions: a token is its
+// kernel's features plus a one-hot position, so its first-layer output is
+//   T[i][p][j] = relu(sum_{k<8} W1[j][k] f_i[k] + W1[j][8+p] + b1[j])
+// for kernel i at position p (17 positions: 16 launch slots and "unplaced").
+// Operands are the BF16 values the token path multiplies; sums are float32.
+__global__ void table_kernel(const uint16_t *wb, const float *master, const float *feat, int32_t n,
+                             float *T)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * KO_NN_POS * kHid)
+        return;
+    const int j = (int)(idx % kHid);
+    const int p = (int)((idx / kHid) % KO_NN_POS);
+    const int64_t i = idx / ((int64_t)kHid * KO_NN_POS);
+    float z = 0.f;
+    for (int k = 0; k < KO_NN_FEAT; k++)
+        z += from_bf16(wb[kW1 + (size_t)j * kIn + k]) * from_bf16(to_bf16(feat[i * KO_NN_FEAT + k]));
+    z += from_bf16(wb[kW1 + (size_t)j * kIn + KO_NN_FEAT + p]);
+    z += master[kB1 + j];
+    T[idx] = fmaxf(z, 0.f);
+}
+
+// Sum pooling from the table: S[b][j] = sum_i T[i][pos[b][i]][j] (kernel order,
+// as the token path sums), stored as BF16.  One workgroup per sample; a
+// position above 16 counts as "unplaced".
+__global__ __launch_bounds__(256) void gather_pool_kernel(const float *T, const uint8_t *pos, int32_t n,
+                                                          uint16_t *Sb)
+{
+    const int64_t b = blockIdx.x;
+    const int j = threadIdx.x;
+    float s = 0.f;
+    for (int i = 0; i < n; i++) {
+        const int p = min((int)pos[b * n + i], KO_NN_UNPLACED);
+        s += T[((int64_t)i * KO_NN_POS + p) * kHid + j];
+    }
+    Sb[b * kHid + j] = to_bf16(s);
 }
 
 // ------------------------------------------------------------------ host side
@@ -364,11 +454,30 @@ int fail(int code, const char *fmt, ...)
 unsigned grid1(int64_t count) { return (unsigned)((count + 255) / 256); }
 
 struct Work {
+    float *P;  // split-K and column-sum partials
     float *Z1, *S, *Z2, *Z3, *y, *dy, *dZ3, *dZ2, *dS, *dZ1;
     uint16_t *Sb, *A2b, *A3b, *dZ3b, *dZ2b, *dZ1b;
 };
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// split count for a reduction over K rows: chunks of at least 256, at most `cap`
+int64_t split_count(int64_t K, int64_t cap)
+{
+    int64_t s = K / 256;
+    return s < 1 ? 1 : (s > cap ? cap : s);
+}
+
+constexpr int64_t kSplitCapW1 = 256, kSplitCapW = 64, kColChunks = 256;
+
+size_t partial_floats(int64_t B, int64_t n)
+{
+    const int64_t T = B * n;
+    size_t need = (size_t)split_count(T, kSplitCapW1) * kHid * kIn;
+    need = std::max(need, (size_t)split_count(B, kSplitCapW) * kHid * kHid);
+    need = std::max(need, (size_t)kColChunks * (kHid + 1));
+    return need;
+}
 
 Work work_of(void *p, int64_t B, int64_t n, size_t *total)
 {
@@ -381,6 +490,7 @@ Work work_of(void *p, int64_t B, int64_t n, size_t *total)
     };
     const int64_t BH = B * kHid, TH = B * n * kHid;
     Work w;
+    w.P = (float *)take(partial_floats(B, n) * 4);
     w.Z1 = (float *)take(TH * 4);
     w.dZ1 = (float *)take(TH * 4);
     w.dZ1b = (uint16_t *)take(TH * 2);
@@ -407,6 +517,48 @@ int gemm(const GemmArgs &a, hipStream_t st)
         return KO_OK;
     dim3 grid((unsigned)((a.M + kTile - 1) / kTile), (unsigned)((a.N + kTile - 1) / kTile));
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, st, a);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+// Weight gradient C[M][N] (fp32, row pitch ldc) = sum over K of A(m,k) B(k,n),
+// with K split across workgroups and the partials added in a fixed order.
+int gemm_splitk(GemmArgs a, float *P, int64_t cap, hipStream_t st)
+{
+    if (a.M <= 0 || a.N <= 0 || a.K <= 0)
+        return KO_OK;
+    const int64_t splits = split_count(a.K, cap);
+    a.kchunk = ((a.K + splits - 1) / splits + kKStep - 1) / kKStep * kKStep;
+    const int64_t used = (a.K + a.kchunk - 1) / a.kchunk;
+    float *C = a.C;
+    const int64_t ldc = a.ldc;
+    a.P = P;
+    a.C = nullptr;
+    a.Cb = nullptr;
+    dim3 grid((unsigned)((a.M + kTile - 1) / kTile), (unsigned)((a.N + kTile - 1) / kTile),
+              (unsigned)used);
+    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, st, a);
+    NN_LAUNCHED();
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid1((int64_t)a.M * a.N)), dim3(256), 0, st, P, used,
+                       a.M, a.N, C, ldc);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+// out[c] = sum_r w(r) X(r, c) for c < cols, and out[out_extra] = sum_r w(r)
+// when with_w is set.
+int colsum(const float *Xf, const uint16_t *Xb, int64_t ld, int64_t rows, int32_t cols, const float *wrow,
+           bool with_w, float *out, int32_t out_extra, float *P, hipStream_t st)
+{
+    const int64_t chunks = std::min<int64_t>(kColChunks, std::max<int64_t>(1, rows / 64));
+    const int64_t chunk = (rows + chunks - 1) / chunks;
+    const int64_t used = (rows + chunk - 1) / chunk;
+    const int32_t width = cols + (with_w ? 1 : 0);
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3((unsigned)used), dim3(320), 0, st, Xf, Xb, ld, rows, cols,
+                       wrow, with_w ? 1 : 0, chunk, P);
+    NN_LAUNCHED();
+    hipLaunchKernelGGL(colsum_finish_kernel, dim3((unsigned)((width + 255) / 256)), dim3(256), 0, st, P, used,
+                       width, out, cols, out_extra);
     NN_LAUNCHED();
     return KO_OK;
 }
@@ -477,6 +629,34 @@ int forward_impl(const State &s, const uint16_t *x, int32_t B, int32_t n, float 
         return rc;
     hipLaunchKernelGGL(out_forward_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, st, w.A3b,
                        s.wb, s.master, B, y);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+// Scoring forward from positions: S from the layer-1 table, then the two
+// hidden layers (BF16 outputs only) and the output layer.
+int forward_positions_impl(const State &s, const float *T, const uint8_t *pos, int32_t B, int32_t n,
+                           float *y, uint16_t *Sb, uint16_t *A2b, uint16_t *A3b, hipStream_t st)
+{
+    int rc;
+    hipLaunchKernelGGL(gather_pool_kernel, dim3((unsigned)B), dim3(kHid), 0, st, T, pos, n, Sb);
+    NN_LAUNCHED();
+    GemmArgs a = gemm_args(Sb, kHid, 1, s.wb + kW2, 1, kHid, B, kHid, kHid);
+    a.bias = s.master + kB2;
+    a.epi = kEpiRelu;
+    a.Cb = A2b;
+    a.ldcb = kHid;
+    if ((rc = gemm(a, st)))
+        return rc;
+    a = gemm_args(A2b, kHid, 1, s.wb + kW3, 1, kHid, B, kHid, kHid);
+    a.bias = s.master + kB3;
+    a.epi = kEpiRelu;
+    a.Cb = A3b;
+    a.ldcb = kHid;
+    if ((rc = gemm(a, st)))
+        return rc;
+    hipLaunchKernelGGL(out_forward_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, st, A3b, s.wb,
+                       s.master, B, y);
     NN_LAUNCHED();
     return KO_OK;
 }
@@ -593,13 +773,25 @@ int ko_nn_lower_bound(const ko_gpu_model *g, const ko_kernel *k, int32_t n, int6
     return KO_OK;
 }
 
-int ko_nn_tokens(const float *feat_dev, const int32_t *set_of_dev, const uint8_t *pos_dev, int32_t B,
-                 int32_t n, uint16_t *x_dev, void *hip_stream)
+int ko_nn_tokens(const float *feat_dev, const int32_t *set_of_dev, const uint8_t *pos_dev,
+                 const int64_t *rows_dev, int32_t B, int32_t n, uint16_t *x_dev, void *hip_stream)
 {
     if (!feat_dev || !pos_dev || !x_dev || B < 1 || n < 1 || n > KO_NN_MAX_TOKENS)
         return fail(KO_EINVAL, "bad arguments");
     hipLaunchKernelGGL(tokens_kernel, dim3(grid1((int64_t)B * n * kIn)), dim3(256), 0,
-                       (hipStream_t)hip_stream, feat_dev, set_of_dev, pos_dev, B, n, x_dev);
+                       (hipStream_t)hip_stream, feat_dev, set_of_dev, pos_dev, rows_dev, B, n, x_dev);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+int ko_nn_targets(const int64_t *makespans_dev, const int32_t *set_of_dev, const int64_t *center_dev,
+                  const int64_t *scale_dev, const int64_t *rows_dev, int32_t B, float *t_dev,
+                  void *hip_stream)
+{
+    if (!makespans_dev || !center_dev || !scale_dev || !t_dev || B < 1)
+        return fail(KO_EINVAL, "bad arguments");
+    hipLaunchKernelGGL(targets_kernel, dim3(grid1(B)), dim3(256), 0, (hipStream_t)hip_stream,
+                       makespans_dev, set_of_dev, center_dev, scale_dev, rows_dev, B, t_dev);
     NN_LAUNCHED();
     return KO_OK;
 }
@@ -636,21 +828,19 @@ int ko_nn_backward(void *state_dev, const uint16_t *x_dev, const float *t_dev, i
     hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, st, w.y, t_dev, B, w.dy, loss_dev);
     NN_LAUNCHED();
     // output layer: dw4[c] = sum_b dy[b] A3b[b][c], db4 = sum_b dy[b]
-    hipLaunchKernelGGL(colsum_kernel, dim3(kHid + 1), dim3(256), 0, st, (const float *)nullptr,
-                       w.A3b, (int64_t)kHid, (int64_t)B, kHid, w.dy, s.grad + kW4,
-                       (int32_t)(kB4 - kW4));
-    NN_LAUNCHED();
+    if ((rc = colsum(nullptr, w.A3b, kHid, B, kHid, w.dy, true, s.grad + kW4, (int32_t)(kB4 - kW4), w.P,
+                     st)))
+        return rc;
     hipLaunchKernelGGL(out_backward_kernel, dim3(grid1((int64_t)B * kHid)), dim3(256), 0, st, w.dy,
                        s.wb, w.Z3, B, w.dZ3, w.dZ3b);
     NN_LAUNCHED();
     // layer 3: db3, dW3 = dZ3b^T A2b, dZ2 = (dZ3b W3b) * [Z2 > 0]
-    hipLaunchKernelGGL(colsum_kernel, dim3(kHid), dim3(256), 0, st, w.dZ3, (const uint16_t *)nullptr,
-                       (int64_t)kHid, (int64_t)B, kHid, (const float *)nullptr, s.grad + kB3, 0);
-    NN_LAUNCHED();
+    if ((rc = colsum(w.dZ3, nullptr, kHid, B, kHid, nullptr, false, s.grad + kB3, 0, w.P, st)))
+        return rc;
     GemmArgs a = gemm_args(w.dZ3b, 1, kHid, w.A2b, kHid, 1, kHid, kHid, B);
     a.C = s.grad + kW3;
     a.ldc = kHid;
-    if ((rc = gemm(a, st)))
+    if ((rc = gemm_splitk(a, w.P, kSplitCapW, st)))
         return rc;
     a = gemm_args(w.dZ3b, kHid, 1, s.wb + kW3, kHid, 1, B, kHid, kHid);
     a.epi = kEpiMask;
@@ -663,13 +853,12 @@ int ko_nn_backward(void *state_dev, const uint16_t *x_dev, const float *t_dev, i
     if ((rc = gemm(a, st)))
         return rc;
     // layer 2: db2, dW2 = dZ2b^T Sb, dS = dZ2b W2b
-    hipLaunchKernelGGL(colsum_kernel, dim3(kHid), dim3(256), 0, st, w.dZ2, (const uint16_t *)nullptr,
-                       (int64_t)kHid, (int64_t)B, kHid, (const float *)nullptr, s.grad + kB2, 0);
-    NN_LAUNCHED();
+    if ((rc = colsum(w.dZ2, nullptr, kHid, B, kHid, nullptr, false, s.grad + kB2, 0, w.P, st)))
+        return rc;
     a = gemm_args(w.dZ2b, 1, kHid, w.Sb, kHid, 1, kHid, kHid, B);
     a.C = s.grad + kW2;
     a.ldc = kHid;
-    if ((rc = gemm(a, st)))
+    if ((rc = gemm_splitk(a, w.P, kSplitCapW, st)))
         return rc;
     a = gemm_args(w.dZ2b, kHid, 1, s.wb + kW2, kHid, 1, B, kHid, kHid);
     a.C = w.dS;
@@ -680,13 +869,12 @@ int ko_nn_backward(void *state_dev, const uint16_t *x_dev, const float *t_dev, i
     hipLaunchKernelGGL(dz1_kernel, dim3(grid1((int64_t)T * kHid)), dim3(256), 0, st, w.dS, w.Z1, B, n,
                        w.dZ1, w.dZ1b);
     NN_LAUNCHED();
-    hipLaunchKernelGGL(colsum_kernel, dim3(kHid), dim3(256), 0, st, w.dZ1, (const uint16_t *)nullptr,
-                       (int64_t)kHid, (int64_t)T, kHid, (const float *)nullptr, s.grad + kB1, 0);
-    NN_LAUNCHED();
+    if ((rc = colsum(w.dZ1, nullptr, kHid, T, kHid, nullptr, false, s.grad + kB1, 0, w.P, st)))
+        return rc;
     a = gemm_args(w.dZ1b, 1, kHid, x_dev, kIn, 1, kHid, kIn, T);
     a.C = s.grad + kW1;
     a.ldc = kIn;
-    if ((rc = gemm(a, st)))
+    if ((rc = gemm_splitk(a, w.P, kSplitCapW1, st)))
         return rc;
     return KO_OK;
 }
@@ -703,6 +891,41 @@ int ko_nn_adam(void *state_dev, int32_t step, float lr, float beta1, float beta2
                        s.grad, s.m, s.v, (int64_t)kNP, lr, beta1, beta2, eps, c1, c2, s.wb);
     NN_LAUNCHED();
     return KO_OK;
+}
+
+int ko_nn_layer1_table(const void *state_dev, const float *feat_dev, int32_t n, float *table_dev,
+                       void *hip_stream)
+{
+    if (!state_dev || !feat_dev || !table_dev)
+        return fail(KO_EINVAL, "state, features and table must not be NULL");
+    if (n < 1 || n > KO_NN_MAX_TOKENS)
+        return fail(KO_EINVAL, "n must be in 1..%d", KO_NN_MAX_TOKENS);
+    State s = state_of(const_cast<void *>(state_dev));
+    hipLaunchKernelGGL(table_kernel, dim3(grid1((int64_t)n * KO_NN_POS * kHid)), dim3(256), 0,
+                       (hipStream_t)hip_stream, s.wb, s.master, feat_dev, n, table_dev);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+size_t ko_nn_score_work_bytes(int32_t B)
+{
+    if (B < 1)
+        return 0;
+    return 3 * align256((size_t)B * kHid * 2);
+}
+
+int ko_nn_forward_positions(const void *state_dev, const float *table_dev, const uint8_t *pos_dev,
+                            int32_t B, int32_t n, float *y_dev, void *work_dev, void *hip_stream)
+{
+    if (!state_dev || !table_dev || !pos_dev || !y_dev || !work_dev)
+        return fail(KO_EINVAL, "state, table, positions, y and workspace must not be NULL");
+    if (B < 1 || n < 1 || n > KO_NN_MAX_TOKENS)
+        return fail(KO_EINVAL, "B must be >= 1 and n in 1..%d", KO_NN_MAX_TOKENS);
+    const size_t part = align256((size_t)B * kHid * 2);
+    char *c = (char *)work_dev;
+    return forward_positions_impl(state_of(const_cast<void *>(state_dev)), table_dev, pos_dev, B, n,
+                                  y_dev, (uint16_t *)c, (uint16_t *)(c + part),
+                                  (uint16_t *)(c + 2 * part), (hipStream_t)hip_stream);
 }
 
 const char *ko_nn_last_error(void) { return g_err.c_str(); }

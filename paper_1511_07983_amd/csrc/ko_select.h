@@ -1,0 +1,21 @@
+// Launchers of ko_select.hip (internal to libko).  Each returns a hipError_t
+// value as int.
+#pragma once
+
+#include <stdint.h>
+
+namespace ko {
+
+int launch_sample_orders(uint32_t n, uint32_t set, uint64_t seed, uint64_t first,
+                         const uint64_t *indices, uint64_t count, uint8_t *orders, uint8_t *positions,
+                         void *stream);
+int launch_radix_hist_f32(const float *src, uint64_t count, uint32_t shift, uint64_t mask,
+                          uint64_t prefix, unsigned long long *bins, int grid_cap, void *stream);
+int launch_radix_hist_i64(const int64_t *src, uint64_t count, uint32_t shift, uint64_t mask,
+                          uint64_t prefix, unsigned long long *bins, int grid_cap, void *stream);
+int launch_gather_f32(const float *src, uint64_t count, uint32_t kth_key, uint64_t *out, uint64_t cap,
+                      unsigned long long *cursor, int grid_cap, void *stream);
+int launch_bitonic_sort_u64(uint64_t *keys, uint64_t used, uint64_t n_pow2, void *stream);
+int launch_unpack_topk(const uint64_t *keys, uint32_t k, int64_t *idx, float *val, void *stream);
+
+}  // namespace ko

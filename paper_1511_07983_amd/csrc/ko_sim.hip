@@ -37,6 +37,7 @@
 #include <hip/hip_runtime.h>
 
 #include "ko_device.h"
+#include "ko_orders.h"
 
 namespace ko {
 
@@ -102,12 +103,6 @@ __device__ __forceinline__ uint32_t div_clamp(uint32_t fr, uint32_t u, float inv
     return q - ((__umul24(q, u) > fr) ? 1u : 0u);
 }
 
-__device__ const uint64_t kFact[21] = {
-    1ull, 1ull, 2ull, 6ull, 24ull, 120ull, 720ull, 5040ull, 40320ull, 362880ull, 3628800ull,
-    39916800ull, 479001600ull, 6227020800ull, 87178291200ull, 1307674368000ull,
-    20922789888000ull, 355687428096000ull, 6402373705728000ull, 121645100408832000ull,
-    2432902008176640000ull};
-
 // Lexicographic rank -> permutation, lane j holding position j.  Digit j of
 // the factorial number system is floor(rank / (n-1-j)!) mod (n-j); position j
 // takes the digit-th smallest kernel index not used by positions < j.
@@ -116,7 +111,7 @@ __device__ uint32_t unrank_lanes(uint64_t rank, uint32_t n)
     const uint32_t lane = lane_id();
     uint32_t digit = 0;
     if (lane < n) {
-        uint64_t f = kFact[n - 1 - lane];
+        uint64_t f = kFactorial[n - 1 - lane];
         digit = (uint32_t)((rank / f) % (uint64_t)(n - lane));
     }
     uint32_t avail = (n >= 32) ? 0xFFFFFFFFu : ((1u << n) - 1u);
@@ -151,14 +146,6 @@ __device__ uint32_t next_perm_lanes(uint32_t perm, uint32_t n)
     perm = (lane == i) ? pl : ((lane == l) ? pi : perm);
     uint32_t src = (lane > i && lane < n) ? (i + n - lane) : lane;
     return (uint32_t)__shfl((int)perm, (int)src);
-}
-
-__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c)
-{
-    uint64_t z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
 }
 
 // Makespan of the order held in `perm` (lane j = kernel at position j).
@@ -381,8 +368,7 @@ __global__ __launch_bounds__(256) void simulate_kernel(SimArgs a, uint32_t gslot
                     perm = unrank_lanes(0, n);
                 }
             } else if (a.mode == kModeSampled) {
-                const uint64_t x = splitmix64_at(a.seed, ((uint64_t)set << 40) | (first + i));
-                perm = unrank_lanes(__umul64hi(x, kFact[n]), n);
+                perm = unrank_lanes(sampled_rank(a.seed, (uint32_t)set, first + i, n), n);
             }
             const int64_t m = simulate_order<S>(a, kr, n, perm, ring, gslots);
             const uint64_t idx = index0 + i;

@@ -19,6 +19,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_NN_PATH = os.path.join(_HERE, "libko_nn.so")
 if not os.path.exists(LIB_NN_PATH):
     raise ImportError(f"{LIB_NN_PATH} is missing: build it with `python paper_1511_07983_amd/build.py`")
+# Load PyTorch's HIP runtime first: libko_nn.so must bind to the same
+# libamdhip64 instance that owns the device memory and streams it is given.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_NN_PATH)
 
 N_FEAT = 8
@@ -29,8 +33,9 @@ D_HID = 256
 MAX_TOKENS = 16
 
 EXPORTED = ("ko_nn_num_params", "ko_nn_state_bytes", "ko_nn_work_bytes", "ko_nn_load", "ko_nn_read",
-            "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens", "ko_nn_forward",
-            "ko_nn_backward", "ko_nn_adam", "ko_nn_last_error")
+            "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens", "ko_nn_targets", "ko_nn_forward",
+            "ko_nn_backward", "ko_nn_adam", "ko_nn_layer1_table", "ko_nn_score_work_bytes",
+            "ko_nn_forward_positions", "ko_nn_last_error")
 
 _vp = ctypes.c_void_p
 _lib.ko_nn_num_params.restype = ctypes.c_size_t
@@ -41,14 +46,20 @@ _lib.ko_nn_load.argtypes = [_vp, _vp, _vp]
 _lib.ko_nn_read.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
 _lib.ko_nn_features.argtypes = [_vp, _vp, ctypes.c_int32, _vp]
 _lib.ko_nn_lower_bound.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
-_lib.ko_nn_tokens.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
+_lib.ko_nn_tokens.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
+_lib.ko_nn_targets.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp]
 _lib.ko_nn_forward.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
 _lib.ko_nn_backward.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
 _lib.ko_nn_adam.argtypes = [_vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                             ctypes.c_float, _vp]
+_lib.ko_nn_layer1_table.argtypes = [_vp, _vp, ctypes.c_int32, _vp, _vp]
+_lib.ko_nn_score_work_bytes.argtypes = [ctypes.c_int32]
+_lib.ko_nn_score_work_bytes.restype = ctypes.c_size_t
+_lib.ko_nn_forward_positions.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
 _lib.ko_nn_last_error.restype = ctypes.c_char_p
-for _f in ("ko_nn_load", "ko_nn_read", "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens",
-           "ko_nn_forward", "ko_nn_backward", "ko_nn_adam"):
+for _f in ("ko_nn_load", "ko_nn_read", "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens", "ko_nn_targets",
+           "ko_nn_forward", "ko_nn_backward", "ko_nn_adam", "ko_nn_layer1_table",
+           "ko_nn_forward_positions"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -88,6 +99,7 @@ class Surrogate:
         self.state = torch.zeros(int(_lib.ko_nn_state_bytes()), dtype=torch.uint8, device=self.device)
         self._work = None
         self._work_key = None
+        self._score_work = None
         if params is not None:
             self.load(params)
 
@@ -109,14 +121,30 @@ class Surrogate:
                                _stream_handle(stream)))
         return out
 
-    def tokens(self, feat, pos, set_of=None, stream=None):
-        """feat: device float32 [S, n, 8]; pos: device uint8 [B, n]; set_of: device int32 [B]."""
+    def tokens(self, feat, pos, set_of=None, rows=None, B=None, stream=None, out=None):
+        """feat: device float32 [S, n, 8]; pos: device uint8 [R, n]; set_of: device
+        int32 [R]; rows: device int64 [B] (sample b uses row rows[b]; default b)."""
         torch = self.torch
-        B, n = pos.shape
-        x = torch.empty((B, n, D_IN), dtype=torch.int16, device=self.device)
+        n = pos.shape[1]
+        if B is None:
+            B = rows.shape[0] if rows is not None else pos.shape[0]
+        x = out if out is not None else torch.empty((B, n, D_IN), dtype=torch.int16, device=self.device)
         _check(_lib.ko_nn_tokens(feat.data_ptr(), set_of.data_ptr() if set_of is not None else None,
-                                 pos.data_ptr(), B, n, x.data_ptr(), _stream_handle(stream)))
+                                 pos.data_ptr(), rows.data_ptr() if rows is not None else None, B, n,
+                                 x.data_ptr(), _stream_handle(stream)))
         return x
+
+    def targets(self, makespans, center, scale, set_of=None, rows=None, B=None, stream=None, out=None):
+        """t[b] = (makespans[r] - center[s]) / scale[s] (device float32 [B]); r = rows[b], s = set_of[r]."""
+        torch = self.torch
+        if B is None:
+            B = rows.shape[0] if rows is not None else makespans.shape[0]
+        t = out if out is not None else torch.empty(B, dtype=torch.float32, device=self.device)
+        _check(_lib.ko_nn_targets(makespans.data_ptr(), set_of.data_ptr() if set_of is not None else None,
+                                  center.data_ptr(), scale.data_ptr(),
+                                  rows.data_ptr() if rows is not None else None, B, t.data_ptr(),
+                                  _stream_handle(stream)))
+        return t
 
     def forward(self, x, stream=None):
         torch = self.torch
@@ -134,6 +162,28 @@ class Surrogate:
                                    loss.data_ptr(), self._workspace(B, n).data_ptr(),
                                    _stream_handle(stream)))
         return loss
+
+    def layer1_table(self, feat, stream=None):
+        """feat: device float32 [n, 8] of one set -> device float32 table [n, 17, 256]."""
+        n = feat.shape[0]
+        table = self.torch.empty((n, N_POS, D_HID), dtype=self.torch.float32, device=self.device)
+        _check(_lib.ko_nn_layer1_table(self.state.data_ptr(), feat.data_ptr(), n, table.data_ptr(),
+                                       _stream_handle(stream)))
+        return table
+
+    def forward_positions(self, table, pos, y=None, stream=None):
+        """pos: device uint8 [B, n] (position of each kernel) -> y [B]."""
+        torch = self.torch
+        B, n = pos.shape
+        if y is None:
+            y = torch.empty(B, dtype=torch.float32, device=self.device)
+        need = int(_lib.ko_nn_score_work_bytes(B))
+        if self._score_work is None or self._score_work.numel() < need:
+            self._score_work = torch.empty(need, dtype=torch.uint8, device=self.device)
+        _check(_lib.ko_nn_forward_positions(self.state.data_ptr(), table.data_ptr(), pos.data_ptr(), B, n,
+                                            y.data_ptr(), self._score_work.data_ptr(),
+                                            _stream_handle(stream)))
+        return y
 
     def adam(self, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         _check(_lib.ko_nn_adam(self.state.data_ptr(), step, lr, beta1, beta2, eps,

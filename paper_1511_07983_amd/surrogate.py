@@ -1,0 +1,395 @@
+"""Surrogate-guided search for good launch orders on one GPU.
+
+The exact simulator (libko) prices one launch order per wavefront; a learned
+scorer (libko_nn) prices an order with two 256x256 BF16 MFMA layers after a
+gather-sum, so it can rank orders by the hundred million.  Every order the
+scorer proposes is re-simulated exactly, so reported makespans, quantiles and
+hit counts are exact integers; the scorer only decides which orders are
+simulated.
+
+Steps (each one a call into the two libraries; this module only sequences
+them and owns the host-side bookkeeping):
+
+  training data   sampled orders of many sets, their exact makespans
+                  (ko_simulate_batch, SAMPLED) and positions (ko_sample_orders);
+  training        shuffled minibatches -> tokens and targets (makespan minus the
+                  set's best sampled makespan, over the set's area lower bound)
+                  -> forward/backward -> Adam,
+                  all in libko_nn; with `mask_suffix` some samples hide a
+                  random suffix of their order ("unplaced"), which teaches the
+                  scorer partial orders for beam search;
+  scoring         the set's layer-1 table, then scores of sampled orders from
+                  positions, in batches; top-k (ko_topk_f32); the top-k orders
+                  regenerated from their sample numbers and re-simulated
+                  exactly;
+  beam search     partial orders grown one position at a time, the best
+                  `width` kept by score; the complete orders are re-simulated;
+  quantile        the exact makespan of the best 1% from a full enumeration
+                  (ko_kth_smallest_i64) and how many orders reach it.
+
+The figure of merit is the number of exact simulations needed to reach an
+order in the exact top 1%: uniform random sampling needs N / hits on average
+(geometric, with replacement); the scorer needs the 1-based position of the
+first hit in its ranked list.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import (OrderSpec, kernel_array, ko_kth_smallest_i64, ko_sample_orders, ko_simulate_batch, ko_sync,
+               ko_topk_f32)
+from . import nn
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class SetTable:
+    """Kernel sets of one size n on one GPU model, with device-side features
+    [S, n, 8] and area lower bounds [S]."""
+    model: object
+    sets: list
+    n: int
+    feat: object
+    lb: object
+    lb_host: np.ndarray
+    kernels: np.ndarray
+    offsets: np.ndarray
+
+    @classmethod
+    def build(cls, model, sets, device="cuda:0"):
+        torch = _torch()
+        n = len(sets[0])
+        if any(len(k) != n for k in sets):
+            raise ValueError("all sets of a SetTable must have the same size")
+        feats = np.stack([nn.features(model, k) for k in sets]).astype(np.float32)
+        lbs = np.array([nn.lower_bound(model, k) for k in sets], dtype=np.int64)
+        return cls(model=model, sets=list(sets), n=n, feat=torch.from_numpy(feats).to(device),
+                   lb=torch.from_numpy(lbs).to(device), lb_host=lbs,
+                   kernels=np.concatenate([kernel_array(k) for k in sets]),
+                   offsets=(np.arange(len(sets) + 1) * n).astype(np.int32))
+
+
+@dataclass
+class Samples:
+    """Set-major sample tables: row r = set r // per_set, sample r % per_set."""
+    per_set: int
+    seed: int
+    makespans: object   # int64 [R]
+    pos: object         # uint8 [R, n]
+    set_of: object      # int32 [R]
+    best: object        # int64 [S]: each set's best sampled makespan (target centre)
+
+    @property
+    def count(self) -> int:
+        return int(self.makespans.shape[0])
+
+
+def exact_samples(table: SetTable, per_set: int, seed: int, device="cuda:0") -> Samples:
+    """`per_set` sampled orders of every set with their exact makespans."""
+    torch = _torch()
+    S, n = len(table.sets), table.n
+    R = S * per_set
+    ms = torch.empty(R, dtype=torch.int64, device=device)
+    st = torch.empty(8 * S, dtype=torch.int64, device=device)
+    ko_simulate_batch(table.model, table.kernels, table.offsets, OrderSpec.sampled([per_set] * S, seed),
+                      makespans=ms, stats=st)
+    pos = torch.empty((R, n), dtype=torch.uint8, device=device)
+    flat = pos.view(-1)
+    for s in range(S):
+        ko_sample_orders(n, s, seed, per_set, positions=flat[s * per_set * n:(s + 1) * per_set * n])
+    set_of = torch.from_numpy(np.repeat(np.arange(S, dtype=np.int32), per_set)).to(device)
+    ko_sync()
+    best = st.view(S, 8)[:, 0].contiguous()  # min_makespan is the first field of a stats record
+    return Samples(per_set=per_set, seed=seed, makespans=ms, pos=pos, set_of=set_of, best=best)
+
+
+def mask_suffixes(samples: Samples, frac: float, seed: int) -> Samples:
+    """A copy of the samples where a fraction `frac` of the rows keep only a
+    random prefix of their order (the other kernels' positions become
+    "unplaced"); targets stay the full order's exact makespan."""
+    torch = _torch()
+    pos = samples.pos.cpu().numpy().copy()
+    R, n = pos.shape
+    rng = np.random.default_rng(seed)
+    rows = np.flatnonzero(rng.random(R) < frac)
+    keep = rng.integers(0, n, size=len(rows))  # positions < keep stay placed
+    sub = pos[rows]
+    sub[sub >= keep[:, None]] = nn.UNPLACED
+    pos[rows] = sub
+    return Samples(per_set=samples.per_set, seed=samples.seed, makespans=samples.makespans,
+                   pos=torch.from_numpy(pos).to(samples.pos.device), set_of=samples.set_of,
+                   best=samples.best)
+
+
+def train(sur: "nn.Surrogate", table: SetTable, data: Samples, *, steps: int, batch: int = 4096,
+          lr: float = 2e-3, warmup: int = 100, seed: int = 0, log_every: int = 100):
+    """Adam on shuffled minibatches; returns [(step, loss)] at log points.
+    Learning rate: linear warm-up, then cosine decay to 5% of `lr`."""
+    torch = _torch()
+    dev = data.makespans.device
+    R = data.count
+    if batch > R:
+        batch = R
+    rng = np.random.default_rng(seed)
+    per_epoch = R // batch
+    x = torch.empty((batch, table.n, nn.D_IN), dtype=torch.int16, device=dev)
+    t = torch.empty(batch, dtype=torch.float32, device=dev)
+    perm = None
+    log = []
+    for step in range(1, steps + 1):
+        j = (step - 1) % per_epoch
+        if j == 0:
+            perm = torch.from_numpy(rng.permutation(R).astype(np.int64)).to(dev)
+        rows = perm[j * batch:(j + 1) * batch]
+        sur.tokens(table.feat, data.pos, data.set_of, rows=rows, out=x)
+        sur.targets(data.makespans, data.best, table.lb, data.set_of, rows=rows, out=t)
+        loss = sur.backward(x, t)
+        if step <= warmup:
+            rate = lr * step / max(1, warmup)
+        else:
+            prog = (step - warmup) / max(1, steps - warmup)
+            rate = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * prog)))
+        sur.adam(step, rate)
+        if step == 1 or step % log_every == 0 or step == steps:
+            log.append((step, float(loss.cpu()[0])))
+    return log
+
+
+def predict(sur: "nn.Surrogate", table: SetTable, set_index: int, pos):
+    """Predicted makespans of one set's orders given as positions [B, n] (device),
+    in cycles above the set's best makespan (float64 host): the network is
+    trained on (makespan - best sampled) / lower bound, and only differences
+    within a set matter for ranking."""
+    tab = sur.layer1_table(table.feat[set_index])
+    y = sur.forward_positions(tab, pos).cpu().numpy().astype(np.float64)
+    return y * float(table.lb_host[set_index])
+
+
+def calibrated_mae(predicted_rel: np.ndarray, exact: np.ndarray) -> float:
+    """Mean absolute error in cycles after one per-set offset (the median of
+    exact - predicted) restores the set's unknown best makespan."""
+    off = float(np.median(exact.astype(np.float64) - predicted_rel))
+    return float(np.mean(np.abs(predicted_rel + off - exact)))
+
+
+@dataclass
+class Quantile:
+    n_orders: int
+    k: int
+    makespan: int      # the k-th smallest exact makespan
+    hits: int          # orders with makespan <= it
+    best: int
+    worst: int
+
+    @property
+    def random_expected(self) -> float:
+        """Mean exact simulations of uniform sampling (with replacement) to the first hit."""
+        return self.n_orders / self.hits
+
+
+def top_quantile(model, kernels, frac: float = 0.01, device="cuda:0") -> Quantile:
+    """Exact best-`frac` threshold of one set by full enumeration on the GPU."""
+    torch = _torch()
+    n = len(kernels)
+    N = math.factorial(n)
+    ms = torch.empty(N, dtype=torch.int64, device=device)
+    st = torch.empty(8, dtype=torch.int64, device=device)
+    ko_simulate_batch(model, kernels, [0, n], OrderSpec.all(), makespans=ms, stats=st)
+    k = max(1, math.ceil(frac * N))
+    q, hits = ko_kth_smallest_i64(ms, k, with_count=True)
+    from . import stats_records
+    rec = stats_records(st)[0]
+    out = Quantile(n_orders=N, k=k, makespan=q, hits=hits, best=int(rec["min_makespan"]),
+                   worst=int(rec["max_makespan"]))
+    del ms
+    return out
+
+
+@dataclass
+class SearchResult:
+    sample_index: np.ndarray   # sample numbers of the ranked orders (SAMPLED-mode counters)
+    orders: np.ndarray         # [K, n] uint8, best predicted first
+    predicted: np.ndarray      # cycles above the set's best (see predict)
+    exact: np.ndarray          # int64 cycles, exact re-simulation
+    n_scored: int
+
+
+def score_and_rerank(sur: "nn.Surrogate", table: SetTable, set_index: int, *, n_score: int, top_k: int,
+                     seed: int, batch: int = 1 << 18, device="cuda:0") -> SearchResult:
+    """Score `n_score` sampled orders, keep the `top_k` best predicted, re-simulate them exactly."""
+    torch = _torch()
+    n = table.n
+    tab = sur.layer1_table(table.feat[set_index])
+    scores = torch.empty(n_score, dtype=torch.float32, device=device)
+    pos = torch.empty(min(batch, n_score) * n, dtype=torch.uint8, device=device)
+    for b0 in range(0, n_score, batch):
+        c = min(batch, n_score - b0)
+        ko_sample_orders(n, set_index, seed, c, first=b0, positions=pos[:c * n])
+        sur.forward_positions(tab, pos[:c * n].view(c, n), y=scores[b0:b0 + c])
+    idx, val = ko_topk_f32(scores, top_k)
+    orders = torch.empty(top_k * n, dtype=torch.uint8, device=device)
+    ko_sample_orders(n, set_index, seed, top_k, indices=idx, orders=orders)
+    ms = torch.empty(top_k, dtype=torch.int64, device=device)
+    kern = table.sets[set_index]
+    ko_simulate_batch(table.model, kern, [0, n], OrderSpec.explicit(orders, [top_k]), makespans=ms)
+    ko_sync()
+    lb = float(table.lb_host[set_index])
+    return SearchResult(sample_index=idx.cpu().numpy(), orders=orders.cpu().numpy().reshape(top_k, n),
+                        predicted=val.cpu().numpy().astype(np.float64) * lb,
+                        exact=ms.cpu().numpy(), n_scored=n_score)
+
+
+def beam_search(sur: "nn.Surrogate", table: SetTable, set_index: int, *, width: int = 256,
+                device="cuda:0") -> SearchResult:
+    """Grow orders position by position, keeping the `width` best-scored
+    prefixes (kernels not yet placed are "unplaced"); re-simulate the final
+    complete orders exactly."""
+    torch = _torch()
+    n = table.n
+    tab = sur.layer1_table(table.feat[set_index])
+    beams = np.zeros((1, 0), dtype=np.int64)  # prefixes of kernel indices
+    n_scored = 0
+    val = None
+    for depth in range(n):
+        used = np.zeros((len(beams), n), dtype=bool)
+        if depth:
+            np.put_along_axis(used, beams, True, axis=1)
+        parent, nxt = np.nonzero(~used)
+        cand = np.concatenate([beams[parent], nxt[:, None]], axis=1)
+        pos = np.full((len(cand), n), nn.UNPLACED, dtype=np.uint8)
+        np.put_along_axis(pos, cand, np.arange(depth + 1, dtype=np.uint8)[None, :].repeat(len(cand), 0),
+                          axis=1)
+        scores = sur.forward_positions(tab, torch.from_numpy(pos).to(device))
+        n_scored += len(cand)
+        keep = min(width, len(cand))
+        idx, v = ko_topk_f32(scores, keep)
+        beams = cand[idx.cpu().numpy()]
+        val = v
+    K = len(beams)
+    orders = torch.from_numpy(beams.astype(np.uint8).ravel().copy()).to(device)
+    ms = torch.empty(K, dtype=torch.int64, device=device)
+    ko_simulate_batch(table.model, table.sets[set_index], [0, n], OrderSpec.explicit(orders, [K]),
+                      makespans=ms)
+    ko_sync()
+    lb = float(table.lb_host[set_index])
+    return SearchResult(sample_index=np.full(K, -1), orders=beams.astype(np.uint8),
+                        predicted=val.cpu().numpy().astype(np.float64) * lb, exact=ms.cpu().numpy(),
+                        n_scored=n_scored)
+
+
+def sims_to_first_hit(exact_ranked: np.ndarray, threshold: int, random_expected: float) -> float:
+    """Exact simulations the ranked list needs to reach makespan <= threshold;
+    after an exhausted list the search continues with random sampling."""
+    hit = np.flatnonzero(exact_ranked <= threshold)
+    if len(hit):
+        return float(hit[0] + 1)
+    return float(len(exact_ranked)) + random_expected
+
+
+# ------------------------------------------------------------------ report
+
+def _init_params(seed: int) -> np.ndarray:
+    """He-style initial weights (zero biases) in the flat parameter order."""
+    rng = np.random.default_rng(seed)
+    shapes = ((256, 32), (256,), (256, 256), (256,), (256, 256), (256,), (256,), (1,))
+    parts = []
+    for i, shape in enumerate(shapes):
+        if len(shape) == 1 and i != 6:
+            parts.append(np.zeros(shape))
+        else:
+            parts.append(rng.normal(0.0, 1.0 / math.sqrt(shape[-1]), size=shape))
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: int = 512,
+           per_set: int = 8192, heldout: int = 4, n_score: int = 100_000_000, top_k: int = 10_000,
+           steps: int = 8192, batch: int = 4096, lr: float = 2e-3, seed: int = 2015, out=print):
+    """Train on exact samples, then per held-out set: exact top-1% threshold by
+    full enumeration, scoring of `n_score` sampled orders, exact re-simulation
+    of the `top_k` best.  Prints one JSON line per held-out set and a summary."""
+    import json
+    import time
+
+    import synth
+
+    torch = _torch()
+    t0 = time.perf_counter()
+    tr_sets = [synth.draw_set(train_workload, s) for s in range(train_sets)]
+    table = SetTable.build(synth.WORKLOADS[train_workload].model, tr_sets)
+    data = exact_samples(table, per_set, seed=seed)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    sur = nn.Surrogate(_init_params(seed + 1))
+    t0 = time.perf_counter()
+    log = train(sur, table, data, steps=steps, batch=batch, lr=lr, warmup=min(200, steps // 10),
+                seed=seed + 2, log_every=max(1, steps // 8))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    out(json.dumps({"phase": "train", "samples": data.count, "sets": train_sets, "n": table.n,
+                    "data_s": round(t_data, 3), "train_s": round(t_train, 3), "steps": steps,
+                    "batch": batch, "loss": log}), flush=True)
+    del data
+    model = synth.WORKLOADS[heldout_workload].model
+    held = [synth.draw_set(heldout_workload, s) for s in range(heldout)]
+    htab = SetTable.build(model, held)
+    rows = []
+    for s, ks in enumerate(held):
+        t0 = time.perf_counter()
+        q = top_quantile(model, ks, 0.01)
+        torch.cuda.synchronize()
+        t_enum = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        res = score_and_rerank(sur, htab, s, n_score=n_score, top_k=top_k, seed=seed + 100 + s)
+        t_score = time.perf_counter() - t0
+        sims = sims_to_first_hit(res.exact, q.makespan, q.random_expected)
+        row = {"phase": "heldout", "set": s, "n_orders": q.n_orders, "top1pct_makespan": q.makespan,
+               "hits": q.hits, "best": q.best, "worst": q.worst,
+               "random_sims_expected": q.random_expected, "surrogate_sims": sims,
+               "speedup": q.random_expected / sims,
+               "recall_at_1pct": float(np.mean(res.exact <= q.makespan)),
+               "mae_cycles_offset_calibrated": calibrated_mae(res.predicted, res.exact),
+               "best_of_topk": int(res.exact.min()), "enum_s": round(t_enum, 3),
+               "score_rerank_s": round(t_score, 3), "n_score": n_score, "top_k": top_k}
+        rows.append(row)
+        out(json.dumps(row), flush=True)
+    sp = np.array([r["speedup"] for r in rows])
+    out(json.dumps({"phase": "summary", "heldout_sets": heldout,
+                    "speedup_geomean": float(np.exp(np.mean(np.log(sp)))),
+                    "speedup_min": float(sp.min()), "speedup_max": float(sp.max()),
+                    "recall_at_1pct_mean": float(np.mean([r["recall_at_1pct"] for r in rows])),
+                    "mae_cycles_offset_calibrated_mean":
+                        float(np.mean([r["mae_cycles_offset_calibrated"] for r in rows]))}), flush=True)
+    return rows
+
+
+if __name__ == "__main__":
+    import argparse
+    import os
+    import sys
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    ap = argparse.ArgumentParser(description="surrogate-guided search report (one GPU)")
+    ap.add_argument("--train-sets", type=int, default=512)
+    ap.add_argument("--per-set", type=int, default=8192)
+    ap.add_argument("--heldout", type=int, default=4)
+    ap.add_argument("--n-score", type=int, default=100_000_000)
+    ap.add_argument("--top-k", type=int, default=10_000)
+    ap.add_argument("--steps", type=int, default=8192)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--train-workload", type=int, default=3)
+    ap.add_argument("--heldout-workload", type=int, default=13)
+    a = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    report(train_workload=a.train_workload, heldout_workload=a.heldout_workload, train_sets=a.train_sets,
+           per_set=a.per_set, heldout=a.heldout, n_score=a.n_score, top_k=a.top_k, steps=a.steps,
+           batch=a.batch, lr=a.lr)

@@ -102,6 +102,11 @@ WORKLOADS = {
     4: Workload(4, "search-n16-mi355x", MI355X_MODEL, 1024, 16, 16, 256, 8192),
     14: Workload(4, "search-train-n16-mi355x", MI355X_MODEL, 512, 16, 16, 256, 8192,
                  set_base=100000),
+    # a small surrogate workload (n=8, 40,320 orders per set: exact quantiles
+    # by full enumeration are cheap), for tests of the learned search
+    5: Workload(5, "surrogate-train-n8-mi355x", MI355X_MODEL, 256, 8, 8, 64, 2048),
+    15: Workload(5, "surrogate-heldout-n8-mi355x", MI355X_MODEL, 16, 8, 8, 64, 2048,
+                 set_base=100000),
 }
 
 

@@ -177,3 +177,28 @@ def test_float_quotient_rule_is_exact():
             qc = np.minimum(q, clamp)
             qc = qc - (qc * u > fr)
             assert np.array_equal(qc, np.minimum(fr // u, clamp)), (u, clamp)
+
+
+def test_sampling_and_selection_reject_bad_arguments_before_device_work():
+    lib = ko.library_handle()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation first
+    assert lib.ko_sample_orders(0, 0, 1, 0, None, 4, fake, None, None) == ko.KO_EINVAL
+    assert lib.ko_sample_orders(21, 0, 1, 0, None, 4, fake, None, None) == ko.KO_EINVAL
+    assert lib.ko_sample_orders(5, -1, 1, 0, None, 4, fake, None, None) == ko.KO_EINVAL
+    assert lib.ko_sample_orders(5, 1 << 24, 1, 0, None, 4, fake, None, None) == ko.KO_EINVAL
+    assert lib.ko_sample_orders(5, 0, 1, 0, None, 4, None, None, None) == ko.KO_EINVAL
+    assert lib.ko_sample_orders(5, 0, 1, (1 << 40) - 3, None, 4, fake, None, None) == ko.KO_ERANGE
+    assert lib.ko_sample_orders(5, 0, 1, 0, None, (1 << 40) + 1, fake, None, None) == ko.KO_ERANGE
+    assert lib.ko_sample_orders(5, 0, 1, 0, None, 0, fake, None, None) == ko.KO_OK
+    assert lib.ko_topk_f32(None, 10, 1, fake, None, None) == ko.KO_EINVAL
+    assert lib.ko_topk_f32(fake, 10, 0, fake, None, None) == ko.KO_EINVAL
+    assert lib.ko_topk_f32(fake, 10, 11, fake, None, None) == ko.KO_EINVAL
+    assert lib.ko_topk_f32(fake, 0, 1, fake, None, None) == ko.KO_EINVAL
+    assert lib.ko_topk_f32(fake, 1 << 32, 5, fake, None, None) == ko.KO_EINVAL
+    assert lib.ko_topk_f32(fake, 100000, 16385, fake, None, None) == ko.KO_EINVAL
+    assert lib.ko_topk_f32(fake, 10, 1, None, None, None) == ko.KO_EINVAL
+    out = ctypes.c_int64()
+    assert lib.ko_kth_smallest_i64(fake, 10, 0, ctypes.byref(out), None, None) == ko.KO_EINVAL
+    assert lib.ko_kth_smallest_i64(fake, 10, 11, ctypes.byref(out), None, None) == ko.KO_EINVAL
+    assert lib.ko_kth_smallest_i64(None, 10, 1, ctypes.byref(out), None, None) == ko.KO_EINVAL
+    assert lib.ko_kth_smallest_i64(fake, 10, 1, None, None, None) == ko.KO_EINVAL

@@ -144,3 +144,26 @@ def test_training_reduces_loss():
     last = float(loss.cpu()[0])
     say(f"training loss {first:.4f} -> {last:.4f}")
     assert last < first / 10
+
+
+@pytest.mark.parametrize("B,n", [(1, 1), (77, 6), (513, 12), (64, 16), (300, 9)])
+def test_forward_positions_matches_oracle_and_token_path(B, n):
+    """Scoring path: the layer-1 table equals the oracle's per-token first
+    layer, and y from positions matches the oracle and the token path."""
+    rng, flat, feat, pos, X = make_case(50 + B + n, B, n)
+    say(f"forward from positions B={B} n={n}")
+    model = nn.Surrogate(flat)
+    table = model.layer1_table(torch.from_numpy(feat[0]).to("cuda:0")).cpu().numpy().astype(np.float64)
+    p64 = mlp.unflatten(flat.astype(np.float64))
+    Xtab = np.zeros((n, mlp.N_POS, mlp.D_IN))
+    Xtab[:, :, :mlp.N_FEAT] = feat[0][:, None, :].astype(np.float64)
+    for q in range(mlp.N_POS):
+        Xtab[:, q, mlp.N_FEAT + q] = 1.0
+    want = np.maximum(mlp.bf16(Xtab) @ mlp.bf16(p64["W1"]).T + p64["b1"], 0.0)
+    assert np.abs(table - want).max() <= 1e-5 * (1.0 + np.abs(want).max())
+    y = model.forward_positions(torch.from_numpy(table.astype(np.float32)).to("cuda:0"),
+                                torch.from_numpy(pos).to("cuda:0")).cpu().numpy().astype(np.float64)
+    yo, _ = mlp.forward(p64, X)
+    assert np.abs(y - yo).max() <= 1e-3 * (1.0 + np.abs(yo).max())
+    y_tok = model.forward(device_tokens(model, feat, pos)).cpu().numpy().astype(np.float64)
+    assert np.abs(y - y_tok).max() <= 1e-3 * (1.0 + np.abs(y_tok).max())
