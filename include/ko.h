@@ -213,6 +213,66 @@ int ko_sync(void *hip_stream);
 /* ko_shutdown — release the per-device workspaces.  Later calls recreate them. */
 int ko_shutdown(void);
 
+/* ------------------------------------------------------------------ plans
+ * A plan is a batch (model, kernel sets, order spec) prepared once: kernel
+ * records derived, work decomposed and tables uploaded to the device.
+ * Launching it only enqueues kernels on a stream (no allocation, copy, memset
+ * or synchronisation), so a launch can be captured in a HIP graph and
+ * replayed: the way many kernel sets of uneven size are evaluated in one
+ * persistent launch fed by a device work queue, again and again. */
+
+typedef struct ko_plan ko_plan;
+typedef struct ko_graph ko_graph;
+
+/* Launch configuration (16 bytes); zero fields take the defaults. */
+typedef struct ko_launch_config {
+    int32_t chunk_log2;  /* orders per work item = 2^chunk_log2 (1..20); 0 = automatic */
+    int32_t wg_per_cu;   /* persistent workgroups (4 waves each) per CU (1..64); 0 = 8 */
+    int32_t reserved[2];
+} ko_launch_config;
+
+/* ko_plan_create — prepare a batch as ko_simulate_batch takes it (same
+ * arguments and errors); config may be NULL.  The plan belongs to the current
+ * device.  In EXPLICIT mode spec->orders_dev is read at every launch and must
+ * stay valid for the life of the plan.  Synchronous. */
+int ko_plan_create(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *set_offsets,
+                   int32_t n_sets, const ko_order_spec *spec, const ko_launch_config *config,
+                   ko_plan **out);
+
+/* ko_plan_info — orders in the batch, work items, orders per item and
+ * workgroups of the persistent grid (any output may be NULL). */
+int ko_plan_info(const ko_plan *plan, uint64_t *total_orders, uint64_t *work_items, uint64_t *chunk,
+                 int32_t *grid);
+
+/* ko_plan_launch — enqueue one evaluation of the plan on hip_stream; outputs
+ * as in ko_simulate_batch.  Kernel launches only: capturable.  Launches of one
+ * plan share its work queue and partials, so they must not overlap in time
+ * (issue them on one stream).  The device status of the launch is read by
+ * ko_plan_status. */
+int ko_plan_launch(ko_plan *plan, const int64_t *ref_makespan_dev, int64_t *makespans_dev,
+                   ko_set_stats *stats_dev, uint64_t *hist_dev, int32_t n_bins, void *hip_stream);
+
+/* ko_plan_status — wait for hip_stream, then report the device status of the
+ * plan's last launch (KO_EHIP for a malformed explicit order). */
+int ko_plan_status(ko_plan *plan, void *hip_stream);
+
+/* ko_plan_destroy — wait for the device, free the plan (NULL is a no-op). */
+int ko_plan_destroy(ko_plan *plan);
+
+/* ko_graph_capture — capture one ko_plan_launch with these outputs on
+ * hip_stream (a created stream, not the null stream) into an instantiated
+ * HIP graph.  The graph holds the plan's and the outputs' addresses: they
+ * must outlive it.  Replays share the plan's work queue with its launches. */
+int ko_graph_capture(ko_plan *plan, const int64_t *ref_makespan_dev, int64_t *makespans_dev,
+                     ko_set_stats *stats_dev, uint64_t *hist_dev, int32_t n_bins, void *hip_stream,
+                     ko_graph **out);
+
+/* ko_graph_launch — replay a captured evaluation on hip_stream. */
+int ko_graph_launch(ko_graph *graph, void *hip_stream);
+
+/* ko_graph_destroy — wait for the device, free the graph (NULL is a no-op). */
+int ko_graph_destroy(ko_graph *graph);
+
 /* ko_sample_orders — the launch orders that ko_simulate_batch evaluates in
  * KO_ORDERS_SAMPLED mode for the set at batch index set_index (seed as in
  * ko_order_spec.seed): sample i is the order of rank

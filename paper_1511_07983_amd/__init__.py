@@ -39,7 +39,9 @@ KO_HEUR_PER_BLOCK = 1
 KO_HEUR_FULL_SORT = 2
 
 EXPORTED = ("ko_heuristic_order", "ko_count_orders", "ko_simulate_batch", "ko_rank_percentile",
-            "ko_sync", "ko_shutdown", "ko_sample_orders", "ko_topk_f32", "ko_kth_smallest_i64",
+            "ko_sync", "ko_shutdown", "ko_plan_create", "ko_plan_info", "ko_plan_launch", "ko_plan_status",
+            "ko_plan_destroy", "ko_graph_capture", "ko_graph_launch", "ko_graph_destroy",
+            "ko_sample_orders", "ko_topk_f32", "ko_kth_smallest_i64",
             "ko_set_kernel_timing", "ko_last_kernel_ms", "ko_last_error")
 
 
@@ -70,6 +72,11 @@ class KoRankResult(ctypes.Structure):
                 ("n_equal", ctypes.c_uint64), ("n_greater", ctypes.c_uint64),
                 ("n_total", ctypes.c_uint64), ("pct_inclusive", ctypes.c_double),
                 ("pct_strict", ctypes.c_double), ("pct_mid", ctypes.c_double)]
+
+
+class KoLaunchConfig(ctypes.Structure):
+    _fields_ = [("chunk_log2", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class KoOrderSpec(ctypes.Structure):
@@ -120,6 +127,20 @@ def _L():
         lib.ko_sync.restype = ctypes.c_int
         lib.ko_shutdown.argtypes = []
         lib.ko_shutdown.restype = ctypes.c_int
+        vp = ctypes.c_void_p
+        lib.ko_plan_create.argtypes = [ctypes.POINTER(KoGpuModel), vp, _i32p, ctypes.c_int32,
+                                        ctypes.POINTER(KoOrderSpec), ctypes.POINTER(KoLaunchConfig),
+                                        ctypes.POINTER(vp)]
+        lib.ko_plan_info.argtypes = [vp, _u64p, _u64p, _u64p, _i32p]
+        lib.ko_plan_launch.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, vp]
+        lib.ko_plan_status.argtypes = [vp, vp]
+        lib.ko_plan_destroy.argtypes = [vp]
+        lib.ko_graph_capture.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, vp, ctypes.POINTER(vp)]
+        lib.ko_graph_launch.argtypes = [vp, vp]
+        lib.ko_graph_destroy.argtypes = [vp]
+        for f in ("ko_plan_create", "ko_plan_info", "ko_plan_launch", "ko_plan_status", "ko_plan_destroy",
+                  "ko_graph_capture", "ko_graph_launch", "ko_graph_destroy"):
+            getattr(lib, f).restype = ctypes.c_int
         lib.ko_sample_orders.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64,
                                           ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p]
@@ -320,6 +341,85 @@ def ko_rank_percentile(gpu, kernels, order, n_samples: int = 0, seed: int = 0, s
                                    o.ctypes.data_as(_i32p), int(n_samples), int(seed) & ((1 << 64) - 1),
                                    ctypes.byref(res), _stream_handle(stream)))
     return {f: getattr(res, f) for f, _ in KoRankResult._fields_}
+
+
+def _outputs(ref_makespan, makespans, stats, hist, n_bins, total, n_sets):
+    import torch
+    ref_p = _dev_ptr(ref_makespan, torch.int64, n_sets, "ref_makespan")
+    ms_p = _dev_ptr(makespans, torch.int64, total, "makespans")
+    st_p = _dev_ptr(stats, torch.int64, 8 * n_sets, "stats")
+    h_p = _dev_ptr(hist, torch.int64, n_sets * max(n_bins, 1), "hist") if hist is not None else None
+    return ref_p, ms_p, st_p, h_p
+
+
+class Plan:
+    """A batch prepared once (ko_plan_create) and launched many times."""
+
+    def __init__(self, gpu, kernels, set_offsets, spec: "OrderSpec", chunk_log2: int = 0, wg_per_cu: int = 0):
+        g = gpu_model(gpu)
+        k = kernel_array(kernels)
+        off = np.ascontiguousarray(set_offsets, dtype=np.int32)
+        self.n_sets = len(off) - 1
+        self._spec = spec.c_struct()  # keeps the rank table alive during create
+        cfg = KoLaunchConfig(int(chunk_log2), int(wg_per_cu))
+        h = ctypes.c_void_p()
+        _check(_L().ko_plan_create(ctypes.byref(g), k.ctypes.data if len(k) else None, off.ctypes.data_as(_i32p),
+                                   self.n_sets, ctypes.byref(self._spec), ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = spec  # an explicit order tensor must outlive the plan
+        tot, items, chunk = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        grid = ctypes.c_int32()
+        _check(_L().ko_plan_info(h, ctypes.byref(tot), ctypes.byref(items), ctypes.byref(chunk),
+                                 ctypes.byref(grid)))
+        self.total_orders, self.work_items, self.chunk, self.grid = tot.value, items.value, chunk.value, grid.value
+
+    def launch(self, *, ref_makespan=None, makespans=None, stats=None, hist=None, n_bins: int = 0, stream=None):
+        p = _outputs(ref_makespan, makespans, stats, hist, n_bins, self.total_orders, self.n_sets)
+        _check(_L().ko_plan_launch(self._h, *p, int(n_bins), _stream_handle(stream)))
+
+    def status(self, stream=None):
+        _check(_L().ko_plan_status(self._h, _stream_handle(stream)))
+
+    def capture(self, *, stream, ref_makespan=None, makespans=None, stats=None, hist=None, n_bins: int = 0):
+        """A HIP graph of one launch with these outputs (stream: a created torch stream)."""
+        p = _outputs(ref_makespan, makespans, stats, hist, n_bins, self.total_orders, self.n_sets)
+        g = ctypes.c_void_p()
+        _check(_L().ko_graph_capture(self._h, *p, int(n_bins), _stream_handle(stream), ctypes.byref(g)))
+        return Graph(g, self, (ref_makespan, makespans, stats, hist))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _L().ko_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """An instantiated HIP graph of one plan launch (ko_graph_capture)."""
+
+    def __init__(self, handle, plan, outputs):
+        self._h = handle
+        self._plan = plan        # the plan and the outputs must outlive the graph
+        self._outputs = outputs
+
+    def launch(self, stream=None):
+        _check(_L().ko_graph_launch(self._h, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _L().ko_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ko_sample_orders(n: int, set_index: int, seed: int, count: int, *, first: int = 0, indices=None,

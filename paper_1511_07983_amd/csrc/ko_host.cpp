@@ -569,6 +569,8 @@ struct BatchPlan {
     std::vector<uint64_t> block_base;
     uint64_t total = 0, n_items = 0, chunk = 0, hist_blocks = 0;
     uint32_t max_n = 0;
+    int slots = 1;        // CU slots per lane
+    int grid = 1;         // workgroups of the simulate kernel
 };
 
 constexpr uint64_t kHistPerBlock = 1 << 16;
@@ -611,49 +613,49 @@ int radix_pass(Workspace &w, hipStream_t stream, uint32_t shift, uint64_t *prefi
                 (unsigned long long)*rem);
 }
 
-int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernels,
-                  const int32_t *set_offsets, int32_t n_sets, const ko_order_spec *spec,
-                  const int64_t *ref_dev, int64_t *makespans_dev, ko_set_stats *stats_dev,
-                  uint64_t *hist_dev, int32_t n_bins, hipStream_t stream)
+int slots_for(int n_cu)
 {
-    int rc = validate_batch(gpu, kernels, set_offsets, n_sets, spec, makespans_dev, stats_dev,
-                            hist_dev, n_bins);
-    if (rc)
-        return rc;
+    const int s = (n_cu + ko::kWave - 1) / ko::kWave;
+    return s == 3 ? 4 : s;
+}
+
+// Host half of a batch: derived kernel records, the set table and the work
+// decomposition (chunks of consecutive orders per work item, persistent grid
+// of wg_per_cu workgroups per CU).  chunk_req = 0 picks the chunk: enough
+// items to balance the persistent waves, few enough to keep partials small.
+int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *set_offsets,
+              int32_t n_sets, const ko_order_spec *spec, int cu_count, uint64_t chunk_req, int wg_per_cu,
+              BatchPlan *plan)
+{
     std::vector<uint64_t> per_set;
-    BatchPlan plan;
-    rc = count_orders(set_offsets, n_sets, spec, &per_set, &plan.total);
+    int rc = count_orders(set_offsets, n_sets, spec, &per_set, &plan->total);
     if (rc)
         return rc;
-    plan.krec.reserve(set_offsets[n_sets]);
+    plan->krec.reserve(set_offsets[n_sets]);
     for (int32_t s = 0; s < n_sets; s++) {
         const int32_t n = set_offsets[s + 1] - set_offsets[s];
-        rc = derive_set(*gpu, kernels + set_offsets[s], n, set_offsets[s], &plan.krec);
+        rc = derive_set(*gpu, kernels + set_offsets[s], n, set_offsets[s], &plan->krec);
         if (rc)
             return rc;
-        plan.max_n = std::max<uint32_t>(plan.max_n, (uint32_t)n);
+        plan->max_n = std::max<uint32_t>(plan->max_n, (uint32_t)n);
     }
-    rc = check_status(w, false);
-    if (rc)
-        return rc;
-
-    // work decomposition: chunks of consecutive orders, enough of them to
-    // balance the persistent waves, few enough to keep the partials small
-    const int slots = (gpu->n_cu + ko::kWave - 1) / ko::kWave == 3 ? 4
-                                                                   : (gpu->n_cu + ko::kWave - 1) / ko::kWave;
-    const int grid = std::max(1, w.cu_count * 8);
-    const uint64_t waves = (uint64_t)grid * 4;
-    uint64_t chunk = pow2_at_least(std::max<uint64_t>(1, plan.total / (waves * 8)));
-    chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, 16), 8192);
+    plan->slots = slots_for(gpu->n_cu);
+    plan->grid = std::max(1, cu_count * wg_per_cu);
+    const uint64_t waves = (uint64_t)plan->grid * 4;
+    uint64_t chunk = chunk_req;
+    if (chunk == 0) {
+        chunk = pow2_at_least(std::max<uint64_t>(1, plan->total / (waves * 8)));
+        chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, 16), 8192);
+    }
     const uint64_t max_items = uint64_t(1) << 22;
-    if (plan.total / chunk > max_items)
-        chunk = pow2_at_least((plan.total + max_items - 1) / max_items);
-    plan.chunk = chunk;
+    if (plan->total / chunk > max_items)
+        chunk = pow2_at_least((plan->total + max_items - 1) / max_items);
+    plan->chunk = chunk;
     uint64_t out_base = 0, item_base = 0, list_base = 0, hist_base = 0;
-    plan.sets.resize(n_sets);
-    plan.block_base.resize(n_sets + 1);
+    plan->sets.resize(n_sets);
+    plan->block_base.resize(n_sets + 1);
     for (int32_t s = 0; s < n_sets; s++) {
-        ko::SetRec &r = plan.sets[s];
+        ko::SetRec &r = plan->sets[s];
         const int32_t n = set_offsets[s + 1] - set_offsets[s];
         r.n = (uint32_t)n;
         r.kbase = (uint32_t)set_offsets[s];
@@ -665,12 +667,112 @@ int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernel
         out_base += per_set[s];
         item_base += (per_set[s] + chunk - 1) / chunk;
         list_base += per_set[s] * (uint64_t)n;
-        plan.block_base[s] = hist_base;
+        plan->block_base[s] = hist_base;
         hist_base += (per_set[s] + kHistPerBlock - 1) / kHistPerBlock;
     }
-    plan.block_base[n_sets] = hist_base;
-    plan.n_items = item_base;
-    plan.hist_blocks = hist_base;
+    plan->block_base[n_sets] = hist_base;
+    plan->n_items = item_base;
+    plan->hist_blocks = hist_base;
+    return KO_OK;
+}
+
+// Device tables a batch runs on.
+struct DevTables {
+    const ko::KernelRec *krec;
+    const ko::SetRec *sets;
+    const uint64_t *block_base;
+    ko::Partial *partials;
+    unsigned long long *counter;  // [0] item cursor, [1] status word
+};
+
+// Enqueue the device work of a batch on `stream`: cursor (and, when asked,
+// status) reset, simulation, per-set reduction, histogram.  Kernel launches
+// only (no copies, allocations, memsets or synchronisation), so a caller can
+// capture it in a HIP graph.
+int enqueue_batch(const DevTables &t, const BatchPlan &p, const ko_gpu_model &gpu, int32_t n_sets,
+                  int32_t mode, uint64_t seed, const uint8_t *orders, bool reset_status, const int64_t *ref_dev,
+                  int64_t *makespans_dev, ko_set_stats *stats_dev, uint64_t *hist_dev, int32_t n_bins,
+                  hipStream_t stream, hipEvent_t sim_begin, hipEvent_t sim_end)
+{
+    int e = ko::launch_zero_u64((uint64_t *)t.counter, reset_status ? 2 : 1, stream);
+    if (e)
+        return hip_fail((hipError_t)e, "zero counters");
+    if (p.n_items > 0) {
+        ko::SimArgs a;
+        a.krec = t.krec;
+        a.sets = t.sets;
+        a.n_sets = n_sets;
+        a.mode = mode;
+        a.n_items = p.n_items;
+        a.chunk = p.chunk;
+        a.seed = seed;
+        a.orders = orders;
+        a.ref = ref_dev;
+        a.makespans = makespans_dev;
+        a.partials = t.partials;
+        a.item_counter = t.counter;
+        a.status = (uint32_t *)(t.counter + 1);
+        a.n_cu = (uint32_t)gpu.n_cu;
+        a.cap_reg = (uint32_t)gpu.reg_cu;
+        a.cap_lds = (uint32_t)gpu.lds_cu;
+        a.cap_wave = (uint32_t)gpu.wave_cu;
+        a.cap_blk = (uint32_t)gpu.blk_cu;
+        const int g = (int)std::min<uint64_t>((uint64_t)p.grid, (p.n_items + 3) / 4);
+        if (sim_begin)
+            KO_HIP(hipEventRecord(sim_begin, stream), "hipEventRecord");
+        e = ko::launch_simulate(a, p.slots, p.max_n, g, stream);
+        if (e)
+            return hip_fail((hipError_t)e, "simulate kernel launch");
+        if (sim_end)
+            KO_HIP(hipEventRecord(sim_end, stream), "hipEventRecord");
+    }
+    if (stats_dev) {
+        ko::ReduceArgs r;
+        r.sets = t.sets;
+        r.n_sets = n_sets;
+        r.chunk = p.chunk;
+        r.partials = t.partials;
+        r.stats = stats_dev;
+        e = ko::launch_reduce(r, stream);
+        if (e)
+            return hip_fail((hipError_t)e, "reduce kernel launch");
+    }
+    if (hist_dev) {
+        e = ko::launch_zero_u64(hist_dev, (uint64_t)n_sets * (uint64_t)n_bins, stream);
+        if (e)
+            return hip_fail((hipError_t)e, "zero histogram");
+        ko::HistArgs h;
+        h.sets = t.sets;
+        h.n_sets = n_sets;
+        h.makespans = makespans_dev;
+        h.stats = stats_dev;
+        h.hist = hist_dev;
+        h.n_bins = n_bins;
+        h.per_block = kHistPerBlock;
+        h.block_base = t.block_base;
+        e = ko::launch_hist(h, p.hist_blocks, stream);
+        if (e)
+            return hip_fail((hipError_t)e, "histogram kernel launch");
+    }
+    return KO_OK;
+}
+
+int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernels,
+                  const int32_t *set_offsets, int32_t n_sets, const ko_order_spec *spec,
+                  const int64_t *ref_dev, int64_t *makespans_dev, ko_set_stats *stats_dev,
+                  uint64_t *hist_dev, int32_t n_bins, hipStream_t stream)
+{
+    int rc = validate_batch(gpu, kernels, set_offsets, n_sets, spec, makespans_dev, stats_dev,
+                            hist_dev, n_bins);
+    if (rc)
+        return rc;
+    BatchPlan plan;
+    rc = make_plan(gpu, kernels, set_offsets, n_sets, spec, w.cu_count, 0, 8, &plan);
+    if (rc)
+        return rc;
+    rc = check_status(w, false);
+    if (rc)
+        return rc;
 
     // device buffers
     const size_t kbytes = plan.krec.size() * sizeof(ko::KernelRec);
@@ -702,75 +804,80 @@ int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernel
         return rc;
     KO_HIP(hipEventRecord(w.staged, stream), "hipEventRecord");
 
-    // the item counter restarts every call; the status word only once reported
-    int e = ko::launch_zero_u64((uint64_t *)w.counter, w.clear_status ? 2 : 1, stream);
+    // the status word is cleared only once a reported status has been seen
+    DevTables t{w.krec, w.sets, w.block_base, w.partials, w.counter};
+    const bool timing = w.timing && plan.n_items > 0;
+    rc = enqueue_batch(t, plan, *gpu, n_sets, spec->mode, spec->seed, spec->orders_dev, w.clear_status,
+                       ref_dev, makespans_dev, stats_dev, hist_dev, n_bins, stream,
+                       timing ? w.sim_begin : nullptr, timing ? w.sim_end : nullptr);
     w.clear_status = false;
-    if (e)
-        return hip_fail((hipError_t)e, "zero counters");
-    if (plan.n_items > 0) {
-        ko::SimArgs a;
-        a.krec = w.krec;
-        a.sets = w.sets;
-        a.n_sets = n_sets;
-        a.mode = spec->mode;
-        a.n_items = plan.n_items;
-        a.chunk = plan.chunk;
-        a.seed = spec->seed;
-        a.orders = spec->orders_dev;
-        a.ref = ref_dev;
-        a.makespans = makespans_dev;
-        a.partials = w.partials;
-        a.item_counter = w.counter;
-        a.status = (uint32_t *)(w.counter + 1);
-        a.n_cu = (uint32_t)gpu->n_cu;
-        a.cap_reg = (uint32_t)gpu->reg_cu;
-        a.cap_lds = (uint32_t)gpu->lds_cu;
-        a.cap_wave = (uint32_t)gpu->wave_cu;
-        a.cap_blk = (uint32_t)gpu->blk_cu;
-        const int g = (int)std::min<uint64_t>((uint64_t)grid, (plan.n_items + 3) / 4);
-        if (w.timing)
-            KO_HIP(hipEventRecord(w.sim_begin, stream), "hipEventRecord");
-        e = ko::launch_simulate(a, slots, plan.max_n, g, stream);
-        if (e)
-            return hip_fail((hipError_t)e, "simulate kernel launch");
-        if (w.timing) {
-            KO_HIP(hipEventRecord(w.sim_end, stream), "hipEventRecord");
-            w.timed = true;
-        }
-    }
-    if (stats_dev) {
-        ko::ReduceArgs r;
-        r.sets = w.sets;
-        r.n_sets = n_sets;
-        r.chunk = plan.chunk;
-        r.partials = w.partials;
-        r.stats = stats_dev;
-        e = ko::launch_reduce(r, stream);
-        if (e)
-            return hip_fail((hipError_t)e, "reduce kernel launch");
-    }
-    if (hist_dev) {
-        e = ko::launch_zero_u64(hist_dev, (uint64_t)n_sets * (uint64_t)n_bins, stream);
-        if (e)
-            return hip_fail((hipError_t)e, "zero histogram");
-        ko::HistArgs h;
-        h.sets = w.sets;
-        h.n_sets = n_sets;
-        h.makespans = makespans_dev;
-        h.stats = stats_dev;
-        h.hist = hist_dev;
-        h.n_bins = n_bins;
-        h.per_block = kHistPerBlock;
-        h.block_base = w.block_base;
-        e = ko::launch_hist(h, plan.hist_blocks, stream);
-        if (e)
-            return hip_fail((hipError_t)e, "histogram kernel launch");
-    }
+    if (rc)
+        return rc;
+    if (timing)
+        w.timed = true;
     KO_HIP(hipMemcpyAsync(w.status_host, (const void *)(w.counter + 1), sizeof(uint32_t),
                           hipMemcpyDeviceToHost, stream),
            "hipMemcpyAsync");
     KO_HIP(hipEventRecord(w.done, stream), "hipEventRecord");
     w.pending_status = true;
+    return KO_OK;
+}
+
+// Output checks shared by the immediate and the planned path.
+int check_outputs(const int64_t *makespans_dev, const ko_set_stats *stats_dev, const uint64_t *hist_dev,
+                  int32_t n_bins)
+{
+    if (hist_dev) {
+        if (!makespans_dev || !stats_dev)
+            return fail(KO_EINVAL, "a histogram needs makespans_dev and stats_dev");
+        if (n_bins < 1 || n_bins > 65536)
+            return fail(KO_EINVAL, "n_bins %d outside 1..65536", n_bins);
+    }
+    return KO_OK;
+}
+
+}  // namespace
+
+// A batch prepared once and launched many times (ko_plan_*).
+struct ko_plan {
+    int device = -1;
+    ko_gpu_model gpu{};
+    int32_t n_sets = 0;
+    int32_t mode = 0;
+    uint64_t seed = 0;
+    const uint8_t *orders = nullptr;
+    BatchPlan plan;
+    ko::KernelRec *krec = nullptr;
+    ko::SetRec *sets = nullptr;
+    uint64_t *block_base = nullptr;
+    ko::Partial *partials = nullptr;
+    unsigned long long *counter = nullptr;
+};
+
+struct ko_graph {
+    int device = -1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void free_plan(ko_plan *p)
+{
+    (void)hipFree(p->krec);
+    (void)hipFree(p->sets);
+    (void)hipFree(p->block_base);
+    (void)hipFree(p->partials);
+    (void)hipFree(p->counter);
+    delete p;
+}
+
+int check_plan_device(const ko_plan *p)
+{
+    int dev = 0;
+    KO_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != p->device)
+        return fail(KO_EINVAL, "the plan was created on device %d, the current device is %d", p->device, dev);
     return KO_OK;
 }
 
@@ -838,6 +945,204 @@ int ko_simulate_batch(const ko_gpu_model *gpu, const ko_kernel *kernels, const i
     } catch (const std::bad_alloc &) {
         return fail(KO_ENOMEM, "host allocation failed");
     }
+}
+
+int ko_plan_create(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *set_offsets,
+                   int32_t n_sets, const ko_order_spec *spec, const ko_launch_config *config,
+                   ko_plan **out)
+{
+    try {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        if (!out)
+            return fail(KO_EINVAL, "out must not be NULL");
+        *out = nullptr;
+        int rc = validate_batch(gpu, kernels, set_offsets, n_sets, spec, nullptr, nullptr, nullptr, 0);
+        if (rc)
+            return rc;
+        uint64_t chunk = 0;
+        int wg = 8;
+        if (config) {
+            if (config->chunk_log2 < 0 || config->chunk_log2 > 20)
+                return fail(KO_EINVAL, "config: chunk_log2 %d outside 0..20", config->chunk_log2);
+            if (config->wg_per_cu < 0 || config->wg_per_cu > 64)
+                return fail(KO_EINVAL, "config: wg_per_cu %d outside 0..64", config->wg_per_cu);
+            if (config->chunk_log2 > 0)
+                chunk = uint64_t(1) << config->chunk_log2;
+            if (config->wg_per_cu > 0)
+                wg = config->wg_per_cu;
+        }
+        Workspace *w = nullptr;
+        if ((rc = get_workspace(&w)))
+            return rc;
+        ko_plan *p = new ko_plan();
+        p->device = w->device;
+        p->gpu = *gpu;
+        p->n_sets = n_sets;
+        p->mode = spec->mode;
+        p->seed = spec->seed;
+        p->orders = spec->orders_dev;
+        rc = make_plan(gpu, kernels, set_offsets, n_sets, spec, w->cu_count, chunk, wg, &p->plan);
+        if (rc) {
+            delete p;
+            return rc;
+        }
+        const size_t kbytes = p->plan.krec.size() * sizeof(ko::KernelRec);
+        const size_t sbytes = p->plan.sets.size() * sizeof(ko::SetRec);
+        const size_t bbytes = p->plan.block_base.size() * sizeof(uint64_t);
+        const size_t pbytes = std::max<uint64_t>(p->plan.n_items, 1) * sizeof(ko::Partial);
+        hipError_t e = hipSuccess;
+        if ((e = hipMalloc((void **)&p->krec, std::max<size_t>(kbytes, 64))) != hipSuccess ||
+            (e = hipMalloc((void **)&p->sets, std::max<size_t>(sbytes, 64))) != hipSuccess ||
+            (e = hipMalloc((void **)&p->block_base, std::max<size_t>(bbytes, 64))) != hipSuccess ||
+            (e = hipMalloc((void **)&p->partials, pbytes)) != hipSuccess ||
+            (e = hipMalloc((void **)&p->counter, 2 * sizeof(unsigned long long))) != hipSuccess) {
+            free_plan(p);
+            return fail(KO_ENOMEM, "plan device allocation failed: %s", hipGetErrorString(e));
+        }
+        if ((kbytes && (e = hipMemcpy(p->krec, p->plan.krec.data(), kbytes, hipMemcpyHostToDevice)) != hipSuccess) ||
+            (sbytes && (e = hipMemcpy(p->sets, p->plan.sets.data(), sbytes, hipMemcpyHostToDevice)) != hipSuccess) ||
+            (e = hipMemcpy(p->block_base, p->plan.block_base.data(), bbytes, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemset(p->counter, 0, 2 * sizeof(unsigned long long))) != hipSuccess ||
+            (e = hipDeviceSynchronize()) != hipSuccess) {
+            free_plan(p);
+            return hip_fail(e, "plan upload");
+        }
+        // the host copies are no longer needed
+        p->plan.krec = std::vector<ko::KernelRec>();
+        *out = p;
+        return KO_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(KO_ENOMEM, "host allocation failed");
+    }
+}
+
+int ko_plan_info(const ko_plan *plan, uint64_t *total_orders, uint64_t *work_items, uint64_t *chunk,
+                 int32_t *grid)
+{
+    if (!plan)
+        return fail(KO_EINVAL, "plan must not be NULL");
+    if (total_orders)
+        *total_orders = plan->plan.total;
+    if (work_items)
+        *work_items = plan->plan.n_items;
+    if (chunk)
+        *chunk = plan->plan.chunk;
+    if (grid)
+        *grid = plan->plan.grid;
+    return KO_OK;
+}
+
+int ko_plan_launch(ko_plan *plan, const int64_t *ref_makespan_dev, int64_t *makespans_dev,
+                   ko_set_stats *stats_dev, uint64_t *hist_dev, int32_t n_bins, void *hip_stream)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (!plan)
+        return fail(KO_EINVAL, "plan must not be NULL");
+    int rc = check_outputs(makespans_dev, stats_dev, hist_dev, n_bins);
+    if (rc || (rc = check_plan_device(plan)))
+        return rc;
+    DevTables t{plan->krec, plan->sets, plan->block_base, plan->partials, plan->counter};
+    return enqueue_batch(t, plan->plan, plan->gpu, plan->n_sets, plan->mode, plan->seed, plan->orders, true,
+                         ref_makespan_dev, makespans_dev, stats_dev, hist_dev, n_bins, (hipStream_t)hip_stream,
+                         nullptr, nullptr);
+}
+
+int ko_plan_status(ko_plan *plan, void *hip_stream)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (!plan)
+        return fail(KO_EINVAL, "plan must not be NULL");
+    int rc = check_plan_device(plan);
+    if (rc)
+        return rc;
+    KO_HIP(hipStreamSynchronize((hipStream_t)hip_stream), "hipStreamSynchronize");
+    uint32_t status = 0;
+    KO_HIP(hipMemcpy(&status, (const void *)(plan->counter + 1), sizeof status, hipMemcpyDeviceToHost),
+           "hipMemcpy");
+    if (status & ko::kStatusBadOrder)
+        return fail(KO_EHIP, "device status: an explicit order is not a permutation of 0..n-1");
+    if (status)
+        return fail(KO_EHIP, "device status 0x%x: internal inconsistency", status);
+    return KO_OK;
+}
+
+int ko_plan_destroy(ko_plan *plan)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (!plan)
+        return KO_OK;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(plan->device);
+    // launches of the plan may still be running on any stream
+    (void)hipDeviceSynchronize();
+    free_plan(plan);
+    (void)hipSetDevice(prev);
+    return KO_OK;
+}
+
+int ko_graph_capture(ko_plan *plan, const int64_t *ref_makespan_dev, int64_t *makespans_dev,
+                     ko_set_stats *stats_dev, uint64_t *hist_dev, int32_t n_bins, void *hip_stream,
+                     ko_graph **out)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (!plan || !out)
+        return fail(KO_EINVAL, "plan and out must not be NULL");
+    *out = nullptr;
+    if (!hip_stream)
+        return fail(KO_EINVAL, "capture needs a created stream, not the null stream");
+    int rc = check_outputs(makespans_dev, stats_dev, hist_dev, n_bins);
+    if (rc || (rc = check_plan_device(plan)))
+        return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    KO_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    DevTables t{plan->krec, plan->sets, plan->block_base, plan->partials, plan->counter};
+    rc = enqueue_batch(t, plan->plan, plan->gpu, plan->n_sets, plan->mode, plan->seed, plan->orders, true,
+                       ref_makespan_dev, makespans_dev, stats_dev, hist_dev, n_bins, st, nullptr, nullptr);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess)
+        return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    ko_graph *g = new ko_graph();
+    g->device = plan->device;
+    g->graph = graph;
+    g->exec = exec;
+    *out = g;
+    return KO_OK;
+}
+
+int ko_graph_launch(ko_graph *graph, void *hip_stream)
+{
+    if (!graph)
+        return fail(KO_EINVAL, "graph must not be NULL");
+    KO_HIP(hipGraphLaunch(graph->exec, (hipStream_t)hip_stream), "hipGraphLaunch");
+    return KO_OK;
+}
+
+int ko_graph_destroy(ko_graph *graph)
+{
+    if (!graph)
+        return KO_OK;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(graph->device);
+    (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(graph->exec);
+    (void)hipGraphDestroy(graph->graph);
+    (void)hipSetDevice(prev);
+    delete graph;
+    return KO_OK;
 }
 
 int ko_rank_percentile(const ko_gpu_model *gpu, const ko_kernel *k, int32_t n, const int32_t *order,

@@ -202,3 +202,28 @@ def test_sampling_and_selection_reject_bad_arguments_before_device_work():
     assert lib.ko_kth_smallest_i64(fake, 10, 11, ctypes.byref(out), None, None) == ko.KO_EINVAL
     assert lib.ko_kth_smallest_i64(None, 10, 1, ctypes.byref(out), None, None) == ko.KO_EINVAL
     assert lib.ko_kth_smallest_i64(fake, 10, 1, None, None, None) == ko.KO_EINVAL
+
+
+def test_plan_and_graph_reject_bad_arguments_before_device_work():
+    lib = ko.library_handle()
+    gpu = ko.gpu_model(dict(synth.MI355X_MODEL.as_dict(), n_cu=0))
+    ks = ko.kernel_array(synth.draw_set(0, 0))
+    off = np.array([0, len(ks)], dtype=np.int32)
+    spec = ko.OrderSpec.all().c_struct()
+    out = ctypes.c_void_p()
+    cfg = ko.KoLaunchConfig(0, 0)
+    assert lib.ko_plan_create(ctypes.byref(gpu), ks.ctypes.data, off.ctypes.data_as(ko._i32p), 1,
+                              ctypes.byref(spec), ctypes.byref(cfg), ctypes.byref(out)) == ko.KO_EINVAL
+    good = ko.gpu_model(synth.MI355X_MODEL)
+    for bad in (ko.KoLaunchConfig(21, 0), ko.KoLaunchConfig(-1, 0), ko.KoLaunchConfig(0, 65)):
+        assert lib.ko_plan_create(ctypes.byref(good), ks.ctypes.data, off.ctypes.data_as(ko._i32p), 1,
+                                  ctypes.byref(spec), ctypes.byref(bad), ctypes.byref(out)) == ko.KO_EINVAL
+    assert lib.ko_plan_create(ctypes.byref(good), ks.ctypes.data, off.ctypes.data_as(ko._i32p), 1,
+                              ctypes.byref(spec), None, None) == ko.KO_EINVAL
+    assert lib.ko_plan_info(None, None, None, None, None) == ko.KO_EINVAL
+    assert lib.ko_plan_launch(None, None, None, None, None, 0, None) == ko.KO_EINVAL
+    assert lib.ko_plan_status(None, None) == ko.KO_EINVAL
+    assert lib.ko_graph_capture(None, None, None, None, None, 0, None, ctypes.byref(out)) == ko.KO_EINVAL
+    assert lib.ko_graph_launch(None, None) == ko.KO_EINVAL
+    assert lib.ko_plan_destroy(None) == ko.KO_OK
+    assert lib.ko_graph_destroy(None) == ko.KO_OK
