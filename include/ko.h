@@ -314,6 +314,31 @@ int ko_topk_f32(const float *y_dev, uint64_t count, int32_t k, int64_t *idx_out_
 int ko_kth_smallest_i64(const int64_t *v_dev, uint64_t count, uint64_t k, int64_t *value_out,
                         uint64_t *count_le_out, void *hip_stream);
 
+/* ------------------------------------------------------------------ hardware
+ * Validation of the model on the GPU itself (not part of the model): each
+ * kernel of a set becomes a synthetic HIP kernel with its grid (n_tblk
+ * blocks), waves_blk * 64 threads per block and lds_blk bytes of dynamic LDS;
+ * every thread runs F = n_inst / scale fused multiply-adds on a register
+ * footprint near regs_thr and F * 1000 / r_milli streaming 16-byte loads.
+ * Kernels are launched in the given order, one stream per kernel (Section 1:
+ * concurrent kernels through streams), and the makespan is the time from the
+ * first launch to the last kernel's end, by HIP events. */
+
+/* ko_hw_vgprs — the VGPR count of the compiled variant that stands in for a
+ * kernel with regs_thr registers per thread (model the hardware with it). */
+int ko_hw_vgprs(int32_t regs_thr, int32_t *vgprs_out);
+
+/* ko_hw_time_orders — makespans (milliseconds, best of `reps` runs) of
+ * n_orders orders (int32 [n_orders][n], host) of the n kernels k[] (host) on
+ * the current device, into makespan_ms_out[n_orders] (host).  Synchronous;
+ * uses a 1 GiB device buffer kept until process exit.  n_tblk <= 2^20,
+ * waves_blk <= 16, lds_blk <= 160 KiB.  Errors: KO_EINVAL, KO_EHIP. */
+int ko_hw_time_orders(const ko_kernel *k, int32_t n, const int32_t *orders, int32_t n_orders, int32_t scale,
+                      int32_t reps, double *makespan_ms_out);
+
+/* ko_hw_last_error — description of the last failure of a ko_hw_* call. */
+const char *ko_hw_last_error(void);
+
 /* ko_set_kernel_timing — measurement aid, not part of the method: while enabled
  * (enable != 0), ko_simulate_batch on the current device records two timing
  * events on its stream, immediately before and after the simulate kernel (the

@@ -42,7 +42,8 @@ EXPORTED = ("ko_heuristic_order", "ko_count_orders", "ko_simulate_batch", "ko_ra
             "ko_sync", "ko_shutdown", "ko_plan_create", "ko_plan_info", "ko_plan_launch", "ko_plan_status",
             "ko_plan_destroy", "ko_graph_capture", "ko_graph_launch", "ko_graph_destroy",
             "ko_sample_orders", "ko_topk_f32", "ko_kth_smallest_i64",
-            "ko_set_kernel_timing", "ko_last_kernel_ms", "ko_last_error")
+            "ko_set_kernel_timing", "ko_last_kernel_ms", "ko_hw_vgprs", "ko_hw_time_orders",
+            "ko_hw_last_error", "ko_last_error")
 
 
 class KoGpuModel(ctypes.Structure):
@@ -152,6 +153,13 @@ def _L():
                                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64),
                                              ctypes.c_void_p]
         lib.ko_kth_smallest_i64.restype = ctypes.c_int
+        lib.ko_hw_vgprs.argtypes = [ctypes.c_int32, _i32p]
+        lib.ko_hw_vgprs.restype = ctypes.c_int
+        lib.ko_hw_time_orders.argtypes = [ctypes.c_void_p, ctypes.c_int32, _i32p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        lib.ko_hw_time_orders.restype = ctypes.c_int
+        lib.ko_hw_last_error.argtypes = []
+        lib.ko_hw_last_error.restype = ctypes.c_char_p
         lib.ko_set_kernel_timing.argtypes = [ctypes.c_int32]
         lib.ko_set_kernel_timing.restype = ctypes.c_int
         lib.ko_last_kernel_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
@@ -463,6 +471,28 @@ def ko_kth_smallest_i64(v, k: int, stream=None, *, with_count: bool = False):
     _check(_L().ko_kth_smallest_i64(_dev_ptr(v, torch.int64, v.numel(), "v"), v.numel(), int(k),
                                     ctypes.byref(out), ctypes.byref(le), _stream_handle(stream)))
     return (int(out.value), int(le.value)) if with_count else int(out.value)
+
+
+def ko_hw_vgprs(regs_thr: int) -> int:
+    out = ctypes.c_int32(0)
+    rc = _L().ko_hw_vgprs(int(regs_thr), ctypes.byref(out))
+    if rc:
+        raise KoError(rc, _L().ko_hw_last_error().decode())
+    return int(out.value)
+
+
+def ko_hw_time_orders(kernels, orders, scale: int, reps: int = 2) -> np.ndarray:
+    """Measured makespans (ms) of the given orders of a kernel set (see ko.h)."""
+    k = kernel_array(kernels)
+    o = np.ascontiguousarray(orders, dtype=np.int32)
+    if o.ndim == 1:
+        o = o[None, :]
+    out = np.zeros(len(o), dtype=np.float64)
+    rc = _L().ko_hw_time_orders(k.ctypes.data, len(k), o.ctypes.data_as(_i32p), len(o), int(scale), int(reps),
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc:
+        raise KoError(rc, _L().ko_hw_last_error().decode())
+    return out
 
 
 def ko_sync(stream=None):

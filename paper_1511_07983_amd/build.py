@@ -50,8 +50,10 @@ def build(verbose: bool = True) -> str:
     _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_sim.hip"), "-o", sim_o])
     sel_o = os.path.join(objdir, "ko_select.o")
     _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_select.hip"), "-o", sel_o])
+    hw_o = os.path.join(objdir, "ko_hw.o")
+    _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_hw.hip"), "-o", hw_o])
     tmp = LIB + ".tmp"
-    _run([HIPCC, *DEVICE, "-shared", "-fPIC", host_o, sim_o, sel_o, "-o", tmp])
+    _run([HIPCC, *DEVICE, "-shared", "-fPIC", host_o, sim_o, sel_o, hw_o, "-o", tmp])
     os.replace(tmp, LIB)
     nn_o = os.path.join(objdir, "ko_nn.o")
     _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_nn.hip"), "-o", nn_o])
