@@ -151,66 +151,84 @@ def parse(asm: str):
     return funcs
 
 
+def _drop(tok: dict, regs):
+    for r in regs:
+        tok.pop(r, None)
+        tok.pop(r - 1, None)
+
+
 def _transfer(inst: Inst, exec_state: str, tok: dict):
-    """Apply one instruction to (exec, saved-mask tokens); returns new exec."""
+    """Apply one instruction to (exec, tokens); returns the new exec state.
+
+    tok maps the low register of an SGPR pair to (kind, R):
+      ("save", R)  OR-ing it into exec restores exec state R (a mask saved
+                   by saveexec, the complementary lanes of an if/else, or an
+                   accumulator of lanes that left a divergent loop);
+      ("copy", R)  a copy of exec taken in state R;
+      ("sub", R)   a subset of such a copy (copy AND condition).
+    """
     m, ops = inst.mnem, inst.ops
     if m.endswith("saveexec_b64") and ops:
         d = _pair(ops[0])
         src = _pair(ops[1]) if len(ops) > 1 else None
         if m == "s_and_saveexec_b64":
-            new_tok = exec_state
-        elif m == "s_andn2_saveexec_b64":
+            new_tok = ("save", exec_state)
+        elif m == "s_andn2_saveexec_b64" and tok.get(src, ("", None))[0] == "save":
             # exec = S & ~exec, D = old exec: D and the new exec partition what S restored
-            new_tok = tok.get(src, PARTIAL)
+            new_tok = ("save", tok[src][1])
         else:
-            new_tok = PARTIAL
-        for r in (d, d + 1) if d is not None else ():
-            tok.pop(r, None)
+            new_tok = None
         if d is not None:
-            tok[d] = new_tok
+            _drop(tok, (d, d + 1))
+            if new_tok:
+                tok[d] = new_tok
         return PARTIAL
     if ops and ops[0] == "exec":
         if m == "s_or_b64" and len(ops) == 3 and "exec" in ops[1:]:
             other = ops[2] if ops[1] == "exec" else ops[1]
-            p = _pair(other)
-            return FULL if (p is not None and tok.get(p) == FULL) else (
-                exec_state if exec_state == FULL else PARTIAL)
-        if m == "s_mov_b64" and len(ops) == 2 and _pair(ops[1]) is not None:
-            return PARTIAL if tok.get(("copy", _pair(ops[1]))) != FULL else FULL
+            t = tok.get(_pair(other))
+            if t and t[0] == "save" and t[1] == FULL:
+                return FULL
+            return exec_state if exec_state == FULL else PARTIAL
+        if m == "s_mov_b64" and len(ops) == 2:
+            t = tok.get(_pair(ops[1]))
+            return FULL if (t and t[0] == "copy" and t[1] == FULL) else PARTIAL
         return PARTIAL
-    # writes to SGPRs: keep or drop tokens
     if m.startswith("s_") and ops and not m.startswith(_NO_SDST):
         d = _pair(ops[0])
-        regs = _sregs(ops[0])
         keep = None
-        if m == "s_mov_b64" and d is not None and len(ops) == 2:
-            if ops[1] == "exec":
+        srcs = ops[1:]
+        tks = [tok.get(_pair(o)) if o != "exec" else ("exec", exec_state) for o in srcs]
+        kinds = [t[0] if t else None for t in tks]
+        if m == "s_mov_b64" and d is not None and len(srcs) == 1:
+            if srcs[0] == "exec":
                 keep = ("copy", exec_state)
-            elif ops[1] in ("0", "0x0"):
-                keep = ("tok", exec_state)
-            elif _pair(ops[1]) is not None and _pair(ops[1]) in tok:
-                keep = ("tok", tok[_pair(ops[1])])
-        elif m == "s_or_b64" and d is not None and len(ops) == 3 and ops[0] in ops[1:] and d in tok:
-            keep = ("tok", tok[d])
-        elif m == "s_xor_b64" and d is not None and len(ops) == 3 and "exec" in ops[1:]:
-            other = ops[2] if ops[1] == "exec" else ops[1]
-            if _pair(other) in tok:
-                keep = ("tok", tok[_pair(other)])
-        for r in regs:
-            for k in [k for k in tok if k == r or k == r - 1 or (isinstance(k, tuple) and k[1] in (r, r - 1))]:
-                tok.pop(k, None)
-        if keep is not None:
-            tok[d] = keep[1]
-            if keep[0] == "copy":
-                tok[("copy", d)] = keep[1]
+            elif srcs[0] in ("0", "0x0"):
+                keep = ("save", exec_state)
+            elif tks[0] and kinds[0] != "exec":
+                keep = tks[0]
+        elif m == "s_or_b64" and d is not None and len(srcs) == 2 and ops[0] in srcs and \
+                tok.get(d, ("", None))[0] == "save":
+            keep = tok[d]
+        elif m == "s_xor_b64" and d is not None and len(srcs) == 2:
+            if "exec" in kinds:
+                other = tks[1 - kinds.index("exec")]
+                if other and other[0] == "save":
+                    keep = other
+            elif sorted(k or "" for k in kinds) == ["copy", "sub"]:
+                # copy ^ (copy & cond): the lanes of the copy outside the subset
+                keep = ("save", tks[kinds.index("copy")][1])
+        elif m == "s_and_b64" and d is not None and len(srcs) == 2 and "copy" in kinds:
+            keep = ("sub", tks[kinds.index("copy")][1])
+        _drop(tok, _sregs(ops[0]))
+        if keep is not None and d is not None:
+            tok[d] = keep
         return exec_state
     if m.startswith("v_") or m.startswith("s_load") or m.startswith("s_buffer_load"):
         for op in ops:
             regs = _sregs(op)
             if regs and (op is ops[0] or "_co_" in m or m.startswith("v_cmp") or m.startswith("v_div_scale")):
-                for r in regs:
-                    for k in [k for k in tok if k == r or k == r - 1 or (isinstance(k, tuple) and k[1] in (r, r - 1))]:
-                        tok.pop(k, None)
+                _drop(tok, regs)
     return exec_state
 
 
