@@ -150,3 +150,51 @@ def percentiles(gpu, sets, *, config=None, n_bins: int = 0, want_makespans: bool
     p1.close()
     p2.close()
     return out
+
+
+def report(*, workload: int = 2, sets: int = 4096, tune_sets: int = 512, reps: int = 5, out=print):
+    """Exact evaluations per second over every order of a batch of kernel sets:
+    autotune on a subset, then replay a captured graph of the whole batch."""
+    import torch
+
+    import synth
+    w = synth.WORKLOADS[workload]
+    all_sets = [synth.draw_set(workload, s) for s in range(sets)]
+    k_t, o_t = concat_sets(all_sets[:tune_sets])
+    cfg, rows = autotune(w.model, k_t, o_t, OrderSpec.all(), reps=2, use_cache=False)
+    kernels, offsets = concat_sets(all_sets)
+    plan = Plan(w.model, kernels, offsets, OrderSpec.all(), chunk_log2=cfg["chunk_log2"],
+                wg_per_cu=cfg["wg_per_cu"])
+    st = torch.empty(8 * sets, dtype=torch.int64, device="cuda:0")
+    ms = torch.empty(plan.total_orders, dtype=torch.int64, device="cuda:0")
+    stream = torch.cuda.Stream()
+    graph = plan.capture(stream=stream, makespans=ms, stats=st)
+    graph.launch(stream)
+    stream.synchronize()
+    plan.status(stream)
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        graph.launch(stream)
+        b.record(stream)
+        b.synchronize()
+        times.append(a.elapsed_time(b) / 1e3)
+    plan.status(stream)
+    t = float(np.median(times))
+    out(json.dumps({"workload": w.name, "sets": sets, "orders": int(plan.total_orders),
+                    "config": {"chunk_log2": cfg["chunk_log2"], "wg_per_cu": cfg["wg_per_cu"]},
+                    "tuning": rows, "graph_replay_s": t, "orders_per_s": plan.total_orders / t,
+                    "work_items": int(plan.work_items)}), flush=True)
+    graph.close()
+    plan.close()
+
+
+if __name__ == "__main__":
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import torch
+    torch.cuda.set_device(0)
+    report()

@@ -370,6 +370,72 @@ def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: i
     return rows
 
 
+def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets: int = 512, per_set: int = 8192,
+                 eval_sets: int = 1024, width: int = 256, q_samples: int = 4096, steps: int = 8192,
+                 batch: int = 4096, lr: float = 1e-3, mask_frac: float = 0.25, seed: int = 2016, out=print):
+    """Beam search (width `width`) against uniform sampling at the same exact
+    budget (`width` exact simulations per set).  The top-1% threshold of each
+    set is the ceil(q_samples/100)-th smallest of `q_samples` exact random
+    orders (n! is out of reach at n=16).  Prints one JSON summary line."""
+    import json
+    import time
+
+    import synth
+
+    torch = _torch()
+    t0 = time.perf_counter()
+    tr = [synth.draw_set(train_workload, s) for s in range(train_sets)]
+    table = SetTable.build(synth.WORKLOADS[train_workload].model, tr)
+    data = mask_suffixes(exact_samples(table, per_set, seed=seed), mask_frac, seed + 1)
+    sur = nn.Surrogate(_init_params(seed + 2))
+    log = train(sur, table, data, steps=steps, batch=batch, lr=lr, warmup=min(200, steps // 10), seed=seed + 3,
+                log_every=max(1, steps // 8))
+    torch.cuda.synchronize()
+    out(json.dumps({"phase": "train", "sets": train_sets, "n": table.n, "samples": data.count,
+                    "mask_frac": mask_frac, "train_s": round(time.perf_counter() - t0, 2), "loss": log}),
+        flush=True)
+    del data
+    model = synth.WORKLOADS[eval_workload].model
+    ev = [synth.draw_set(eval_workload, s) for s in range(eval_sets)]
+    etab = SetTable.build(model, ev)
+    S = len(ev)
+    # exact random samples of every set in one batch: q_samples for the
+    # threshold, then `width` more as the random-search budget
+    t0 = time.perf_counter()
+    qms = torch.empty(S * q_samples, dtype=torch.int64, device="cuda:0")
+    ko_simulate_batch(model, etab.kernels, etab.offsets, OrderSpec.sampled([q_samples] * S, seed + 10),
+                      makespans=qms)
+    rms = torch.empty(S * width, dtype=torch.int64, device="cuda:0")
+    ko_simulate_batch(model, etab.kernels, etab.offsets, OrderSpec.sampled([width] * S, seed + 11),
+                      makespans=rms)
+    ko_sync()
+    k = max(1, math.ceil(q_samples / 100))
+    thr = np.array([ko_kth_smallest_i64(qms[s * q_samples:(s + 1) * q_samples], k) for s in range(S)])
+    rnd = rms.cpu().numpy().reshape(S, width)
+    t_exact = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rows = []
+    for s in range(S):
+        res = beam_search(sur, etab, s, width=width)
+        hit_b = np.flatnonzero(res.exact <= thr[s])
+        hit_r = np.flatnonzero(rnd[s] <= thr[s])
+        rows.append((int(res.exact.min()), int(rnd[s].min()), len(hit_b), len(hit_r),
+                     int(hit_b[0]) + 1 if len(hit_b) else 0, int(hit_r[0]) + 1 if len(hit_r) else 0))
+    t_beam = time.perf_counter() - t0
+    a = np.array(rows, dtype=np.float64)
+    better = float(np.mean(a[:, 0] < a[:, 1]))
+    tie = float(np.mean(a[:, 0] == a[:, 1]))
+    out(json.dumps({"phase": "beam_vs_random", "eval_sets": S, "n": etab.n, "width": width,
+                    "exact_budget_per_set": width, "q_samples": q_samples,
+                    "best_ratio_beam_over_random_mean": float(np.mean(a[:, 0] / a[:, 1])),
+                    "beam_better_frac": better, "tie_frac": tie,
+                    "beam_hits_top1pct_mean": float(a[:, 2].mean()), "random_hits_top1pct_mean": float(a[:, 3].mean()),
+                    "sets_beam_found_top1pct": float(np.mean(a[:, 2] > 0)),
+                    "sets_random_found_top1pct": float(np.mean(a[:, 3] > 0)),
+                    "exact_sampling_s": round(t_exact, 2), "beam_s": round(t_beam, 2)}), flush=True)
+    return rows
+
+
 if __name__ == "__main__":
     import argparse
     import os
@@ -387,9 +453,16 @@ if __name__ == "__main__":
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--train-workload", type=int, default=3)
     ap.add_argument("--heldout-workload", type=int, default=13)
+    ap.add_argument("--beam", action="store_true", help="n=16 beam search vs random sampling instead")
+    ap.add_argument("--eval-sets", type=int, default=1024)
+    ap.add_argument("--width", type=int, default=256)
     a = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
+    if a.beam:
+        report_beam(train_sets=a.train_sets, per_set=a.per_set, eval_sets=a.eval_sets, width=a.width,
+                    steps=a.steps, batch=a.batch, lr=a.lr)
+        raise SystemExit(0)
     report(train_workload=a.train_workload, heldout_workload=a.heldout_workload, train_sets=a.train_sets,
            per_set=a.per_set, heldout=a.heldout, n_score=a.n_score, top_k=a.top_k, steps=a.steps,
            batch=a.batch, lr=a.lr)
