@@ -88,6 +88,15 @@ int ko_nn_targets(const int64_t *makespans_dev, const int32_t *set_of_dev, const
                   const int64_t *scale_dev, const int64_t *rows_dev, int32_t B, float *t_dev,
                   void *hip_stream);
 
+/* ko_nn_within_set_ranks — for values[n_sets][per_set] (int64, device; e.g.
+ * the exact makespans of each set's sampled orders), ranks[s][i] (int64,
+ * device) = position of sample i when set s is sorted by (value, i).  With
+ * ko_nn_targets (centre 0, scale per_set) this gives rank-quantile targets,
+ * which train the scorer on the order of a set's samples rather than on
+ * cycles.  per_set <= 8192; a set's values must span less than 2^51. */
+int ko_nn_within_set_ranks(const int64_t *values_dev, int32_t n_sets, int32_t per_set, int64_t *ranks_dev,
+                           void *hip_stream);
+
 /* ko_nn_forward — y[B] (float32, device) for tokens x[B][n][32].  1 <= n <= 16. */
 int ko_nn_forward(const void *state_dev, const uint16_t *x_dev, int32_t B, int32_t n, float *y_dev,
                   void *work_dev, void *hip_stream);

@@ -384,6 +384,55 @@ __global__ void targets_kernel(const int64_t *makespans, const int32_t *set_of, 
     t[b] = (float)((double)(makespans[r] - center[s]) / (double)scale[s]);
 }
 
+// Within-set ranks: ranks[s * per + i] = position of sample i of set s when
+// the set's values are sorted by (value, i).  One workgroup per set sorts the
+// keys (value - min) << 13 | i in LDS with a bitonic network (per <= 8192,
+// padded to a power of two with the largest key); values of a set must span
+// less than 2^51.
+constexpr int kRankMax = 8192;
+
+__global__ __launch_bounds__(1024) void within_set_rank_kernel(const int64_t *values, int32_t per, int32_t p2,
+                                                               int64_t *ranks)
+{
+    __shared__ uint64_t key[kRankMax];
+    __shared__ int64_t vmin[32];
+    const int64_t s = blockIdx.x;
+    const int64_t *v = values + s * per;
+    // minimum of the set (keys are offsets from it)
+    int64_t m = INT64_MAX;
+    for (int i = threadIdx.x; i < per; i += blockDim.x)
+        m = min(m, v[i]);
+    for (int o = 32; o >= 1; o >>= 1)
+        m = min(m, (int64_t)__shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0)
+        vmin[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = vmin[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); w++)
+        m = min(m, vmin[w]);
+    for (int i = threadIdx.x; i < p2; i += blockDim.x)
+        key[i] = (i < per) ? (((uint64_t)(v[i] - m) << 13) | (uint64_t)i) : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= p2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < p2; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint64_t a = key[i], b = key[l];
+                    const bool up = (i & k) == 0;
+                    if (up ? (a > b) : (a < b)) {
+                        key[i] = b;
+                        key[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int p = threadIdx.x; p < per; p += blockDim.x)
+        ranks[s * per + (int64_t)(key[p] & 8191u)] = p;
+}
+
 // Layer 1 for one set, tabulated over launch positions: a token is its
 // kernel's features plus a one-hot position, so its first-layer output is
 //   T[i][p][j] = relu(sum_{k<8} W1[j][k] f_i[k] + W1[j][8+p] + b1[j])
@@ -792,6 +841,20 @@ int ko_nn_targets(const int64_t *makespans_dev, const int32_t *set_of_dev, const
         return fail(KO_EINVAL, "bad arguments");
     hipLaunchKernelGGL(targets_kernel, dim3(grid1(B)), dim3(256), 0, (hipStream_t)hip_stream,
                        makespans_dev, set_of_dev, center_dev, scale_dev, rows_dev, B, t_dev);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+int ko_nn_within_set_ranks(const int64_t *values_dev, int32_t n_sets, int32_t per_set, int64_t *ranks_dev,
+                           void *hip_stream)
+{
+    if (!values_dev || !ranks_dev || n_sets < 1 || per_set < 1 || per_set > kRankMax)
+        return fail(KO_EINVAL, "need values, ranks, n_sets >= 1 and 1 <= per_set <= %d", kRankMax);
+    int32_t p2 = 1;
+    while (p2 < per_set)
+        p2 <<= 1;
+    hipLaunchKernelGGL(within_set_rank_kernel, dim3((unsigned)n_sets), dim3(1024), 0, (hipStream_t)hip_stream,
+                       values_dev, per_set, p2, ranks_dev);
     NN_LAUNCHED();
     return KO_OK;
 }

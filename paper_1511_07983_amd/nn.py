@@ -33,7 +33,8 @@ D_HID = 256
 MAX_TOKENS = 16
 
 EXPORTED = ("ko_nn_num_params", "ko_nn_state_bytes", "ko_nn_work_bytes", "ko_nn_load", "ko_nn_read",
-            "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens", "ko_nn_targets", "ko_nn_forward",
+            "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens", "ko_nn_targets", "ko_nn_within_set_ranks",
+            "ko_nn_forward",
             "ko_nn_backward", "ko_nn_adam", "ko_nn_layer1_table", "ko_nn_score_work_bytes",
             "ko_nn_forward_positions", "ko_nn_last_error")
 
@@ -53,12 +54,13 @@ _lib.ko_nn_backward.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _
 _lib.ko_nn_adam.argtypes = [_vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                             ctypes.c_float, _vp]
 _lib.ko_nn_layer1_table.argtypes = [_vp, _vp, ctypes.c_int32, _vp, _vp]
+_lib.ko_nn_within_set_ranks.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
 _lib.ko_nn_score_work_bytes.argtypes = [ctypes.c_int32]
 _lib.ko_nn_score_work_bytes.restype = ctypes.c_size_t
 _lib.ko_nn_forward_positions.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
 _lib.ko_nn_last_error.restype = ctypes.c_char_p
 for _f in ("ko_nn_load", "ko_nn_read", "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens", "ko_nn_targets",
-           "ko_nn_forward", "ko_nn_backward", "ko_nn_adam", "ko_nn_layer1_table",
+           "ko_nn_forward", "ko_nn_backward", "ko_nn_adam", "ko_nn_layer1_table", "ko_nn_within_set_ranks",
            "ko_nn_forward_positions"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -87,6 +89,15 @@ def lower_bound(gpu, kernels) -> int:
     lb = ctypes.c_int64(0)
     _check(_lib.ko_nn_lower_bound(ctypes.addressof(g), k.ctypes.data, len(k), ctypes.byref(lb)))
     return int(lb.value)
+
+
+def within_set_ranks(values, n_sets: int, per_set: int, stream=None):
+    """Device int64 ranks of each set's samples (see ko_nn_within_set_ranks)."""
+    import torch
+    ranks = torch.empty(n_sets * per_set, dtype=torch.int64, device=values.device)
+    _check(_lib.ko_nn_within_set_ranks(values.data_ptr(), n_sets, per_set, ranks.data_ptr(),
+                                       _stream_handle(stream)))
+    return ranks
 
 
 class Surrogate:

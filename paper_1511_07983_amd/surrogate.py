@@ -12,9 +12,11 @@ them and owns the host-side bookkeeping):
 
   training data   sampled orders of many sets, their exact makespans
                   (ko_simulate_batch, SAMPLED) and positions (ko_sample_orders);
-  training        shuffled minibatches -> tokens and targets (makespan minus the
-                  set's best sampled makespan, over the set's area lower bound)
-                  -> forward/backward -> Adam,
+  training        shuffled minibatches -> tokens and targets (by default the
+                  rank quantile of a sample among its set's samples, from a
+                  device sort per set; or makespan minus the set's best sampled
+                  makespan over the set's area lower bound) -> forward/backward
+                  -> Adam,
                   all in libko_nn; with `mask_suffix` some samples hide a
                   random suffix of their order ("unplaced"), which teaches the
                   scorer partial orders for beam search;
@@ -85,15 +87,21 @@ class Samples:
     makespans: object   # int64 [R]
     pos: object         # uint8 [R, n]
     set_of: object      # int32 [R]
-    best: object        # int64 [S]: each set's best sampled makespan (target centre)
+    best: object        # int64 [S]: each set's best sampled makespan
+    target: str = "quantile"
+    t_values: object = None   # int64 [R]; targets are (t_values - t_center[s]) / t_scale[s]
+    t_center: object = None   # int64 [S]
+    t_scale: object = None    # int64 [S]
 
     @property
     def count(self) -> int:
         return int(self.makespans.shape[0])
 
 
-def exact_samples(table: SetTable, per_set: int, seed: int, device="cuda:0") -> Samples:
-    """`per_set` sampled orders of every set with their exact makespans."""
+def exact_samples(table: SetTable, per_set: int, seed: int, device="cuda:0", target: str = "quantile") -> Samples:
+    """`per_set` sampled orders of every set with their exact makespans and
+    training targets: "quantile" = rank among the set's samples / per_set,
+    "lb" = (makespan - best sampled) / area lower bound."""
     torch = _torch()
     S, n = len(table.sets), table.n
     R = S * per_set
@@ -108,7 +116,16 @@ def exact_samples(table: SetTable, per_set: int, seed: int, device="cuda:0") -> 
     set_of = torch.from_numpy(np.repeat(np.arange(S, dtype=np.int32), per_set)).to(device)
     ko_sync()
     best = st.view(S, 8)[:, 0].contiguous()  # min_makespan is the first field of a stats record
-    return Samples(per_set=per_set, seed=seed, makespans=ms, pos=pos, set_of=set_of, best=best)
+    if target == "quantile":
+        values = nn.within_set_ranks(ms, S, per_set)
+        center = torch.zeros(S, dtype=torch.int64, device=device)
+        scale = torch.full((S,), per_set, dtype=torch.int64, device=device)
+    elif target == "lb":
+        values, center, scale = ms, best, table.lb
+    else:
+        raise ValueError(f"unknown target {target!r}")
+    return Samples(per_set=per_set, seed=seed, makespans=ms, pos=pos, set_of=set_of, best=best, target=target,
+                   t_values=values, t_center=center, t_scale=scale)
 
 
 def mask_suffixes(samples: Samples, frac: float, seed: int) -> Samples:
@@ -126,7 +143,8 @@ def mask_suffixes(samples: Samples, frac: float, seed: int) -> Samples:
     pos[rows] = sub
     return Samples(per_set=samples.per_set, seed=samples.seed, makespans=samples.makespans,
                    pos=torch.from_numpy(pos).to(samples.pos.device), set_of=samples.set_of,
-                   best=samples.best)
+                   best=samples.best, target=samples.target, t_values=samples.t_values,
+                   t_center=samples.t_center, t_scale=samples.t_scale)
 
 
 def train(sur: "nn.Surrogate", table: SetTable, data: Samples, *, steps: int, batch: int = 4096,
@@ -150,7 +168,7 @@ def train(sur: "nn.Surrogate", table: SetTable, data: Samples, *, steps: int, ba
             perm = torch.from_numpy(rng.permutation(R).astype(np.int64)).to(dev)
         rows = perm[j * batch:(j + 1) * batch]
         sur.tokens(table.feat, data.pos, data.set_of, rows=rows, out=x)
-        sur.targets(data.makespans, data.best, table.lb, data.set_of, rows=rows, out=t)
+        sur.targets(data.t_values, data.t_center, data.t_scale, data.set_of, rows=rows, out=t)
         loss = sur.backward(x, t)
         if step <= warmup:
             rate = lr * step / max(1, warmup)
@@ -164,13 +182,22 @@ def train(sur: "nn.Surrogate", table: SetTable, data: Samples, *, steps: int, ba
 
 
 def predict(sur: "nn.Surrogate", table: SetTable, set_index: int, pos):
-    """Predicted makespans of one set's orders given as positions [B, n] (device),
-    in cycles above the set's best makespan (float64 host): the network is
-    trained on (makespan - best sampled) / lower bound, and only differences
-    within a set matter for ranking."""
+    """Scores of one set's orders given as positions [B, n] (device), float64
+    host: lower is better.  With rank-quantile training a score estimates the
+    order's quantile among the set's orders; with "lb" training it is cycles
+    above the set's best over its lower bound."""
     tab = sur.layer1_table(table.feat[set_index])
-    y = sur.forward_positions(tab, pos).cpu().numpy().astype(np.float64)
-    return y * float(table.lb_host[set_index])
+    return sur.forward_positions(tab, pos).cpu().numpy().astype(np.float64)
+
+
+def mae_cycles(res: "SearchResult", q: Quantile, target: str, lb: float) -> float:
+    """MAE in cycles of the re-simulated candidates.  Quantile scores are
+    mapped to cycles through the set's exact makespan distribution; "lb"
+    scores are cycles above the best over the lower bound, put on the
+    absolute scale by one per-set offset."""
+    if target == "quantile":
+        return float(np.mean(np.abs(q.cycles_at(res.predicted) - res.exact)))
+    return calibrated_mae(res.predicted * lb, res.exact)
 
 
 def calibrated_mae(predicted_rel: np.ndarray, exact: np.ndarray) -> float:
@@ -188,11 +215,20 @@ class Quantile:
     hits: int          # orders with makespan <= it
     best: int
     worst: int
+    hist: np.ndarray = None   # exact makespan histogram over [best, worst] (equal-width bins)
 
     @property
     def random_expected(self) -> float:
         """Mean exact simulations of uniform sampling (with replacement) to the first hit."""
         return self.n_orders / self.hits
+
+    def cycles_at(self, quantile) -> np.ndarray:
+        """The makespan at the given quantile(s) of all orders, read from the
+        exact histogram with linear interpolation inside a bin."""
+        q = np.clip(np.asarray(quantile, dtype=np.float64), 0.0, 1.0)
+        cdf = np.concatenate([[0.0], np.cumsum(self.hist) / self.n_orders])
+        edges = self.best + (self.worst - self.best + 1) * np.arange(len(self.hist) + 1) / len(self.hist)
+        return np.interp(q, cdf, edges)
 
 
 def top_quantile(model, kernels, frac: float = 0.01, device="cuda:0") -> Quantile:
@@ -202,13 +238,14 @@ def top_quantile(model, kernels, frac: float = 0.01, device="cuda:0") -> Quantil
     N = math.factorial(n)
     ms = torch.empty(N, dtype=torch.int64, device=device)
     st = torch.empty(8, dtype=torch.int64, device=device)
-    ko_simulate_batch(model, kernels, [0, n], OrderSpec.all(), makespans=ms, stats=st)
+    h = torch.empty(1024, dtype=torch.int64, device=device)
+    ko_simulate_batch(model, kernels, [0, n], OrderSpec.all(), makespans=ms, stats=st, hist=h, n_bins=1024)
     k = max(1, math.ceil(frac * N))
     q, hits = ko_kth_smallest_i64(ms, k, with_count=True)
     from . import stats_records
     rec = stats_records(st)[0]
     out = Quantile(n_orders=N, k=k, makespan=q, hits=hits, best=int(rec["min_makespan"]),
-                   worst=int(rec["max_makespan"]))
+                   worst=int(rec["max_makespan"]), hist=h.cpu().numpy().astype(np.float64))
     del ms
     return out
 
@@ -217,7 +254,7 @@ def top_quantile(model, kernels, frac: float = 0.01, device="cuda:0") -> Quantil
 class SearchResult:
     sample_index: np.ndarray   # sample numbers of the ranked orders (SAMPLED-mode counters)
     orders: np.ndarray         # [K, n] uint8, best predicted first
-    predicted: np.ndarray      # cycles above the set's best (see predict)
+    predicted: np.ndarray      # network scores, best first (see predict)
     exact: np.ndarray          # int64 cycles, exact re-simulation
     n_scored: int
 
@@ -243,7 +280,7 @@ def score_and_rerank(sur: "nn.Surrogate", table: SetTable, set_index: int, *, n_
     ko_sync()
     lb = float(table.lb_host[set_index])
     return SearchResult(sample_index=idx.cpu().numpy(), orders=orders.cpu().numpy().reshape(top_k, n),
-                        predicted=val.cpu().numpy().astype(np.float64) * lb,
+                        predicted=val.cpu().numpy().astype(np.float64),
                         exact=ms.cpu().numpy(), n_scored=n_score)
 
 
@@ -281,7 +318,7 @@ def beam_search(sur: "nn.Surrogate", table: SetTable, set_index: int, *, width: 
     ko_sync()
     lb = float(table.lb_host[set_index])
     return SearchResult(sample_index=np.full(K, -1), orders=beams.astype(np.uint8),
-                        predicted=val.cpu().numpy().astype(np.float64) * lb, exact=ms.cpu().numpy(),
+                        predicted=val.cpu().numpy().astype(np.float64), exact=ms.cpu().numpy(),
                         n_scored=n_scored)
 
 
@@ -311,7 +348,8 @@ def _init_params(seed: int) -> np.ndarray:
 
 def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: int = 512,
            per_set: int = 8192, heldout: int = 4, n_score: int = 100_000_000, top_k: int = 10_000,
-           steps: int = 8192, batch: int = 4096, lr: float = 2e-3, seed: int = 2015, out=print):
+           steps: int = 8192, batch: int = 4096, lr: float = 1e-3, seed: int = 2015, target: str = "quantile",
+           out=print):
     """Train on exact samples, then per held-out set: exact top-1% threshold by
     full enumeration, scoring of `n_score` sampled orders, exact re-simulation
     of the `top_k` best.  Prints one JSON line per held-out set and a summary."""
@@ -324,7 +362,7 @@ def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: i
     t0 = time.perf_counter()
     tr_sets = [synth.draw_set(train_workload, s) for s in range(train_sets)]
     table = SetTable.build(synth.WORKLOADS[train_workload].model, tr_sets)
-    data = exact_samples(table, per_set, seed=seed)
+    data = exact_samples(table, per_set, seed=seed, target=target)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     sur = nn.Surrogate(_init_params(seed + 1))
@@ -333,7 +371,7 @@ def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: i
                 seed=seed + 2, log_every=max(1, steps // 8))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    out(json.dumps({"phase": "train", "samples": data.count, "sets": train_sets, "n": table.n,
+    out(json.dumps({"phase": "train", "target": target, "samples": data.count, "sets": train_sets, "n": table.n,
                     "data_s": round(t_data, 3), "train_s": round(t_train, 3), "steps": steps,
                     "batch": batch, "loss": log}), flush=True)
     del data
@@ -355,7 +393,7 @@ def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: i
                "random_sims_expected": q.random_expected, "surrogate_sims": sims,
                "speedup": q.random_expected / sims,
                "recall_at_1pct": float(np.mean(res.exact <= q.makespan)),
-               "mae_cycles_offset_calibrated": calibrated_mae(res.predicted, res.exact),
+               "mae_cycles": mae_cycles(res, q, target, float(htab.lb_host[s])),
                "best_of_topk": int(res.exact.min()), "enum_s": round(t_enum, 3),
                "score_rerank_s": round(t_score, 3), "n_score": n_score, "top_k": top_k}
         rows.append(row)
@@ -365,8 +403,8 @@ def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: i
                     "speedup_geomean": float(np.exp(np.mean(np.log(sp)))),
                     "speedup_min": float(sp.min()), "speedup_max": float(sp.max()),
                     "recall_at_1pct_mean": float(np.mean([r["recall_at_1pct"] for r in rows])),
-                    "mae_cycles_offset_calibrated_mean":
-                        float(np.mean([r["mae_cycles_offset_calibrated"] for r in rows]))}), flush=True)
+                    "mae_cycles_mean": float(np.mean([r["mae_cycles"] for r in rows])),
+                    "target": target}), flush=True)
     return rows
 
 
@@ -386,7 +424,7 @@ def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets:
     t0 = time.perf_counter()
     tr = [synth.draw_set(train_workload, s) for s in range(train_sets)]
     table = SetTable.build(synth.WORKLOADS[train_workload].model, tr)
-    data = mask_suffixes(exact_samples(table, per_set, seed=seed), mask_frac, seed + 1)
+    data = mask_suffixes(exact_samples(table, per_set, seed=seed, target="quantile"), mask_frac, seed + 1)
     sur = nn.Surrogate(_init_params(seed + 2))
     log = train(sur, table, data, steps=steps, batch=batch, lr=lr, warmup=min(200, steps // 10), seed=seed + 3,
                 log_every=max(1, steps // 8))
@@ -450,7 +488,8 @@ if __name__ == "__main__":
     ap.add_argument("--top-k", type=int, default=10_000)
     ap.add_argument("--steps", type=int, default=8192)
     ap.add_argument("--batch", type=int, default=4096)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--target", default="quantile", choices=("quantile", "lb"))
     ap.add_argument("--train-workload", type=int, default=3)
     ap.add_argument("--heldout-workload", type=int, default=13)
     ap.add_argument("--beam", action="store_true", help="n=16 beam search vs random sampling instead")
@@ -465,4 +504,4 @@ if __name__ == "__main__":
         raise SystemExit(0)
     report(train_workload=a.train_workload, heldout_workload=a.heldout_workload, train_sets=a.train_sets,
            per_set=a.per_set, heldout=a.heldout, n_score=a.n_score, top_k=a.top_k, steps=a.steps,
-           batch=a.batch, lr=a.lr)
+           batch=a.batch, lr=a.lr, target=a.target)
