@@ -12,7 +12,10 @@ workload (10 kernels, 256-CU MI355X-shaped model, 3,628,800 launch orders):
      histogram (device).
 
 Inputs are synthetic and seeded (SeedSequence([20151123, 1, 0])) and resident
-in HBM before timing starts.  Prints one JSON line.
+in HBM before timing starts.  After the timed steps, the metric's second part
+is measured on the n=12 workload (key "surrogate": exact simulations to the
+first order in the exact top 1%, learned scorer against uniform sampling;
+--no-surrogate skips it), then the CPU oracle.  Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -60,6 +63,9 @@ def parse():
     p.add_argument("--workload", type=int, default=1, help="synthetic workload index (default 1: n=10)")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target duration of the CPU oracle sample (0 = skip)")
+    p.add_argument("--no-surrogate", action="store_true",
+                   help="skip the surrogate leg (n=12: train, then exact simulations to a top-1%% order)")
+    p.add_argument("--surrogate-heldout", type=int, default=8)
     p.add_argument("--copy-mb", type=int, default=0,
                    help="after timing, copy this many MiB device-to-device once (untimed): a "
                         "plain copy of known size that calibrates HBM byte counters in a profile")
@@ -82,6 +88,31 @@ def cpu_baseline(model, ks, seconds: float) -> dict:
             "sample": f"lexicographic ranks {pilot}..{pilot + count - 1} of the same set "
                       f"({count} orders, {dt:.1f} s, plain C event-driven oracle, -O2, "
                       f"{threads} threads)"}
+
+
+def surrogate_leg(heldout: int) -> dict:
+    """The metric's second part on the n=12 workload (not in `value`): train the
+    scorer on 2^22 exact samples (8192 sets x 512, rank-quantile targets,
+    65,536 Adam steps), then per held-out set score 10^8 sampled orders,
+    re-simulate the best 10^4 exactly and count exact simulations to the first
+    order in the exact top 1% (full enumeration), against uniform sampling's
+    exact expectation N / hits."""
+    import json as _json
+
+    from paper_1511_07983_amd import surrogate
+    lines = []
+    try:
+        surrogate.report(heldout=heldout, out=lambda text, flush=True: lines.append(_json.loads(text)))
+    except Exception as exc:  # keep the throughput line even if this leg fails
+        return {"error": f"{type(exc).__name__}: {exc}"}
+    train = next(l for l in lines if l.get("phase") == "train")
+    summary = next(l for l in lines if l.get("phase") == "summary")
+    rows = [l for l in lines if l.get("phase") == "heldout"]
+    return {"workload": "surrogate-heldout-n12-mi355x", "heldout_sets": heldout,
+            "speedup_geomean": summary["speedup_geomean"], "per_set": [round(r["speedup"], 3) for r in rows],
+            "recall_at_1pct_mean": summary["recall_at_1pct_mean"], "mae_cycles_mean": summary["mae_cycles_mean"],
+            "train_s": train["train_s"], "train_samples": train["samples"], "train_sets": train["sets"],
+            "score_rerank_s_per_set": round(float(sum(r["score_rerank_s"] for r in rows) / max(1, len(rows))), 3)}
 
 
 def main():
@@ -184,6 +215,8 @@ def main():
         "heuristic": {"order": ko.ko_heuristic_order(w.model, kernels), "pct_inclusive": pct,
                       "min_makespan": int(rec["min_makespan"]), "max_makespan": int(rec["max_makespan"])},
     }
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg(args.surrogate_heldout)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(w.model, ks, args.cpu_seconds)
     print(json.dumps(out), flush=True)

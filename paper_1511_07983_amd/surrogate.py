@@ -346,9 +346,9 @@ def _init_params(seed: int) -> np.ndarray:
     return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
 
 
-def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: int = 512,
-           per_set: int = 8192, heldout: int = 4, n_score: int = 100_000_000, top_k: int = 10_000,
-           steps: int = 8192, batch: int = 4096, lr: float = 1e-3, seed: int = 2015, target: str = "quantile",
+def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: int = 8192,
+           per_set: int = 512, heldout: int = 8, n_score: int = 100_000_000, top_k: int = 10_000,
+           steps: int = 65536, batch: int = 4096, lr: float = 1e-3, seed: int = 2015, target: str = "quantile",
            out=print):
     """Train on exact samples, then per held-out set: exact top-1% threshold by
     full enumeration, scoring of `n_score` sampled orders, exact re-simulation
@@ -481,12 +481,12 @@ if __name__ == "__main__":
 
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     ap = argparse.ArgumentParser(description="surrogate-guided search report (one GPU)")
-    ap.add_argument("--train-sets", type=int, default=512)
-    ap.add_argument("--per-set", type=int, default=8192)
-    ap.add_argument("--heldout", type=int, default=4)
+    ap.add_argument("--train-sets", type=int, default=8192)
+    ap.add_argument("--per-set", type=int, default=512)
+    ap.add_argument("--heldout", type=int, default=8)
     ap.add_argument("--n-score", type=int, default=100_000_000)
     ap.add_argument("--top-k", type=int, default=10_000)
-    ap.add_argument("--steps", type=int, default=8192)
+    ap.add_argument("--steps", type=int, default=65536)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--target", default="quantile", choices=("quantile", "lb"))
