@@ -171,6 +171,86 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs a)
             }
 }
 
+// The product of every forward and scoring layer, C = A W^T with A [M][K]
+// and W [N][K] both contiguous along K (sak = sbk = 1): 128 x 128 tiles of 4
+// waves, each wave a 64 x 64 block of 4 x 4 MFMA 16x16x32 tiles, K in steps of
+// 32 staged through LDS with 16-byte loads (rows padded to 40 elements).
+// Needs K % 32 == 0, N % 128 == 0, row pitches and base addresses aligned to
+// 16 bytes; gemm() checks this and uses gemm_bf16_kernel otherwise.
+constexpr int kNtTile = 128;
+
+__global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[kNtTile][kPad];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kNtTile][kPad];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t m0 = (int64_t)blockIdx.x * kNtTile;
+    const int64_t n0 = (int64_t)blockIdx.y * kNtTile;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t k0 = 0; k0 < a.K; k0 += kKStep) {
+        // 128 rows x 4 chunks of 8 elements per operand: two chunks per thread
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int idx = tid + h * 256;
+            const int r = idx >> 2, c = (idx & 3) * 8;
+            const int64_t m = m0 + r;
+            uint4 va = make_uint4(0u, 0u, 0u, 0u);
+            if (m < a.M)
+                va = *reinterpret_cast<const uint4 *>(a.A + m * a.sam + k0 + c);
+            *reinterpret_cast<uint4 *>(&As[r][c]) = va;
+            const int64_t n = n0 + r;
+            uint4 vb = make_uint4(0u, 0u, 0u, 0u);
+            if (n < a.N)
+                vb = *reinterpret_cast<const uint4 *>(a.B + n * a.sbn + k0 + c);
+            *reinterpret_cast<uint4 *>(&Bs[r][c]) = vb;
+        }
+        __syncthreads();
+        const int kk = (lane >> 4) * 8;
+        bf16x8 af[4], bfr[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+            af[i] = *reinterpret_cast<const bf16x8 *>(&As[wm * 64 + i * 16 + (lane & 15)][kk]);
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn * 64 + j * 16 + (lane & 15)][kk]);
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int64_t row = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + e;
+                const int64_t col = n0 + wn * 64 + j * 16 + (lane & 15);
+                if (row >= a.M || col >= a.N)
+                    continue;
+                float v = acc[i][j][e];
+                if (a.epi == kEpiMask) {
+                    v = (a.zref[row * a.ldz + col] > 0.f) ? v : 0.f;
+                } else if (a.bias) {
+                    v += a.bias[col];
+                }
+                if (a.C)
+                    a.C[row * a.ldc + col] = v;
+                if (a.Cb)
+                    a.Cb[row * a.ldcb + col] = to_bf16(a.epi == kEpiRelu ? fmaxf(v, 0.f) : v);
+            }
+}
+
 // C[r][c] = sum_z P[z][r][c], z ascending
 __global__ void splitk_reduce_kernel(const float *P, int64_t splits, int32_t M, int32_t N, float *C,
                                      int64_t ldc)
@@ -179,6 +259,7 @@ __global__ void splitk_reduce_kernel(const float *P, int64_t splits, int32_t M, 
     if (idx >= (int64_t)M * N)
         return;
     float s = 0.f;
+#pragma unroll 8
     for (int64_t z = 0; z < splits; z++)
         s += P[z * M * N + idx];
     C[(idx / N) * ldc + idx % N] = s;
@@ -296,16 +377,20 @@ __global__ __launch_bounds__(320) void colsum_partial_kernel(const float *Xf, co
     part[(int64_t)blockIdx.x * width + c] = s;
 }
 
-__global__ void colsum_finish_kernel(const float *part, int64_t chunks, int32_t width, float *out,
-                                     int32_t cols, int32_t out_extra)
+// Stage 2: one workgroup per column; thread t adds chunks t, t + 256, ... in
+// order, then a fixed tree combines the threads (deterministic).
+__global__ __launch_bounds__(256) void colsum_finish_kernel(const float *part, int64_t chunks, int32_t width,
+                                                            float *out, int32_t cols, int32_t out_extra)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= width)
-        return;
+    __shared__ float red[4];
+    const int c = blockIdx.x;
     float s = 0.f;
-    for (int64_t g = 0; g < chunks; g++)
+#pragma unroll 4
+    for (int64_t g = threadIdx.x; g < chunks; g += 256)
         s += part[g * width + c];
-    out[c < cols ? c : out_extra] = s;
+    s = block_sum(s, red);
+    if (threadIdx.x == 0)
+        out[c < cols ? c : out_extra] = s;
 }
 
 // dZ1[r][c] = dS[r / n][c] * [Z1[r][c] > 0]   (fp32 and bf16)
@@ -517,7 +602,9 @@ int64_t split_count(int64_t K, int64_t cap)
     return s < 1 ? 1 : (s > cap ? cap : s);
 }
 
-constexpr int64_t kSplitCapW1 = 256, kSplitCapW = 64, kColChunks = 256;
+// split counts: enough workgroups to fill the chip, few enough partials that
+// the ordered reduction stays short; column sums use chunks of >= 16 rows
+constexpr int64_t kSplitCapW1 = 256, kSplitCapW = 32, kColChunks = 4096, kColRows = 16;
 
 size_t partial_floats(int64_t B, int64_t n)
 {
@@ -560,10 +647,23 @@ Work work_of(void *p, int64_t B, int64_t n, size_t *total)
     return w;
 }
 
+bool nt_eligible(const GemmArgs &a)
+{
+    auto aligned = [](const void *p) { return ((uintptr_t)p & 15u) == 0; };
+    return !a.P && a.sak == 1 && a.sbk == 1 && a.K % kKStep == 0 && a.N % kNtTile == 0 && a.sam % 8 == 0 &&
+           a.sbn % 8 == 0 && aligned(a.A) && aligned(a.B);
+}
+
 int gemm(const GemmArgs &a, hipStream_t st)
 {
     if (a.M <= 0 || a.N <= 0 || a.K <= 0)
         return KO_OK;
+    if (nt_eligible(a)) {
+        dim3 g((unsigned)((a.M + kNtTile - 1) / kNtTile), (unsigned)(a.N / kNtTile));
+        hipLaunchKernelGGL(gemm_nt_kernel, g, dim3(256), 0, st, a);
+        NN_LAUNCHED();
+        return KO_OK;
+    }
     dim3 grid((unsigned)((a.M + kTile - 1) / kTile), (unsigned)((a.N + kTile - 1) / kTile));
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, st, a);
     NN_LAUNCHED();
@@ -599,15 +699,14 @@ int gemm_splitk(GemmArgs a, float *P, int64_t cap, hipStream_t st)
 int colsum(const float *Xf, const uint16_t *Xb, int64_t ld, int64_t rows, int32_t cols, const float *wrow,
            bool with_w, float *out, int32_t out_extra, float *P, hipStream_t st)
 {
-    const int64_t chunks = std::min<int64_t>(kColChunks, std::max<int64_t>(1, rows / 64));
-    const int64_t chunk = (rows + chunks - 1) / chunks;
+    const int64_t chunk = std::max<int64_t>(kColRows, (rows + kColChunks - 1) / kColChunks);
     const int64_t used = (rows + chunk - 1) / chunk;
     const int32_t width = cols + (with_w ? 1 : 0);
     hipLaunchKernelGGL(colsum_partial_kernel, dim3((unsigned)used), dim3(320), 0, st, Xf, Xb, ld, rows, cols,
                        wrow, with_w ? 1 : 0, chunk, P);
     NN_LAUNCHED();
-    hipLaunchKernelGGL(colsum_finish_kernel, dim3((unsigned)((width + 255) / 256)), dim3(256), 0, st, P, used,
-                       width, out, cols, out_extra);
+    hipLaunchKernelGGL(colsum_finish_kernel, dim3((unsigned)width), dim3(256), 0, st, P, used, width, out, cols,
+                       out_extra);
     NN_LAUNCHED();
     return KO_OK;
 }

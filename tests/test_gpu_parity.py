@@ -310,3 +310,35 @@ def test_full_size_n10_all_orders_properties():
     r = ko.ko_rank_percentile(w.model, ks, h_order)
     assert r["makespan"] == ref
     assert (r["n_less"], r["n_equal"], r["n_greater"]) == (rec["n_less"], rec["n_equal"], rec["n_greater"])
+
+
+# ------------------------------------------------------------------ degenerate cases
+
+def test_identical_kernels_every_order_ties():
+    """A set of identical kernels: every launch order is the same sequence of
+    blocks, so all n! makespans are equal (and equal the oracle's)."""
+    w = synth.WORKLOADS[1]
+    k0 = synth.draw_set(1, 3)[:1]
+    ks = np.concatenate([k0] * 7)
+    say("identical kernels n=7")
+    ms, st, hist, _ = run_batch(w.model, [ks], ko.OrderSpec.all(), ref=[0], n_bins=8)
+    want = oracle.makespan(w.model.as_dict(), ks, list(range(7)))
+    assert np.all(ms == want) and len(ms) == math.factorial(7)
+    rec = st[0]
+    assert rec["min_makespan"] == rec["max_makespan"] == want
+    assert rec["argmin"] == 0 and rec["argmax"] == 0
+    assert int(hist[0][0]) == math.factorial(7) and int(hist[0][1:].sum()) == 0
+
+
+def test_blocks_on_distinct_cus_make_order_irrelevant():
+    """Total blocks <= N_CU with one block per CU: every block starts at
+    cycle 0 on its own CU, so the makespan is the longest block duration for
+    every order."""
+    model = synth.MI355X_MODEL
+    rng = np.random.default_rng(5)
+    ks = synth.draw_kernels(rng, 6, 10, 40)  # 6 kernels x <= 40 blocks <= 240 CUs
+    assert int(ks["n_tblk"].sum()) <= model.n_cu
+    say("blocks on distinct CUs")
+    ms, _, _, _ = run_batch(model, [ks], ko.OrderSpec.all())
+    _, dur = oracle.derive(model.as_dict(), ks)
+    assert np.all(ms == int(max(dur)))
