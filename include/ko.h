@@ -225,10 +225,24 @@ typedef struct ko_plan ko_plan;
 typedef struct ko_graph ko_graph;
 
 /* Launch configuration (16 bytes); zero fields take the defaults. */
+/* Engines of the simulation (all give identical results):
+ *   KO_ENGINE_WAVE   one wavefront per order, lanes own CUs (any model, n <= 20);
+ *   KO_ENGINE_LANES  one lane per order, the CUs' free resources held as runs
+ *                    of equal values (n <= 16, N_CU <= 256, registers per CU
+ *                    < 2^23, LDS per CU < 2^18 bytes, waves and blocks per CU
+ *                    < 128); work items whose orders outgrow its per-lane
+ *                    capacities are re-run by the wave engine;
+ *   KO_ENGINE_AUTO   the lane engine where it applies, else the wave engine. */
+enum { KO_ENGINE_AUTO = 0, KO_ENGINE_WAVE = 1, KO_ENGINE_LANES = 2 };
+
 typedef struct ko_launch_config {
     int32_t chunk_log2;  /* orders per work item = 2^chunk_log2 (1..20); 0 = automatic */
-    int32_t wg_per_cu;   /* persistent workgroups (4 waves each) per CU (1..64); 0 = 8 */
-    int32_t reserved[2];
+    int32_t wg_per_cu;   /* persistent workgroups (4 waves each) per CU (1..64); 0 = 8;
+                            the lane engine launches 4x as many one-wave workgroups */
+    int32_t engine;      /* KO_ENGINE_*; KO_EINVAL if LANES does not apply */
+    int32_t lane_entries; /* lane engine: group entries per lane (1..64); 0 = by set size
+                             (40 up to 8 kernels, 48 up to 12, 64 up to 16).  Fewer
+                             entries send more work items to the wave engine. */
 } ko_launch_config;
 
 /* ko_plan_create — prepare a batch as ko_simulate_batch takes it (same
@@ -255,6 +269,13 @@ int ko_plan_launch(ko_plan *plan, const int64_t *ref_makespan_dev, int64_t *make
 /* ko_plan_status — wait for hip_stream, then report the device status of the
  * plan's last launch (KO_EHIP for a malformed explicit order). */
 int ko_plan_status(ko_plan *plan, void *hip_stream);
+
+/* ko_plan_engine — the engine the plan runs (KO_ENGINE_WAVE or KO_ENGINE_LANES),
+ * its group entries per lane (0 for the wave engine) and, after waiting for
+ * hip_stream, how many work items the plan's last launch handed from the lane
+ * engine to the wave engine (any output may be NULL). */
+int ko_plan_engine(ko_plan *plan, int32_t *engine_out, int32_t *lane_entries_out, uint64_t *handed_over_out,
+                   void *hip_stream);
 
 /* ko_plan_destroy — wait for the device, free the plan (NULL is a no-op). */
 int ko_plan_destroy(ko_plan *plan);

@@ -40,6 +40,7 @@ KO_HEUR_FULL_SORT = 2
 
 EXPORTED = ("ko_heuristic_order", "ko_count_orders", "ko_simulate_batch", "ko_rank_percentile",
             "ko_sync", "ko_shutdown", "ko_plan_create", "ko_plan_info", "ko_plan_launch", "ko_plan_status",
+            "ko_plan_engine",
             "ko_plan_destroy", "ko_graph_capture", "ko_graph_launch", "ko_graph_destroy",
             "ko_sample_orders", "ko_topk_f32", "ko_kth_smallest_i64",
             "ko_set_kernel_timing", "ko_last_kernel_ms", "ko_hw_vgprs", "ko_hw_time_orders",
@@ -75,9 +76,13 @@ class KoRankResult(ctypes.Structure):
                 ("pct_strict", ctypes.c_double), ("pct_mid", ctypes.c_double)]
 
 
+# simulation engines (ko_launch_config.engine); all give identical results
+ENGINE_AUTO, ENGINE_WAVE, ENGINE_LANES = 0, 1, 2
+
+
 class KoLaunchConfig(ctypes.Structure):
     _fields_ = [("chunk_log2", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("engine", ctypes.c_int32), ("lane_entries", ctypes.c_int32)]
 
 
 class KoOrderSpec(ctypes.Structure):
@@ -135,11 +140,13 @@ def _L():
         lib.ko_plan_info.argtypes = [vp, _u64p, _u64p, _u64p, _i32p]
         lib.ko_plan_launch.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, vp]
         lib.ko_plan_status.argtypes = [vp, vp]
+        lib.ko_plan_engine.argtypes = [vp, _i32p, _i32p, _u64p, vp]
         lib.ko_plan_destroy.argtypes = [vp]
         lib.ko_graph_capture.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, vp, ctypes.POINTER(vp)]
         lib.ko_graph_launch.argtypes = [vp, vp]
         lib.ko_graph_destroy.argtypes = [vp]
-        for f in ("ko_plan_create", "ko_plan_info", "ko_plan_launch", "ko_plan_status", "ko_plan_destroy",
+        for f in ("ko_plan_create", "ko_plan_info", "ko_plan_launch", "ko_plan_status", "ko_plan_engine",
+                  "ko_plan_destroy",
                   "ko_graph_capture", "ko_graph_launch", "ko_graph_destroy"):
             getattr(lib, f).restype = ctypes.c_int
         lib.ko_sample_orders.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64,
@@ -363,13 +370,14 @@ def _outputs(ref_makespan, makespans, stats, hist, n_bins, total, n_sets):
 class Plan:
     """A batch prepared once (ko_plan_create) and launched many times."""
 
-    def __init__(self, gpu, kernels, set_offsets, spec: "OrderSpec", chunk_log2: int = 0, wg_per_cu: int = 0):
+    def __init__(self, gpu, kernels, set_offsets, spec: "OrderSpec", chunk_log2: int = 0, wg_per_cu: int = 0,
+                 engine: int = ENGINE_AUTO, lane_entries: int = 0):
         g = gpu_model(gpu)
         k = kernel_array(kernels)
         off = np.ascontiguousarray(set_offsets, dtype=np.int32)
         self.n_sets = len(off) - 1
         self._spec = spec.c_struct()  # keeps the rank table alive during create
-        cfg = KoLaunchConfig(int(chunk_log2), int(wg_per_cu))
+        cfg = KoLaunchConfig(int(chunk_log2), int(wg_per_cu), int(engine), int(lane_entries))
         h = ctypes.c_void_p()
         _check(_L().ko_plan_create(ctypes.byref(g), k.ctypes.data if len(k) else None, off.ctypes.data_as(_i32p),
                                    self.n_sets, ctypes.byref(self._spec), ctypes.byref(cfg), ctypes.byref(h)))
@@ -387,6 +395,14 @@ class Plan:
 
     def status(self, stream=None):
         _check(_L().ko_plan_status(self._h, _stream_handle(stream)))
+
+    def engine(self, stream=None):
+        """(engine, group entries per lane, work items the last launch handed
+        from the lane engine to the wave engine); waits for the stream."""
+        e, ent, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_uint64()
+        _check(_L().ko_plan_engine(self._h, ctypes.byref(e), ctypes.byref(ent), ctypes.byref(n),
+                                   _stream_handle(stream)))
+        return e.value, ent.value, n.value
 
     def capture(self, *, stream, ref_makespan=None, makespans=None, stats=None, hist=None, n_bins: int = 0):
         """A HIP graph of one launch with these outputs (stream: a created torch stream)."""

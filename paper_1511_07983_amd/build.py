@@ -2,7 +2,8 @@
 
     python paper_1511_07983_amd/build.py
 
-compiles csrc/ko_host.cpp and csrc/ko_sim.hip into paper_1511_07983_amd/libko.so,
+compiles csrc/ko_host.cpp, ko_sim.hip, ko_lanes.hip, ko_select.hip and ko_hw.hip into
+paper_1511_07983_amd/libko.so,
 and csrc/ko_nn.hip (the learned surrogate) into paper_1511_07983_amd/libko_nn.so.
 Host code is built with -ffp-contract=off so the binary64 scores of the
 launch-order heuristic are evaluated exactly as written.
@@ -36,6 +37,14 @@ DEVICE = [
 ]
 
 
+# Per-source device flags.  The lane kernel takes orders from an LDS cursor
+# inside lane-divergent code; with the atomic optimizer off each lane issues
+# its own atomic instead of a compiler-built wave scan and broadcast.
+EXTRA = {
+    "ko_lanes.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+}
+
+
 def _run(cmd):
     print("+", " ".join(cmd), flush=True)
     subprocess.check_call(cmd)
@@ -52,8 +61,10 @@ def build(verbose: bool = True) -> str:
     _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_select.hip"), "-o", sel_o])
     hw_o = os.path.join(objdir, "ko_hw.o")
     _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_hw.hip"), "-o", hw_o])
+    lanes_o = os.path.join(objdir, "ko_lanes.o")
+    _run([HIPCC, *COMMON, *DEVICE, *EXTRA["ko_lanes.hip"], "-c", os.path.join(CSRC, "ko_lanes.hip"), "-o", lanes_o])
     tmp = LIB + ".tmp"
-    _run([HIPCC, *DEVICE, "-shared", "-fPIC", host_o, sim_o, sel_o, hw_o, "-o", tmp])
+    _run([HIPCC, *DEVICE, "-shared", "-fPIC", host_o, sim_o, sel_o, hw_o, lanes_o, "-o", tmp])
     os.replace(tmp, LIB)
     nn_o = os.path.join(objdir, "ko_nn.o")
     _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_nn.hip"), "-o", nn_o])

@@ -68,6 +68,14 @@ struct SimArgs {
     Partial *partials;       // per item
     unsigned long long *item_counter;
     uint32_t *status;
+    // simulate_kernel only: take items from this list (item_list_count
+    // entries, a device word) instead of 0..n_items-1; null = no list
+    const uint32_t *item_list;
+    const unsigned long long *item_list_count;
+    // simulate_lanes_kernel only: work items whose orders exceeded the lane
+    // kernel's capacities are appended here (count in ovf_count)
+    uint32_t *ovf_list;
+    unsigned long long *ovf_count;
     // GPU model
     uint32_t n_cu;
     uint32_t cap_reg, cap_lds, cap_wave, cap_blk;
@@ -96,6 +104,15 @@ struct HistArgs {
 int launch_simulate(const SimArgs &a, int slots_per_lane, uint32_t group_slots, int grid,
                     void *stream);
 int launch_reduce(const ReduceArgs &a, void *stream);
+
+// Lane kernels (ko_lanes.hip): one order per lane, CU states as runs.  A set
+// class is the largest set size a variant takes (8, 12 or 16); each holds
+// lane_entry_cap(class) group entries per lane in LDS.
+constexpr uint32_t lane_entry_cap(int set_class)
+{
+    return set_class <= 8 ? 40u : (set_class <= 12 ? 48u : 64u);
+}
+int launch_simulate_lanes(const SimArgs &a, int set_class, uint32_t entries, int grid, void *stream);
 int launch_hist(const HistArgs &a, uint64_t n_blocks, void *stream);
 int launch_zero_u64(uint64_t *p, uint64_t count, void *stream);
 int device_cu_count(int *out);

@@ -357,6 +357,10 @@ int heuristic(const ko_gpu_model &g, const ko_kernel *k, int32_t n, uint32_t fla
 
 // ---------------------------------------------------------------- workspace
 
+// Device words of a batch: item cursor, items listed by the lane kernel,
+// cursor over that list, status word.
+constexpr size_t kCounterWords = 4;
+
 struct Workspace {
     int device = -1;
     bool ready = false;
@@ -370,7 +374,7 @@ struct Workspace {
     size_t partials_cap = 0;
     uint64_t *block_base = nullptr;
     size_t block_base_cap = 0;
-    unsigned long long *counter = nullptr;  // [0] item counter, [1] status word
+    unsigned long long *counter = nullptr;  // kCounterWords words, see DevTables
     int64_t *scratch_i64 = nullptr;          // rank_percentile: reference makespan
     uint8_t *scratch_order = nullptr;        // rank_percentile: the order
     ko_set_stats *scratch_stats = nullptr;   // rank_percentile: stats
@@ -434,7 +438,7 @@ int get_workspace(Workspace **out)
         w.device = dev;
         KO_HIP(hipDeviceGetAttribute(&w.cu_count, hipDeviceAttributeMultiprocessorCount, dev),
                "hipDeviceGetAttribute");
-        KO_HIP(hipMalloc((void **)&w.counter, 2 * sizeof(unsigned long long)), "hipMalloc");
+        KO_HIP(hipMalloc((void **)&w.counter, kCounterWords * sizeof(unsigned long long)), "hipMalloc");
         KO_HIP(hipMalloc((void **)&w.scratch_i64, sizeof(int64_t)), "hipMalloc");
         KO_HIP(hipMalloc((void **)&w.scratch_order, 64), "hipMalloc");
         KO_HIP(hipMalloc((void **)&w.scratch_stats, sizeof(ko_set_stats)), "hipMalloc");
@@ -444,7 +448,7 @@ int get_workspace(Workspace **out)
                "hipHostMalloc");
         KO_HIP(hipHostMalloc((void **)&w.ref_host, sizeof(int64_t), hipHostMallocDefault),
                "hipHostMalloc");
-        KO_HIP(hipMemset(w.counter, 0, 2 * sizeof(unsigned long long)), "hipMemset");
+        KO_HIP(hipMemset(w.counter, 0, kCounterWords * sizeof(unsigned long long)), "hipMemset");
         KO_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
         *w.status_host = 0;
         KO_HIP(hipEventCreateWithFlags(&w.staged, hipEventDisableTiming), "hipEventCreate");
@@ -571,7 +575,14 @@ struct BatchPlan {
     uint32_t max_n = 0;
     int slots = 1;        // CU slots per lane
     int grid = 1;         // workgroups of the simulate kernel
+    int lane_class = 0;   // lane kernel variant (largest set it takes), 0 = simulate_kernel only
+    int lane_grid = 0;    // workgroups (one wave each) of the lane kernel
+    uint32_t lane_entries = 0;  // group entries per lane, 0 = class default
 };
+
+// Per-item device memory of a batch: its Partial and one slot of the list of
+// items the lane kernel hands over to simulate_kernel.
+constexpr size_t kItemBytes = sizeof(ko::Partial) + sizeof(uint32_t);
 
 constexpr uint64_t kHistPerBlock = 1 << 16;
 
@@ -613,6 +624,17 @@ int radix_pass(Workspace &w, hipStream_t stream, uint32_t shift, uint64_t *prefi
                 (unsigned long long)*rem);
 }
 
+// The lane kernel packs a CU's free resources into two words (registers
+// below 2^23, LDS bytes below 2^18, waves and block slots below 128, CU index
+// below 2^8) and takes sets of up to 16 kernels.
+int lane_class_for(const ko_gpu_model &g, uint32_t max_n)
+{
+    if (g.n_cu > 256 || g.reg_cu >= (1 << 23) || g.lds_cu >= (1 << 18) || g.wave_cu > 127 || g.blk_cu > 127 ||
+        max_n > 16)
+        return 0;
+    return max_n <= 8 ? 8 : (max_n <= 12 ? 12 : 16);
+}
+
 int slots_for(int n_cu)
 {
     const int s = (n_cu + ko::kWave - 1) / ko::kWave;
@@ -625,7 +647,7 @@ int slots_for(int n_cu)
 // items to balance the persistent waves, few enough to keep partials small.
 int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *set_offsets,
               int32_t n_sets, const ko_order_spec *spec, int cu_count, uint64_t chunk_req, int wg_per_cu,
-              BatchPlan *plan)
+              int engine, BatchPlan *plan)
 {
     std::vector<uint64_t> per_set;
     int rc = count_orders(set_offsets, n_sets, spec, &per_set, &plan->total);
@@ -641,9 +663,18 @@ int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *
     }
     plan->slots = slots_for(gpu->n_cu);
     plan->grid = std::max(1, cu_count * wg_per_cu);
-    const uint64_t waves = (uint64_t)plan->grid * 4;
+    plan->lane_class = engine == KO_ENGINE_WAVE ? 0 : lane_class_for(*gpu, plan->max_n);
+    if (engine == KO_ENGINE_LANES && plan->lane_class == 0)
+        return fail(KO_EINVAL, "the lane engine takes sets of at most 16 kernels on at most 256 CUs");
+    plan->lane_grid = plan->grid * 4;
     uint64_t chunk = chunk_req;
-    if (chunk == 0) {
+    if (chunk == 0 && plan->lane_class) {
+        // about 4 items per resident wave (~12 per CU), each at least 2 orders per lane
+        const uint64_t waves = (uint64_t)std::max(1, cu_count) * 12;
+        chunk = pow2_at_least(std::max<uint64_t>(1, plan->total / (waves * 4)));
+        chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, 128), 8192);
+    } else if (chunk == 0) {
+        const uint64_t waves = (uint64_t)plan->grid * 4;
         chunk = pow2_at_least(std::max<uint64_t>(1, plan->total / (waves * 8)));
         chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, 16), 8192);
     }
@@ -681,8 +712,8 @@ struct DevTables {
     const ko::KernelRec *krec;
     const ko::SetRec *sets;
     const uint64_t *block_base;
-    ko::Partial *partials;
-    unsigned long long *counter;  // [0] item cursor, [1] status word
+    ko::Partial *partials;        // n_items Partials, then n_items uint32 list slots
+    unsigned long long *counter;  // [0] item cursor, [1] listed items, [2] list cursor, [3] status word
 };
 
 // Enqueue the device work of a batch on `stream`: cursor (and, when asked,
@@ -694,7 +725,7 @@ int enqueue_batch(const DevTables &t, const BatchPlan &p, const ko_gpu_model &gp
                   int64_t *makespans_dev, ko_set_stats *stats_dev, uint64_t *hist_dev, int32_t n_bins,
                   hipStream_t stream, hipEvent_t sim_begin, hipEvent_t sim_end)
 {
-    int e = ko::launch_zero_u64((uint64_t *)t.counter, reset_status ? 2 : 1, stream);
+    int e = ko::launch_zero_u64((uint64_t *)t.counter, reset_status ? 4 : 3, stream);
     if (e)
         return hip_fail((hipError_t)e, "zero counters");
     if (p.n_items > 0) {
@@ -711,7 +742,11 @@ int enqueue_batch(const DevTables &t, const BatchPlan &p, const ko_gpu_model &gp
         a.makespans = makespans_dev;
         a.partials = t.partials;
         a.item_counter = t.counter;
-        a.status = (uint32_t *)(t.counter + 1);
+        a.status = (uint32_t *)(t.counter + 3);
+        a.item_list = nullptr;
+        a.item_list_count = nullptr;
+        a.ovf_list = reinterpret_cast<uint32_t *>(t.partials + p.n_items);
+        a.ovf_count = t.counter + 1;
         a.n_cu = (uint32_t)gpu.n_cu;
         a.cap_reg = (uint32_t)gpu.reg_cu;
         a.cap_lds = (uint32_t)gpu.lds_cu;
@@ -720,9 +755,27 @@ int enqueue_batch(const DevTables &t, const BatchPlan &p, const ko_gpu_model &gp
         const int g = (int)std::min<uint64_t>((uint64_t)p.grid, (p.n_items + 3) / 4);
         if (sim_begin)
             KO_HIP(hipEventRecord(sim_begin, stream), "hipEventRecord");
-        e = ko::launch_simulate(a, p.slots, p.max_n, g, stream);
-        if (e)
-            return hip_fail((hipError_t)e, "simulate kernel launch");
+        if (p.lane_class) {
+            e = ko::launch_simulate_lanes(a, p.lane_class, p.lane_entries, p.lane_grid, stream);
+            if (e)
+                return hip_fail((hipError_t)e, "lane kernel launch");
+            // items listed by the lane kernel, again with simulate_kernel (a
+            // short launch that finds an empty list in the common case)
+            ko::SimArgs f = a;
+            f.item_list = a.ovf_list;
+            f.item_list_count = a.ovf_count;
+            f.item_counter = t.counter + 2;
+            f.ovf_list = nullptr;
+            f.ovf_count = nullptr;
+            const int fg = (int)std::min<uint64_t>((uint64_t)g, 256);
+            e = ko::launch_simulate(f, p.slots, p.max_n, fg, stream);
+            if (e)
+                return hip_fail((hipError_t)e, "simulate kernel launch");
+        } else {
+            e = ko::launch_simulate(a, p.slots, p.max_n, g, stream);
+            if (e)
+                return hip_fail((hipError_t)e, "simulate kernel launch");
+        }
         if (sim_end)
             KO_HIP(hipEventRecord(sim_end, stream), "hipEventRecord");
     }
@@ -767,7 +820,7 @@ int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernel
     if (rc)
         return rc;
     BatchPlan plan;
-    rc = make_plan(gpu, kernels, set_offsets, n_sets, spec, w.cu_count, 0, 8, &plan);
+    rc = make_plan(gpu, kernels, set_offsets, n_sets, spec, w.cu_count, 0, 8, KO_ENGINE_AUTO, &plan);
     if (rc)
         return rc;
     rc = check_status(w, false);
@@ -782,7 +835,7 @@ int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernel
         (rc = grow_device(w.done, (void **)&w.sets, &w.sets_cap, sbytes)) ||
         (rc = grow_device(w.done, (void **)&w.block_base, &w.block_base_cap, bbytes)) ||
         (rc = grow_device(w.done, (void **)&w.partials, &w.partials_cap,
-                          std::max<uint64_t>(plan.n_items, 1) * sizeof(ko::Partial))))
+                          std::max<uint64_t>(plan.n_items, 1) * kItemBytes)))
         return rc;
     // the previous call on any stream must be done with the workspace
     KO_HIP(hipStreamWaitEvent(stream, w.done, 0), "hipStreamWaitEvent");
@@ -815,7 +868,7 @@ int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernel
         return rc;
     if (timing)
         w.timed = true;
-    KO_HIP(hipMemcpyAsync(w.status_host, (const void *)(w.counter + 1), sizeof(uint32_t),
+    KO_HIP(hipMemcpyAsync(w.status_host, (const void *)(w.counter + 3), sizeof(uint32_t),
                           hipMemcpyDeviceToHost, stream),
            "hipMemcpyAsync");
     KO_HIP(hipEventRecord(w.done, stream), "hipEventRecord");
@@ -961,7 +1014,13 @@ int ko_plan_create(const ko_gpu_model *gpu, const ko_kernel *kernels, const int3
             return rc;
         uint64_t chunk = 0;
         int wg = 8;
+        int engine = KO_ENGINE_AUTO;
         if (config) {
+            if (config->engine < KO_ENGINE_AUTO || config->engine > KO_ENGINE_LANES)
+                return fail(KO_EINVAL, "config: engine %d unknown", config->engine);
+            engine = config->engine;
+            if (config->lane_entries < 0 || config->lane_entries > 64)
+                return fail(KO_EINVAL, "config: lane_entries %d outside 0..64", config->lane_entries);
             if (config->chunk_log2 < 0 || config->chunk_log2 > 20)
                 return fail(KO_EINVAL, "config: chunk_log2 %d outside 0..20", config->chunk_log2);
             if (config->wg_per_cu < 0 || config->wg_per_cu > 64)
@@ -981,28 +1040,30 @@ int ko_plan_create(const ko_gpu_model *gpu, const ko_kernel *kernels, const int3
         p->mode = spec->mode;
         p->seed = spec->seed;
         p->orders = spec->orders_dev;
-        rc = make_plan(gpu, kernels, set_offsets, n_sets, spec, w->cu_count, chunk, wg, &p->plan);
+        rc = make_plan(gpu, kernels, set_offsets, n_sets, spec, w->cu_count, chunk, wg, engine, &p->plan);
         if (rc) {
             delete p;
             return rc;
         }
+        if (config)
+            p->plan.lane_entries = (uint32_t)config->lane_entries;
         const size_t kbytes = p->plan.krec.size() * sizeof(ko::KernelRec);
         const size_t sbytes = p->plan.sets.size() * sizeof(ko::SetRec);
         const size_t bbytes = p->plan.block_base.size() * sizeof(uint64_t);
-        const size_t pbytes = std::max<uint64_t>(p->plan.n_items, 1) * sizeof(ko::Partial);
+        const size_t pbytes = std::max<uint64_t>(p->plan.n_items, 1) * kItemBytes;
         hipError_t e = hipSuccess;
         if ((e = hipMalloc((void **)&p->krec, std::max<size_t>(kbytes, 64))) != hipSuccess ||
             (e = hipMalloc((void **)&p->sets, std::max<size_t>(sbytes, 64))) != hipSuccess ||
             (e = hipMalloc((void **)&p->block_base, std::max<size_t>(bbytes, 64))) != hipSuccess ||
             (e = hipMalloc((void **)&p->partials, pbytes)) != hipSuccess ||
-            (e = hipMalloc((void **)&p->counter, 2 * sizeof(unsigned long long))) != hipSuccess) {
+            (e = hipMalloc((void **)&p->counter, kCounterWords * sizeof(unsigned long long))) != hipSuccess) {
             free_plan(p);
             return fail(KO_ENOMEM, "plan device allocation failed: %s", hipGetErrorString(e));
         }
         if ((kbytes && (e = hipMemcpy(p->krec, p->plan.krec.data(), kbytes, hipMemcpyHostToDevice)) != hipSuccess) ||
             (sbytes && (e = hipMemcpy(p->sets, p->plan.sets.data(), sbytes, hipMemcpyHostToDevice)) != hipSuccess) ||
             (e = hipMemcpy(p->block_base, p->plan.block_base.data(), bbytes, hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemset(p->counter, 0, 2 * sizeof(unsigned long long))) != hipSuccess ||
+            (e = hipMemset(p->counter, 0, kCounterWords * sizeof(unsigned long long))) != hipSuccess ||
             (e = hipDeviceSynchronize()) != hipSuccess) {
             free_plan(p);
             return hip_fail(e, "plan upload");
@@ -1057,12 +1118,36 @@ int ko_plan_status(ko_plan *plan, void *hip_stream)
         return rc;
     KO_HIP(hipStreamSynchronize((hipStream_t)hip_stream), "hipStreamSynchronize");
     uint32_t status = 0;
-    KO_HIP(hipMemcpy(&status, (const void *)(plan->counter + 1), sizeof status, hipMemcpyDeviceToHost),
+    KO_HIP(hipMemcpy(&status, (const void *)(plan->counter + 3), sizeof status, hipMemcpyDeviceToHost),
            "hipMemcpy");
     if (status & ko::kStatusBadOrder)
         return fail(KO_EHIP, "device status: an explicit order is not a permutation of 0..n-1");
     if (status)
         return fail(KO_EHIP, "device status 0x%x: internal inconsistency", status);
+    return KO_OK;
+}
+
+int ko_plan_engine(ko_plan *plan, int32_t *engine_out, int32_t *lane_entries_out, uint64_t *handed_over_out,
+                   void *hip_stream)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (!plan)
+        return fail(KO_EINVAL, "plan must not be NULL");
+    const int cls = plan->plan.lane_class;
+    const uint32_t ent = plan->plan.lane_entries;
+    if (engine_out)
+        *engine_out = cls ? KO_ENGINE_LANES : KO_ENGINE_WAVE;
+    if (lane_entries_out)
+        *lane_entries_out = cls ? (int32_t)(ent ? ent : ko::lane_entry_cap(cls)) : 0;
+    if (handed_over_out) {
+        int rc = check_plan_device(plan);
+        if (rc)
+            return rc;
+        KO_HIP(hipStreamSynchronize((hipStream_t)hip_stream), "hipStreamSynchronize");
+        unsigned long long n = 0;
+        KO_HIP(hipMemcpy(&n, (const void *)(plan->counter + 1), sizeof n, hipMemcpyDeviceToHost), "hipMemcpy");
+        *handed_over_out = n;
+    }
     return KO_OK;
 }
 

@@ -322,9 +322,11 @@ __global__ __launch_bounds__(256) void simulate_kernel(SimArgs a, uint32_t gslot
         // at the top of this loop: the lane-0 branch that stores the Partial
         // at the bottom can then be threaded around it, and lanes 1..63 would
         // re-enter the loop without lane 0 (and without a fetched item).
-        const uint64_t item = uniform64(atomicAdd(a.item_counter, lane == 0 ? 1ull : 0ull));
-        if (item >= a.n_items)
+        const uint64_t raw = uniform64(atomicAdd(a.item_counter, lane == 0 ? 1ull : 0ull));
+        const uint64_t limit = a.item_list ? (uint64_t)*a.item_list_count : a.n_items;
+        if (raw >= limit)
             break;
+        const uint64_t item = a.item_list ? (uint64_t)a.item_list[raw] : raw;
         // the set owning this item: the last set whose first item <= item
         int lo = 0, hi = a.n_sets - 1;
         while (lo < hi) {

@@ -19,7 +19,8 @@ mask:
 
 A cross-lane instruction reached with exec possibly PARTIAL is reported.
 Readlane of the VGPRs that hold SGPR spills is exempt (spill code is
-independent of exec), as are writelanes.
+independent of exec), as are writelanes; a saved mask that is spilled to a VGPR
+lane and reloaded keeps what it restores.
 """
 
 from __future__ import annotations
@@ -155,6 +156,56 @@ def _drop(tok: dict, regs):
     for r in regs:
         tok.pop(r, None)
         tok.pop(r - 1, None)
+        tok.pop(("half", r), None)
+
+
+def _lane_operand(op: str):
+    try:
+        return int(op, 0)
+    except ValueError:
+        return None
+
+
+def _spill_transfer(inst: Inst, tok: dict) -> bool:
+    """SGPR spills to VGPR lanes: a saved exec mask spilled with writelane and
+    reloaded with readlane keeps its token.  Returns True if handled."""
+    m, ops = inst.mnem, inst.ops
+    if m not in ("v_writelane_b32", "v_readlane_b32") or len(ops) != 3:
+        return False
+    lane = _lane_operand(ops[2])
+    if m == "v_writelane_b32":
+        v = re.fullmatch(r"v(\d+)", ops[0])
+        src = _sregs(ops[1])
+        if not v or lane is None:
+            return True
+        key = ("spill", int(v.group(1)), lane)
+        t = None
+        if len(src) == 1:
+            r = src[0]
+            if r in tok:
+                t = (tok[r], 0)
+            elif (r - 1) in tok:
+                t = (tok[r - 1], 1)
+        if t:
+            tok[key] = t
+        else:
+            tok.pop(key, None)
+        return True
+    dst = _sregs(ops[0])
+    v = re.fullmatch(r"v(\d+)", ops[1])
+    _drop(tok, dst)
+    if len(dst) != 1 or not v or lane is None:
+        return True
+    d = dst[0]
+    slot = tok.get(("spill", int(v.group(1)), lane))
+    if not slot:
+        return True
+    tok[("half", d)] = slot
+    lo = d if slot[1] == 0 else d - 1
+    a, b = tok.get(("half", lo)), tok.get(("half", lo + 1))
+    if a and b and a[0] == b[0] and a[1] == 0 and b[1] == 1:
+        tok[lo] = a[0]
+    return True
 
 
 def _transfer(inst: Inst, exec_state: str, tok: dict):
@@ -187,7 +238,8 @@ def _transfer(inst: Inst, exec_state: str, tok: dict):
         if m == "s_or_b64" and len(ops) == 3 and "exec" in ops[1:]:
             other = ops[2] if ops[1] == "exec" else ops[1]
             t = tok.get(_pair(other))
-            if t and t[0] == "save" and t[1] == FULL:
+            # OR-ing back a saved mask, or a copy of the whole exec, restores it
+            if t and t[0] in ("save", "copy") and t[1] == FULL:
                 return FULL
             return exec_state if exec_state == FULL else PARTIAL
         if m == "s_mov_b64" and len(ops) == 2:
@@ -223,6 +275,8 @@ def _transfer(inst: Inst, exec_state: str, tok: dict):
         _drop(tok, _sregs(ops[0]))
         if keep is not None and d is not None:
             tok[d] = keep
+        return exec_state
+    if _spill_transfer(inst, tok):
         return exec_state
     if m.startswith("v_") or m.startswith("s_load") or m.startswith("s_buffer_load"):
         for op in ops:

@@ -215,7 +215,9 @@ def test_plan_and_graph_reject_bad_arguments_before_device_work():
     assert lib.ko_plan_create(ctypes.byref(gpu), ks.ctypes.data, off.ctypes.data_as(ko._i32p), 1,
                               ctypes.byref(spec), ctypes.byref(cfg), ctypes.byref(out)) == ko.KO_EINVAL
     good = ko.gpu_model(synth.MI355X_MODEL)
-    for bad in (ko.KoLaunchConfig(21, 0), ko.KoLaunchConfig(-1, 0), ko.KoLaunchConfig(0, 65)):
+    for bad in (ko.KoLaunchConfig(21, 0), ko.KoLaunchConfig(-1, 0), ko.KoLaunchConfig(0, 65),
+                ko.KoLaunchConfig(0, 0, 3, 0), ko.KoLaunchConfig(0, 0, -1, 0), ko.KoLaunchConfig(0, 0, 2, 65),
+                ko.KoLaunchConfig(0, 0, 2, -1)):
         assert lib.ko_plan_create(ctypes.byref(good), ks.ctypes.data, off.ctypes.data_as(ko._i32p), 1,
                                   ctypes.byref(spec), ctypes.byref(bad), ctypes.byref(out)) == ko.KO_EINVAL
     assert lib.ko_plan_create(ctypes.byref(good), ks.ctypes.data, off.ctypes.data_as(ko._i32p), 1,
@@ -223,6 +225,7 @@ def test_plan_and_graph_reject_bad_arguments_before_device_work():
     assert lib.ko_plan_info(None, None, None, None, None) == ko.KO_EINVAL
     assert lib.ko_plan_launch(None, None, None, None, None, 0, None) == ko.KO_EINVAL
     assert lib.ko_plan_status(None, None) == ko.KO_EINVAL
+    assert lib.ko_plan_engine(None, None, None, None, None) == ko.KO_EINVAL
     assert lib.ko_graph_capture(None, None, None, None, None, 0, None, ctypes.byref(out)) == ko.KO_EINVAL
     assert lib.ko_graph_launch(None, None) == ko.KO_EINVAL
     assert lib.ko_plan_destroy(None) == ko.KO_OK

@@ -1,7 +1,7 @@
 """Compiled gfx950 assembly: wave collectives run with every lane active.
 
-The simulate, reduce and surrogate-output kernels exchange values between the
-lanes of a wave (readlane, readfirstlane, shuffles).  These tests compile the
+The simulate, lane-simulate, reduce and surrogate kernels exchange values
+between the lanes of a wave (readlane, readfirstlane, shuffles).  These tests compile the
 library sources to assembly with the build's own flags (CPU only, nothing is
 launched) and check, with the dataflow analysis of tests/isa_convergence.py,
 that no cross-lane instruction of those kernels can execute while some lanes
@@ -41,8 +41,8 @@ def _build_module():
 
 def _asm(src, out, extra_inc=()):
     b = _build_module()
-    cmd = [b.HIPCC, *b.COMMON, *b.DEVICE, *[f"-I{d}" for d in extra_inc],
-           "--cuda-device-only", "-S", src, "-o", out]
+    cmd = [b.HIPCC, *b.COMMON, *b.DEVICE, *b.EXTRA.get(os.path.basename(src), []),
+           *[f"-I{d}" for d in extra_inc], "--cuda-device-only", "-S", src, "-o", out]
     subprocess.run(cmd, check=True, capture_output=True)
     with open(out) as f:
         return f.read()
@@ -52,6 +52,12 @@ def _asm(src, out, extra_inc=()):
 def sim_report(tmp_path_factory):
     d = tmp_path_factory.mktemp("isa")
     return ic.check(_asm(os.path.join(CSRC, "ko_sim.hip"), str(d / "ko_sim.s")))
+
+
+@pytest.fixture(scope="module")
+def lanes_report(tmp_path_factory):
+    d = tmp_path_factory.mktemp("isa")
+    return ic.check(_asm(os.path.join(CSRC, "ko_lanes.hip"), str(d / "ko_lanes.s")))
 
 
 @pytest.fixture(scope="module")
@@ -72,6 +78,17 @@ def test_simulate_collectives_full_exec(sim_report, needle):
         bad, div_loops = sim_report[name]
         assert bad == [], (name, bad[:5])
         assert div_loops == 0, (name, div_loops)
+
+
+@pytest.mark.parametrize("needle", ["simulate_lanes_kernelILi12ELi8E", "simulate_lanes_kernelILi16ELi12E",
+                                    "simulate_lanes_kernelILi20ELi16E"])
+def test_lane_kernels_collectives_full_exec(lanes_report, needle):
+    """The lane kernels diverge by design (each lane runs its own order), so
+    their loops may be lane-divergent; every wave operation (item fetch,
+    statistics shuffles, overflow ballot) must still see all lanes."""
+    for name in _pick(lanes_report, needle):
+        bad, _ = lanes_report[name]
+        assert bad == [], (name, bad[:5])
 
 
 def test_reduce_collectives_full_exec(sim_report):
