@@ -38,12 +38,12 @@ OPS_PER_BLOCK = 13
 
 # HBM bytes per all-orders launch of the simulate kernel on the n=10 set, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs calibrated against a 256 MiB copy
-# (FETCH x 2.0, WRITE x 1.0; profiles/simulate_kernel4_n10_counters.md).  They
-# hold for the kernel sources they were measured on, identified by hash; any
-# change to those sources reports null until the counters are taken again.
-TRAFFIC_SOURCES = ("paper_1511_07983_amd/csrc/ko_sim.hip", "paper_1511_07983_amd/csrc/ko_orders.h",
-                   "paper_1511_07983_amd/csrc/ko_device.h")
-TRAFFIC_MEASURED = {"6364247cb140ad65": (153 + 33922) * 1024}
+# (profiles/ holds the summaries).  They hold for the kernel sources they were
+# measured on, identified by hash; any change to those sources reports null
+# until the counters are taken again.
+TRAFFIC_SOURCES = ("paper_1511_07983_amd/csrc/ko_sim.hip", "paper_1511_07983_amd/csrc/ko_lanes.hip",
+                   "paper_1511_07983_amd/csrc/ko_orders.h", "paper_1511_07983_amd/csrc/ko_device.h")
+TRAFFIC_MEASURED = {"3f79f4b722357fa2": int((302.0 * 2 + 29078.5) * 1024)}
 
 
 def measured_traffic():
@@ -101,8 +101,14 @@ def surrogate_leg(heldout: int) -> dict:
 
     from paper_1511_07983_amd import surrogate
     lines = []
+
+    def keep(text, flush=True):
+        rec = _json.loads(text)
+        lines.append(rec)
+        print(f"[bench] surrogate {rec.get('phase')} done", file=sys.stderr, flush=True)
+
     try:
-        surrogate.report(heldout=heldout, out=lambda text, flush=True: lines.append(_json.loads(text)))
+        surrogate.report(heldout=heldout, out=keep)
     except Exception as exc:  # keep the throughput line even if this leg fails
         return {"error": f"{type(exc).__name__}: {exc}"}
     train = next(l for l in lines if l.get("phase") == "train")
@@ -139,6 +145,16 @@ def main():
     off = [0, n]
     kernels = ko.kernel_array(ks)
     b_total = int(ks["n_tblk"].sum())
+
+    # the kernel the all-orders leg runs (the library picks the engine by set size)
+    probe = ko.Plan(w.model, kernels, off, ko.OrderSpec.sampled([1], 0))
+    engine = probe.engine()[0]
+    probe.close()
+    if engine == ko.ENGINE_LANES:
+        rc, gc = {8: (12, 8), 12: (16, 12), 16: (20, 16)}[8 if n <= 8 else (12 if n <= 12 else 16)]
+        kernel_name = f"ko::simulate_lanes_kernel<{rc}, {gc}>"
+    else:
+        kernel_name = "ko::simulate_kernel<4>"
 
     ms = torch.empty(N, dtype=torch.int64, device=dev)
     st = torch.empty(8, dtype=torch.int64, device=dev)
@@ -210,7 +226,7 @@ def main():
                    "histogram_bins": 1024},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "Top/s",
                      "frac": achieved / ALU_PEAK_TOPS, "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
-                     "kernel": "ko::simulate_kernel<4>", "kernel_ms": 1e3 * kernel_avg,
+                     "kernel": kernel_name, "kernel_ms": 1e3 * kernel_avg,
                      "ops_per_order": ops_per_order},
         "heuristic": {"order": ko.ko_heuristic_order(w.model, kernels), "pct_inclusive": pct,
                       "min_makespan": int(rec["min_makespan"]), "max_makespan": int(rec["max_makespan"])},

@@ -37,12 +37,8 @@ DEVICE = [
 ]
 
 
-# Per-source device flags.  The lane kernel takes orders from an LDS cursor
-# inside lane-divergent code; with the atomic optimizer off each lane issues
-# its own atomic instead of a compiler-built wave scan and broadcast.
-EXTRA = {
-    "ko_lanes.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
-}
+# Per-source device flags (none at present).
+EXTRA = {}
 
 
 def _run(cmd):
@@ -62,7 +58,8 @@ def build(verbose: bool = True) -> str:
     hw_o = os.path.join(objdir, "ko_hw.o")
     _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_hw.hip"), "-o", hw_o])
     lanes_o = os.path.join(objdir, "ko_lanes.o")
-    _run([HIPCC, *COMMON, *DEVICE, *EXTRA["ko_lanes.hip"], "-c", os.path.join(CSRC, "ko_lanes.hip"), "-o", lanes_o])
+    _run([HIPCC, *COMMON, *DEVICE, *EXTRA.get("ko_lanes.hip", []), "-c", os.path.join(CSRC, "ko_lanes.hip"),
+          "-o", lanes_o])
     tmp = LIB + ".tmp"
     _run([HIPCC, *DEVICE, "-shared", "-fPIC", host_o, sim_o, sel_o, hw_o, lanes_o, "-o", tmp])
     os.replace(tmp, LIB)

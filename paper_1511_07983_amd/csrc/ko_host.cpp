@@ -666,7 +666,9 @@ int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *
     plan->lane_class = engine == KO_ENGINE_WAVE ? 0 : lane_class_for(*gpu, plan->max_n);
     if (engine == KO_ENGINE_LANES && plan->lane_class == 0)
         return fail(KO_EINVAL, "the lane engine takes sets of at most 16 kernels on at most 256 CUs");
-    plan->lane_grid = plan->grid * 4;
+    // one-wave workgroups: as many as the chip holds at once (about 8 per CU
+    // at this kernel's register use), never more than there are items
+    plan->lane_grid = std::max(1, cu_count * std::min(wg_per_cu, 16));
     uint64_t chunk = chunk_req;
     if (chunk == 0 && plan->lane_class) {
         // about 4 items per resident wave (~12 per CU), each at least 2 orders per lane
@@ -756,7 +758,8 @@ int enqueue_batch(const DevTables &t, const BatchPlan &p, const ko_gpu_model &gp
         if (sim_begin)
             KO_HIP(hipEventRecord(sim_begin, stream), "hipEventRecord");
         if (p.lane_class) {
-            e = ko::launch_simulate_lanes(a, p.lane_class, p.lane_entries, p.lane_grid, stream);
+            const int lg = (int)std::min<uint64_t>((uint64_t)p.lane_grid, p.n_items);
+            e = ko::launch_simulate_lanes(a, p.lane_class, p.lane_entries, lg, stream);
             if (e)
                 return hip_fail((hipError_t)e, "lane kernel launch");
             // items listed by the lane kernel, again with simulate_kernel (a

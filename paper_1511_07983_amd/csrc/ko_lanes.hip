@@ -481,7 +481,13 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
         bool item_ovf = false;
         LaneSim<RC, GC> L;
         for (;;) {
-            const uint32_t i = atomicAdd(cursor, 1u);
+            // The cursor is indexed by a zero that passes through an empty asm
+            // in a vector register, so its address counts as lane-varying: the
+            // atomic stays one LDS atomic per active lane instead of becoming
+            // a compiler-built scan and broadcast inside this divergent loop.
+            uint32_t zero = 0;
+            asm volatile("" : "+v"(zero));
+            const uint32_t i = atomicAdd(cursor + zero, 1u);
             if ((uint64_t)i >= count)
                 break;
             uint64_t perm;
