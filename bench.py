@@ -151,7 +151,7 @@ def main():
     engine = probe.engine()[0]
     probe.close()
     if engine == ko.ENGINE_LANES:
-        rc, gc = {8: (12, 8), 12: (16, 12), 16: (20, 16)}[8 if n <= 8 else (12 if n <= 12 else 16)]
+        rc, gc = (12, 8) if n <= 8 else (12, 10) if n <= 10 else (16, 12) if n <= 12 else (20, 16)
         kernel_name = f"ko::simulate_lanes_kernel<{rc}, {gc}>"
     else:
         kernel_name = "ko::simulate_kernel<4>"

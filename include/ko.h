@@ -238,10 +238,11 @@ enum { KO_ENGINE_AUTO = 0, KO_ENGINE_WAVE = 1, KO_ENGINE_LANES = 2 };
 typedef struct ko_launch_config {
     int32_t chunk_log2;  /* orders per work item = 2^chunk_log2 (1..20); 0 = automatic */
     int32_t wg_per_cu;   /* persistent workgroups (4 waves each) per CU (1..64); 0 = 8;
-                            the lane engine launches 4x as many one-wave workgroups */
+                            the lane engine launches 2x as many one-wave workgroups
+                            (at most 32 per CU) */
     int32_t engine;      /* KO_ENGINE_*; KO_EINVAL if LANES does not apply */
     int32_t lane_entries; /* lane engine: group entries per lane (1..64); 0 = by set size
-                             (40 up to 8 kernels, 48 up to 12, 64 up to 16).  Fewer
+                             (40 up to 10 kernels, 48 up to 12, 64 up to 16).  Fewer
                              entries send more work items to the wave engine. */
 } ko_launch_config;
 
@@ -272,10 +273,12 @@ int ko_plan_status(ko_plan *plan, void *hip_stream);
 
 /* ko_plan_engine — the engine the plan runs (KO_ENGINE_WAVE or KO_ENGINE_LANES),
  * its group entries per lane (0 for the wave engine) and, after waiting for
- * hip_stream, how many work items the plan's last launch handed from the lane
- * engine to the wave engine (any output may be NULL). */
-int ko_plan_engine(ko_plan *plan, int32_t *engine_out, int32_t *lane_entries_out, uint64_t *handed_over_out,
-                   void *hip_stream);
+ * hip_stream, what the plan's last launch passed from the lane engine to the
+ * wave engine: orders evaluated one wavefront each (spilled_out, counting
+ * those the record list could not hold) and work items re-run whole
+ * (handed_over_out).  Any output may be NULL. */
+int ko_plan_engine(ko_plan *plan, int32_t *engine_out, int32_t *lane_entries_out, uint64_t *spilled_out,
+                   uint64_t *handed_over_out, void *hip_stream);
 
 /* ko_plan_destroy — wait for the device, free the plan (NULL is a no-op). */
 int ko_plan_destroy(ko_plan *plan);

@@ -140,7 +140,7 @@ def _L():
         lib.ko_plan_info.argtypes = [vp, _u64p, _u64p, _u64p, _i32p]
         lib.ko_plan_launch.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, vp]
         lib.ko_plan_status.argtypes = [vp, vp]
-        lib.ko_plan_engine.argtypes = [vp, _i32p, _i32p, _u64p, vp]
+        lib.ko_plan_engine.argtypes = [vp, _i32p, _i32p, _u64p, _u64p, vp]
         lib.ko_plan_destroy.argtypes = [vp]
         lib.ko_graph_capture.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, vp, ctypes.POINTER(vp)]
         lib.ko_graph_launch.argtypes = [vp, vp]
@@ -397,12 +397,12 @@ class Plan:
         _check(_L().ko_plan_status(self._h, _stream_handle(stream)))
 
     def engine(self, stream=None):
-        """(engine, group entries per lane, work items the last launch handed
-        from the lane engine to the wave engine); waits for the stream."""
-        e, ent, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_uint64()
-        _check(_L().ko_plan_engine(self._h, ctypes.byref(e), ctypes.byref(ent), ctypes.byref(n),
+        """(engine, group entries per lane, orders and whole work items the last
+        launch passed from the lane engine to the wave engine); waits for the stream."""
+        e, ent, sp, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_L().ko_plan_engine(self._h, ctypes.byref(e), ctypes.byref(ent), ctypes.byref(sp), ctypes.byref(n),
                                    _stream_handle(stream)))
-        return e.value, ent.value, n.value
+        return e.value, ent.value, sp.value, n.value
 
     def capture(self, *, stream, ref_makespan=None, makespans=None, stats=None, hist=None, n_bins: int = 0):
         """A HIP graph of one launch with these outputs (stream: a created torch stream)."""

@@ -51,6 +51,17 @@ struct Partial {
 
 enum : int32_t { kModeAll = 0, kModeRange = 1, kModeExplicit = 2, kModeSampled = 3 };
 
+// One order a lane of the lane kernel gave up on (it outgrew the lane's
+// capacities).  spill_kernel evaluates it with the wave engine and
+// reduce_kernel folds it into its set's statistics.  32 bytes.
+struct SpillRec {
+    uint32_t set;       // batch index of its set
+    uint32_t item;      // its work item
+    uint64_t sample;    // index of the order among its set's orders
+    uint64_t pos;       // its slot in the makespan array
+    int64_t makespan;   // written by spill_kernel
+};
+
 // Device status bits (OR-ed into the workspace status word).
 enum : uint32_t { kStatusGroupOverflow = 1u, kStatusBadOrder = 2u };
 
@@ -72,10 +83,17 @@ struct SimArgs {
     // entries, a device word) instead of 0..n_items-1; null = no list
     const uint32_t *item_list;
     const unsigned long long *item_list_count;
-    // simulate_lanes_kernel only: work items whose orders exceeded the lane
-    // kernel's capacities are appended here (count in ovf_count)
+    // simulate_lanes_kernel only: orders that exceeded a lane's capacities
+    // are recorded in spill (count in spill_count, at most spill_cap); the
+    // work items of orders that found the record list full are appended to
+    // ovf_list (count in ovf_count) and marked in handed_bits, and then re-run
+    // whole by simulate_kernel.  spill_kernel reads the records and the bits.
     uint32_t *ovf_list;
     unsigned long long *ovf_count;
+    SpillRec *spill;
+    unsigned long long *spill_count;
+    uint64_t spill_cap;
+    uint32_t *handed_bits;
     // GPU model
     uint32_t n_cu;
     uint32_t cap_reg, cap_lds, cap_wave, cap_blk;
@@ -84,9 +102,16 @@ struct SimArgs {
 struct ReduceArgs {
     const SetRec *sets;
     int32_t n_sets;
+    int32_t mode;
     uint64_t chunk;
     const Partial *partials;
     void *stats;             // ko_set_stats[n_sets] (layout-compatible with Partial)
+    const int64_t *ref;      // per set, or null
+    // orders the lane kernel spilled (null when the wave engine ran alone)
+    const SpillRec *spill;
+    const unsigned long long *spill_count;
+    uint64_t spill_cap;
+    const uint32_t *handed_bits;
 };
 
 struct HistArgs {
@@ -104,13 +129,15 @@ struct HistArgs {
 int launch_simulate(const SimArgs &a, int slots_per_lane, uint32_t group_slots, int grid,
                     void *stream);
 int launch_reduce(const ReduceArgs &a, void *stream);
+// Spilled orders of the lane kernel, one wavefront per order (ko_sim.hip).
+int launch_spill(const SimArgs &a, int slots_per_lane, uint32_t group_slots, int grid, void *stream);
 
 // Lane kernels (ko_lanes.hip): one order per lane, CU states as runs.  A set
-// class is the largest set size a variant takes (8, 12 or 16); each holds
+// class is the largest set size a variant takes (8, 10, 12 or 16); each holds
 // lane_entry_cap(class) group entries per lane in LDS.
 constexpr uint32_t lane_entry_cap(int set_class)
 {
-    return set_class <= 8 ? 40u : (set_class <= 12 ? 48u : 64u);
+    return set_class <= 10 ? 40u : (set_class <= 12 ? 48u : 64u);
 }
 int launch_simulate_lanes(const SimArgs &a, int set_class, uint32_t entries, int grid, void *stream);
 int launch_hist(const HistArgs &a, uint64_t n_blocks, void *stream);

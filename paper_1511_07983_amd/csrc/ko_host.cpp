@@ -357,9 +357,11 @@ int heuristic(const ko_gpu_model &g, const ko_kernel *k, int32_t n, uint32_t fla
 
 // ---------------------------------------------------------------- workspace
 
-// Device words of a batch: item cursor, items listed by the lane kernel,
-// cursor over that list, status word.
-constexpr size_t kCounterWords = 4;
+// Device words of a batch: item cursor, items handed from the lane kernel to
+// simulate_kernel, cursor over that list, spilled orders, cursor over them,
+// status word (last, so that a launch can reset the others alone).
+constexpr size_t kCounterWords = 6;
+constexpr size_t kStatusWord = 5;
 
 struct Workspace {
     int device = -1;
@@ -578,11 +580,30 @@ struct BatchPlan {
     int lane_class = 0;   // lane kernel variant (largest set it takes), 0 = simulate_kernel only
     int lane_grid = 0;    // workgroups (one wave each) of the lane kernel
     uint32_t lane_entries = 0;  // group entries per lane, 0 = class default
+    uint64_t spill_cap = 1;     // records of spilled orders
 };
 
-// Per-item device memory of a batch: its Partial and one slot of the list of
-// items the lane kernel hands over to simulate_kernel.
-constexpr size_t kItemBytes = sizeof(ko::Partial) + sizeof(uint32_t);
+// Per-batch device memory after the counters: n_items Partials, the list of
+// items handed over whole (n_items uint32), their bitmap, and the records of
+// spilled orders (at most kSpillCap).
+constexpr uint64_t kSpillCap = 1 << 16;
+
+struct ItemArea {
+    size_t list_off = 0, bits_off = 0, spill_off = 0, bytes = 0;
+    uint64_t bit_words = 0;  // 64-bit words of the bitmap
+};
+
+ItemArea item_area(uint64_t n_items, uint64_t spill_cap)
+{
+    ItemArea r;
+    const uint64_t items = std::max<uint64_t>(n_items, 1);
+    r.list_off = items * sizeof(ko::Partial);
+    r.bits_off = (r.list_off + items * sizeof(uint32_t) + 255) & ~(size_t)255;
+    r.bit_words = (items + 63) / 64;
+    r.spill_off = (r.bits_off + r.bit_words * 8 + 255) & ~(size_t)255;
+    r.bytes = r.spill_off + std::max<uint64_t>(spill_cap, 1) * sizeof(ko::SpillRec);
+    return r;
+}
 
 constexpr uint64_t kHistPerBlock = 1 << 16;
 
@@ -632,7 +653,7 @@ int lane_class_for(const ko_gpu_model &g, uint32_t max_n)
     if (g.n_cu > 256 || g.reg_cu >= (1 << 23) || g.lds_cu >= (1 << 18) || g.wave_cu > 127 || g.blk_cu > 127 ||
         max_n > 16)
         return 0;
-    return max_n <= 8 ? 8 : (max_n <= 12 ? 12 : 16);
+    return max_n <= 8 ? 8 : (max_n <= 10 ? 10 : (max_n <= 12 ? 12 : 16));
 }
 
 int slots_for(int n_cu)
@@ -666,15 +687,16 @@ int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *
     plan->lane_class = engine == KO_ENGINE_WAVE ? 0 : lane_class_for(*gpu, plan->max_n);
     if (engine == KO_ENGINE_LANES && plan->lane_class == 0)
         return fail(KO_EINVAL, "the lane engine takes sets of at most 16 kernels on at most 256 CUs");
-    // one-wave workgroups: as many as the chip holds at once (about 8 per CU
-    // at this kernel's register use), never more than there are items
-    plan->lane_grid = std::max(1, cu_count * std::min(wg_per_cu, 16));
+    // one-wave workgroups, at least as many as the chip holds at once (8 to 12
+    // per CU at these kernels' register use), never more than there are items
+    plan->lane_grid = std::max(1, cu_count * std::min(2 * wg_per_cu, 32));
     uint64_t chunk = chunk_req;
     if (chunk == 0 && plan->lane_class) {
-        // about 4 items per resident wave (~12 per CU), each at least 2 orders per lane
+        // at most 256 orders (4 per lane; measured best on the n=10 and batch
+        // workloads), fewer when that leaves under 4 items per resident wave
         const uint64_t waves = (uint64_t)std::max(1, cu_count) * 12;
         chunk = pow2_at_least(std::max<uint64_t>(1, plan->total / (waves * 4)));
-        chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, 128), 8192);
+        chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, 64), 256);
     } else if (chunk == 0) {
         const uint64_t waves = (uint64_t)plan->grid * 4;
         chunk = pow2_at_least(std::max<uint64_t>(1, plan->total / (waves * 8)));
@@ -684,6 +706,7 @@ int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *
     if (plan->total / chunk > max_items)
         chunk = pow2_at_least((plan->total + max_items - 1) / max_items);
     plan->chunk = chunk;
+    plan->spill_cap = plan->lane_class ? std::max<uint64_t>(1, std::min<uint64_t>(plan->total, kSpillCap)) : 1;
     uint64_t out_base = 0, item_base = 0, list_base = 0, hist_base = 0;
     plan->sets.resize(n_sets);
     plan->block_base.resize(n_sets + 1);
@@ -714,8 +737,8 @@ struct DevTables {
     const ko::KernelRec *krec;
     const ko::SetRec *sets;
     const uint64_t *block_base;
-    ko::Partial *partials;        // n_items Partials, then n_items uint32 list slots
-    unsigned long long *counter;  // [0] item cursor, [1] listed items, [2] list cursor, [3] status word
+    ko::Partial *partials;        // start of the batch's item area (item_area)
+    unsigned long long *counter;  // kCounterWords words
 };
 
 // Enqueue the device work of a batch on `stream`: cursor (and, when asked,
@@ -727,9 +750,18 @@ int enqueue_batch(const DevTables &t, const BatchPlan &p, const ko_gpu_model &gp
                   int64_t *makespans_dev, ko_set_stats *stats_dev, uint64_t *hist_dev, int32_t n_bins,
                   hipStream_t stream, hipEvent_t sim_begin, hipEvent_t sim_end)
 {
-    int e = ko::launch_zero_u64((uint64_t *)t.counter, reset_status ? 4 : 3, stream);
+    int e = ko::launch_zero_u64((uint64_t *)t.counter, reset_status ? kCounterWords : kStatusWord, stream);
     if (e)
         return hip_fail((hipError_t)e, "zero counters");
+    const ItemArea area = item_area(p.n_items, p.spill_cap);
+    char *base = reinterpret_cast<char *>(t.partials);
+    uint32_t *handed_bits = reinterpret_cast<uint32_t *>(base + area.bits_off);
+    ko::SpillRec *spill = reinterpret_cast<ko::SpillRec *>(base + area.spill_off);
+    if (p.lane_class && p.n_items > 0) {
+        e = ko::launch_zero_u64(reinterpret_cast<uint64_t *>(handed_bits), area.bit_words, stream);
+        if (e)
+            return hip_fail((hipError_t)e, "zero item bitmap");
+    }
     if (p.n_items > 0) {
         ko::SimArgs a;
         a.krec = t.krec;
@@ -744,11 +776,15 @@ int enqueue_batch(const DevTables &t, const BatchPlan &p, const ko_gpu_model &gp
         a.makespans = makespans_dev;
         a.partials = t.partials;
         a.item_counter = t.counter;
-        a.status = (uint32_t *)(t.counter + 3);
+        a.status = (uint32_t *)(t.counter + kStatusWord);
         a.item_list = nullptr;
         a.item_list_count = nullptr;
-        a.ovf_list = reinterpret_cast<uint32_t *>(t.partials + p.n_items);
+        a.ovf_list = reinterpret_cast<uint32_t *>(base + area.list_off);
         a.ovf_count = t.counter + 1;
+        a.spill = spill;
+        a.spill_count = t.counter + 3;
+        a.spill_cap = p.spill_cap;
+        a.handed_bits = handed_bits;
         a.n_cu = (uint32_t)gpu.n_cu;
         a.cap_reg = (uint32_t)gpu.reg_cu;
         a.cap_lds = (uint32_t)gpu.lds_cu;
@@ -762,15 +798,22 @@ int enqueue_batch(const DevTables &t, const BatchPlan &p, const ko_gpu_model &gp
             e = ko::launch_simulate_lanes(a, p.lane_class, p.lane_entries, lg, stream);
             if (e)
                 return hip_fail((hipError_t)e, "lane kernel launch");
-            // items listed by the lane kernel, again with simulate_kernel (a
-            // short launch that finds an empty list in the common case)
+            // orders the lanes spilled, with the wave engine (a short launch
+            // that finds no record in the common case)
+            const int fg = (int)std::min<uint64_t>((uint64_t)g, 256);
+            ko::SimArgs sp = a;
+            sp.item_counter = t.counter + 4;
+            e = ko::launch_spill(sp, p.slots, p.max_n, fg, stream);
+            if (e)
+                return hip_fail((hipError_t)e, "spill kernel launch");
+            // items handed over whole, again with simulate_kernel (also empty
+            // in the common case)
             ko::SimArgs f = a;
             f.item_list = a.ovf_list;
             f.item_list_count = a.ovf_count;
             f.item_counter = t.counter + 2;
             f.ovf_list = nullptr;
             f.ovf_count = nullptr;
-            const int fg = (int)std::min<uint64_t>((uint64_t)g, 256);
             e = ko::launch_simulate(f, p.slots, p.max_n, fg, stream);
             if (e)
                 return hip_fail((hipError_t)e, "simulate kernel launch");
@@ -786,9 +829,16 @@ int enqueue_batch(const DevTables &t, const BatchPlan &p, const ko_gpu_model &gp
         ko::ReduceArgs r;
         r.sets = t.sets;
         r.n_sets = n_sets;
+        r.mode = mode;
         r.chunk = p.chunk;
         r.partials = t.partials;
         r.stats = stats_dev;
+        r.ref = ref_dev;
+        const bool lanes = p.lane_class && p.n_items > 0;
+        r.spill = lanes ? spill : nullptr;
+        r.spill_count = lanes ? t.counter + 3 : nullptr;
+        r.spill_cap = p.spill_cap;
+        r.handed_bits = lanes ? handed_bits : nullptr;
         e = ko::launch_reduce(r, stream);
         if (e)
             return hip_fail((hipError_t)e, "reduce kernel launch");
@@ -838,7 +888,7 @@ int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernel
         (rc = grow_device(w.done, (void **)&w.sets, &w.sets_cap, sbytes)) ||
         (rc = grow_device(w.done, (void **)&w.block_base, &w.block_base_cap, bbytes)) ||
         (rc = grow_device(w.done, (void **)&w.partials, &w.partials_cap,
-                          std::max<uint64_t>(plan.n_items, 1) * kItemBytes)))
+                          item_area(plan.n_items, plan.spill_cap).bytes)))
         return rc;
     // the previous call on any stream must be done with the workspace
     KO_HIP(hipStreamWaitEvent(stream, w.done, 0), "hipStreamWaitEvent");
@@ -871,7 +921,7 @@ int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernel
         return rc;
     if (timing)
         w.timed = true;
-    KO_HIP(hipMemcpyAsync(w.status_host, (const void *)(w.counter + 3), sizeof(uint32_t),
+    KO_HIP(hipMemcpyAsync(w.status_host, (const void *)(w.counter + kStatusWord), sizeof(uint32_t),
                           hipMemcpyDeviceToHost, stream),
            "hipMemcpyAsync");
     KO_HIP(hipEventRecord(w.done, stream), "hipEventRecord");
@@ -1053,7 +1103,7 @@ int ko_plan_create(const ko_gpu_model *gpu, const ko_kernel *kernels, const int3
         const size_t kbytes = p->plan.krec.size() * sizeof(ko::KernelRec);
         const size_t sbytes = p->plan.sets.size() * sizeof(ko::SetRec);
         const size_t bbytes = p->plan.block_base.size() * sizeof(uint64_t);
-        const size_t pbytes = std::max<uint64_t>(p->plan.n_items, 1) * kItemBytes;
+        const size_t pbytes = item_area(p->plan.n_items, p->plan.spill_cap).bytes;
         hipError_t e = hipSuccess;
         if ((e = hipMalloc((void **)&p->krec, std::max<size_t>(kbytes, 64))) != hipSuccess ||
             (e = hipMalloc((void **)&p->sets, std::max<size_t>(sbytes, 64))) != hipSuccess ||
@@ -1121,7 +1171,7 @@ int ko_plan_status(ko_plan *plan, void *hip_stream)
         return rc;
     KO_HIP(hipStreamSynchronize((hipStream_t)hip_stream), "hipStreamSynchronize");
     uint32_t status = 0;
-    KO_HIP(hipMemcpy(&status, (const void *)(plan->counter + 3), sizeof status, hipMemcpyDeviceToHost),
+    KO_HIP(hipMemcpy(&status, (const void *)(plan->counter + kStatusWord), sizeof status, hipMemcpyDeviceToHost),
            "hipMemcpy");
     if (status & ko::kStatusBadOrder)
         return fail(KO_EHIP, "device status: an explicit order is not a permutation of 0..n-1");
@@ -1130,8 +1180,8 @@ int ko_plan_status(ko_plan *plan, void *hip_stream)
     return KO_OK;
 }
 
-int ko_plan_engine(ko_plan *plan, int32_t *engine_out, int32_t *lane_entries_out, uint64_t *handed_over_out,
-                   void *hip_stream)
+int ko_plan_engine(ko_plan *plan, int32_t *engine_out, int32_t *lane_entries_out, uint64_t *spilled_out,
+                   uint64_t *handed_over_out, void *hip_stream)
 {
     std::lock_guard<std::mutex> lock(g_mutex);
     if (!plan)
@@ -1142,14 +1192,17 @@ int ko_plan_engine(ko_plan *plan, int32_t *engine_out, int32_t *lane_entries_out
         *engine_out = cls ? KO_ENGINE_LANES : KO_ENGINE_WAVE;
     if (lane_entries_out)
         *lane_entries_out = cls ? (int32_t)(ent ? ent : ko::lane_entry_cap(cls)) : 0;
-    if (handed_over_out) {
+    if (spilled_out || handed_over_out) {
         int rc = check_plan_device(plan);
         if (rc)
             return rc;
         KO_HIP(hipStreamSynchronize((hipStream_t)hip_stream), "hipStreamSynchronize");
-        unsigned long long n = 0;
-        KO_HIP(hipMemcpy(&n, (const void *)(plan->counter + 1), sizeof n, hipMemcpyDeviceToHost), "hipMemcpy");
-        *handed_over_out = n;
+        unsigned long long c[kCounterWords] = {};
+        KO_HIP(hipMemcpy(c, (const void *)plan->counter, sizeof c, hipMemcpyDeviceToHost), "hipMemcpy");
+        if (spilled_out)
+            *spilled_out = c[3];
+        if (handed_over_out)
+            *handed_over_out = c[1];
     }
     return KO_OK;
 }

@@ -29,9 +29,13 @@
 // is the one the per-CU kernel computes; only the storage is compressed.
 //
 // Capacities are fixed per instantiation (RC runs, GC groups, E entries).
-// An order that would exceed one is abandoned and its work item listed; the
-// host then runs simulate_kernel over the listed items, which rewrites their
-// makespans and partial, so results never depend on the capacities.
+// A lane gives up on an order that would exceed one and writes a spill record
+// (set, item, order index, makespan slot); spill_kernel then evaluates the
+// recorded orders with the wave engine, one wavefront per order, and
+// reduce_kernel folds them into their sets' statistics.  Only if the record
+// list is full is the whole work item listed and marked, and re-run by
+// simulate_kernel, which rewrites its makespans and partial (its records are
+// then ignored).  Results never depend on the capacities.
 //
 // A lane that finishes an order takes the next one of the work item from a
 // cursor in LDS, so the wave keeps all lanes busy until the item runs dry.
@@ -112,9 +116,7 @@ struct LaneSim {
     uint64_t gm[GC];
     uint64_t used;
     uint64_t t;
-    uint32_t ptr, pos, k, rem;
-    uint32_t u_reg, u_lds, u_wave, ua, ub, dur;
-    float i_reg, i_lds, i_wave;
+    uint32_t ptr, pos, k, rem;  // the front kernel's parameters are read from the LDS table
     bool ovf;
 
     __device__ __forceinline__ uint32_t end_of(int j, uint32_t n_cu) const
@@ -125,15 +127,6 @@ struct LaneSim {
     __device__ __forceinline__ void load_kernel(const uint32_t *tab, uint32_t kk)
     {
         k = kk;
-        ua = tab[kTUa + kk];
-        ub = tab[kTUb + kk];
-        u_reg = tab[kTReg + kk];
-        u_lds = tab[kTLds + kk];
-        u_wave = tab[kTWave + kk];
-        i_reg = __uint_as_float(tab[kTIReg + kk]);
-        i_lds = __uint_as_float(tab[kTILds + kk]);
-        i_wave = __uint_as_float(tab[kTIWave + kk]);
-        dur = tab[kTDur + kk];
         rem = tab[kTBlk + kk];
     }
 
@@ -220,9 +213,13 @@ struct LaneSim {
 
     // One bulk step of the front kernel at the current cycle.  Returns false
     // when no block of it fits anywhere.
-    __device__ __forceinline__ bool bulk_step(uint32_t n_cu, uint32_t *ent, uint32_t ecap_mask_bits)
+    __device__ __forceinline__ bool bulk_step(uint32_t n_cu, const uint32_t *tab, uint32_t *ent,
+                                              uint32_t ecap_mask_bits)
     {
         const uint32_t lane = lane_no();
+        const uint32_t u_reg = tab[kTReg + k], u_lds = tab[kTLds + k], u_wave = tab[kTWave + k];
+        const float i_reg = __uint_as_float(tab[kTIReg + k]), i_lds = __uint_as_float(tab[kTILds + k]),
+                    i_wave = __uint_as_float(tab[kTIWave + k]);
         uint32_t T = 0, cmax = 0;
 #pragma unroll
         for (int j = 0; j < RC; j++) {
@@ -299,16 +296,6 @@ struct LaneSim {
         split(c1, n_cu);
         if (ovf)
             return false;
-        // a free group slot (live groups never exceed the set size)
-        int g = -1;
-#pragma unroll
-        for (int s = GC - 1; s >= 0; s--)
-            if (rel[s] == kFree)
-                g = s;
-        if (g < 0) {
-            ovf = true;
-            return false;
-        }
         const uint64_t full = (ecap_mask_bits >= 64) ? ~0ull : ((1ull << ecap_mask_bits) - 1ull);
         uint64_t mask = 0;
         bool open = false;
@@ -319,8 +306,8 @@ struct LaneSim {
                 const uint32_t s = A[j] & 511u;
                 const bool inside = (p0 <= cut) ? (s >= p0 && s <= cut) : (s >= p0 || s <= cut);
                 const uint32_t c = min(cap[j], r - 1u) + ((cap[j] >= r && inside) ? 1u : 0u);
-                A[j] -= c * ua;
-                B[j] -= c * ub;
+                A[j] -= c * tab[kTUa + k];
+                B[j] -= c * tab[kTUb + k];
                 if (open && c != ec) {
                     if (used == full) {
                         ovf = true;
@@ -351,12 +338,21 @@ struct LaneSim {
         }
         if (ovf)
             return false;
+        // the first free group slot takes the group (live groups never exceed
+        // the set size); written as a search that assigns as it goes, which
+        // keeps rel and gm in registers
+        bool placed = false;
+        const uint32_t dur = tab[kTDur + k];
 #pragma unroll
         for (int s = 0; s < GC; s++) {
-            if (s == g) {
-                rel[s] = dur;
-                gm[s] = mask;
-            }
+            const bool take = !placed && rel[s] == kFree;
+            rel[s] = take ? dur : rel[s];
+            gm[s] = take ? mask : gm[s];
+            placed = placed || take;
+        }
+        if (!placed) {
+            ovf = true;
+            return false;
         }
         merge();
         rem -= q;
@@ -515,7 +511,7 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
             for (;;) {
                 // placement at the current cycle: bulk steps until blocked
                 for (;;) {
-                    if (!L.bulk_step(n_cu, ent, ecap) || L.rem != 0)
+                    if (!L.bulk_step(n_cu, tab, ent, ecap) || L.rem != 0)
                         break;
                     L.pos++;
                     if (L.pos >= n)
@@ -536,7 +532,21 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
                     break;
             }
             if (L.ovf) {
-                item_ovf = true;
+                // recorded for spill_kernel (the wave engine, one wavefront
+                // per order); if the record list is full, the whole item goes
+                // to simulate_kernel instead
+                const unsigned long long slot = atomicAdd(a.spill_count + zero, 1ull);
+                if (slot < a.spill_cap) {
+                    SpillRec r;
+                    r.set = (uint32_t)set;
+                    r.item = (uint32_t)item;
+                    r.sample = first + i;
+                    r.pos = out_base + i;
+                    r.makespan = 0;
+                    a.spill[slot] = r;
+                } else {
+                    item_ovf = true;
+                }
                 continue;
             }
             if (m < mn || (m == mn && i < imn)) {
@@ -577,6 +587,7 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
             // listed for simulate_kernel, which rewrites the item's makespans
             // and partial; every lane issues the atomic, lane 0 adds one
             const uint64_t at = wave_uniform64(atomicAdd(a.ovf_count, lane == 0 ? 1ull : 0ull));
+            atomicOr(&a.handed_bits[item >> 5], lane == 0 ? 1u << (item & 31u) : 0u);
             if (lane == 0)
                 a.ovf_list[at] = (uint32_t)item;
         }
@@ -597,7 +608,7 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
 
 }  // namespace
 
-// Lane kernels exist for sets of up to 8, 12 and 16 kernels, with `entries`
+// Lane kernels exist for sets of up to 8, 10, 12 and 16 kernels, with `entries`
 // group entries per lane (0 = the class default, at most 64).  Returns
 // hipErrorInvalidValue otherwise.
 int launch_simulate_lanes(const SimArgs &a, int set_class, uint32_t entries, int grid, void *stream)
@@ -610,6 +621,9 @@ int launch_simulate_lanes(const SimArgs &a, int set_class, uint32_t entries, int
     switch (set_class) {
     case 8:
         hipLaunchKernelGGL((simulate_lanes_kernel<12, 8>), dim3(grid), dim3(64), lds, st, a, ecap);
+        break;
+    case 10:
+        hipLaunchKernelGGL((simulate_lanes_kernel<12, 10>), dim3(grid), dim3(64), lds, st, a, ecap);
         break;
     case 12:
         hipLaunchKernelGGL((simulate_lanes_kernel<16, 12>), dim3(grid), dim3(64), lds, st, a, ecap);

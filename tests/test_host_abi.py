@@ -225,7 +225,7 @@ def test_plan_and_graph_reject_bad_arguments_before_device_work():
     assert lib.ko_plan_info(None, None, None, None, None) == ko.KO_EINVAL
     assert lib.ko_plan_launch(None, None, None, None, None, 0, None) == ko.KO_EINVAL
     assert lib.ko_plan_status(None, None) == ko.KO_EINVAL
-    assert lib.ko_plan_engine(None, None, None, None, None) == ko.KO_EINVAL
+    assert lib.ko_plan_engine(None, None, None, None, None, None) == ko.KO_EINVAL
     assert lib.ko_graph_capture(None, None, None, None, None, 0, None, ctypes.byref(out)) == ko.KO_EINVAL
     assert lib.ko_graph_launch(None, None) == ko.KO_EINVAL
     assert lib.ko_plan_destroy(None) == ko.KO_OK

@@ -80,14 +80,20 @@ def test_simulate_collectives_full_exec(sim_report, needle):
         assert div_loops == 0, (name, div_loops)
 
 
-@pytest.mark.parametrize("needle", ["simulate_lanes_kernelILi12ELi8E", "simulate_lanes_kernelILi16ELi12E",
-                                    "simulate_lanes_kernelILi20ELi16E"])
+@pytest.mark.parametrize("needle", ["simulate_lanes_kernelILi12ELi8E", "simulate_lanes_kernelILi12ELi10E",
+                                    "simulate_lanes_kernelILi16ELi12E", "simulate_lanes_kernelILi20ELi16E"])
 def test_lane_kernels_collectives_full_exec(lanes_report, needle):
     """The lane kernels diverge by design (each lane runs its own order), so
     their loops may be lane-divergent; every wave operation (item fetch,
     statistics shuffles, overflow ballot) must still see all lanes."""
     for name in _pick(lanes_report, needle):
         bad, _ = lanes_report[name]
+        assert bad == [], (name, bad[:5])
+
+
+def test_spill_kernel_collectives_full_exec(sim_report):
+    for name in _pick(sim_report, "spill_kernel"):
+        bad, div_loops = sim_report[name]
         assert bad == [], (name, bad[:5])
 
 

@@ -87,7 +87,7 @@ def test_n10_rank_window_against_oracle():
     pick = np.sort(rng.choice(cnt, 200, replace=False))
     want = oracle.makespans_ranks(w.model.as_dict(), ks, [lo + int(i) for i in pick])
     assert np.array_equal(ms[pick], want)
-    assert info[2] == 0, "no work item should need the wave engine at full capacity"
+    assert info[3] == 0, "no work item should be re-run whole at full capacity"
 
 
 def test_batch_sets_all_orders():
@@ -164,9 +164,10 @@ def test_tiny_resource_models():
 
 
 @pytest.mark.parametrize("entries", [1, 2, 5])
-def test_overflowing_items_are_handed_to_the_wave_engine(entries):
-    """With 1..5 group entries per lane most orders overflow: their work items
-    are re-run by the wave engine and every output is unchanged."""
+def test_overflowing_orders_are_spilled_to_the_wave_engine(entries):
+    """With 1..5 group entries per lane most orders overflow: they are recorded,
+    evaluated one wavefront each and folded into the statistics; every output
+    is unchanged."""
     w = synth.WORKLOADS[1]
     ks = synth.draw_set(1, 0)
     lo, cnt = 123_456, 6000
@@ -176,7 +177,48 @@ def test_overflowing_items_are_handed_to_the_wave_engine(entries):
     lanes = run(w.model, [ks], spec, ko.ENGINE_LANES, ref=[2_600_000], n_bins=8, chunk_log2=8,
                 lane_entries=entries)
     assert lanes[3][1] == entries
-    assert lanes[3][2] > 0, "expected work items handed to the wave engine"
+    assert lanes[3][2] > 0, "expected spilled orders"
+    assert np.array_equal(lanes[0], wave[0])
+    assert np.array_equal(lanes[1], wave[1])
+    assert np.array_equal(lanes[2], wave[2])
+
+
+@pytest.mark.parametrize("mode", ["range", "sampled", "explicit"])
+def test_full_spill_list_hands_whole_items_over(mode):
+    """More spilled orders than the record list holds (65,536): the rest of
+    those orders' work items are re-run whole, records of such items are
+    ignored, and every output is unchanged, in each order mode."""
+    w = synth.WORKLOADS[1]
+    ks = synth.draw_set(1, 0)
+    cnt = 80_000
+    say(f"one entry per lane, {cnt} orders ({mode}): spill list overflows")
+    if mode == "range":
+        spec = ko.OrderSpec.rank_range([[777, 777 + cnt]])
+    elif mode == "sampled":
+        spec = ko.OrderSpec.sampled([cnt], 5)
+    else:
+        rng = np.random.default_rng(9)
+        orders = np.array([rng.permutation(10) for _ in range(cnt)], dtype=np.uint8)
+        spec = ko.OrderSpec.explicit(torch.from_numpy(orders.ravel().copy()).to(DEV), [cnt])
+    wave = run(w.model, [ks], spec, ko.ENGINE_WAVE, ref=[2_600_000], n_bins=8, chunk_log2=9)
+    lanes = run(w.model, [ks], spec, ko.ENGINE_LANES, ref=[2_600_000], n_bins=8, chunk_log2=9,
+                lane_entries=1)
+    assert lanes[3][2] > 65_536 and lanes[3][3] > 0, lanes[3]
+    assert np.array_equal(lanes[0], wave[0])
+    assert np.array_equal(lanes[1], wave[1])
+    assert np.array_equal(lanes[2], wave[2])
+
+
+def test_spilled_orders_across_sets_fold_into_their_own_set():
+    """A batch of sets with few entries per lane: spilled orders of different
+    sets must reach their own set's statistics."""
+    w = synth.WORKLOADS[2]
+    sets = [synth.draw_set(2, s) for s in range(24)]
+    say("24 batch sets, 3 entries per lane")
+    refs = [2_000_000 + 15_000 * s for s in range(len(sets))]
+    wave = run(w.model, sets, ko.OrderSpec.all(), ko.ENGINE_WAVE, ref=refs, n_bins=16)
+    lanes = run(w.model, sets, ko.OrderSpec.all(), ko.ENGINE_LANES, ref=refs, n_bins=16, lane_entries=3)
+    assert lanes[3][2] > 0
     assert np.array_equal(lanes[0], wave[0])
     assert np.array_equal(lanes[1], wave[1])
     assert np.array_equal(lanes[2], wave[2])
@@ -188,7 +230,7 @@ def test_engine_choice():
     kernels, offsets = kb.concat_sets([ks])
     say("engine choice: auto, and lanes refused for n=20")
     p = ko.Plan(w.model, kernels, offsets, ko.OrderSpec.sampled([64], 1))
-    assert p.engine()[:2] == (ko.ENGINE_LANES, 48)
+    assert p.engine()[:2] == (ko.ENGINE_LANES, 40)
     p.close()
     big = synth.draw_kernels(np.random.default_rng(3), 20, 64, 512)
     k20, o20 = kb.concat_sets([big])
