@@ -26,7 +26,7 @@ import numpy as np
 
 from . import OrderSpec, Plan, gpu_model, kernel_array, ko_heuristic_order, stats_records
 
-CHUNKS = (5, 7, 9, 11)      # orders per work item: 32, 128, 512, 2048
+CHUNKS = (5, 6, 8, 10)      # orders per work item: 32, 64, 256, 1024 (lane engine: 64-256)
 WG_PER_CU = (4, 8, 16)
 
 

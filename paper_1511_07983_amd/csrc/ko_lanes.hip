@@ -80,21 +80,41 @@ __device__ __forceinline__ uint32_t quot_clamp(uint32_t fr, uint32_t u, float in
     return q - ((__umul24(q, u) > fr) ? 1u : 0u);
 }
 
+constexpr double fact_d(int k) { return k <= 1 ? 1.0 : k * fact_d(k - 1); }
+
+// 1 / k! in binary64, k = 0..20 (each k! up to 20! is exact in binary64 up to
+// 18!; the reciprocal only seeds the digit, which is then corrected exactly)
+static __device__ const double kInvFactorial[21] = {
+    1.0 / fact_d(0),  1.0 / fact_d(1),  1.0 / fact_d(2),  1.0 / fact_d(3),  1.0 / fact_d(4),
+    1.0 / fact_d(5),  1.0 / fact_d(6),  1.0 / fact_d(7),  1.0 / fact_d(8),  1.0 / fact_d(9),
+    1.0 / fact_d(10), 1.0 / fact_d(11), 1.0 / fact_d(12), 1.0 / fact_d(13), 1.0 / fact_d(14),
+    1.0 / fact_d(15), 1.0 / fact_d(16), 1.0 / fact_d(17), 1.0 / fact_d(18), 1.0 / fact_d(19),
+    1.0 / fact_d(20)};
+
 // Lexicographic rank -> order packed as nibbles (position j in bits 4j..4j+3).
-// Digit j (at most n-1-j) is found by subtracting (n-1-j)! until the rest is
-// smaller: no division, and nothing the compiler turns into a wave-wide value.
+// Digit j is floor(rest / (n-1-j)!): estimated as rest x 1/(n-1-j)! in binary64
+// (rest < 16! < 2^53, so the estimate is off by at most one) and corrected with
+// one exact integer comparison.  No division, so nothing the compiler turns
+// into a wave-wide value.
 __device__ uint64_t unrank_nibbles(uint64_t rank, uint32_t n)
 {
     uint64_t avail = 0xFEDCBA9876543210ull;  // unused kernel indices, ascending
     uint64_t perm = 0;
     for (uint32_t j = 0; j < n; j++) {
-        const uint64_t f = kFactorial[n - 1u - j];
-        uint32_t d = 0;
-        while (rank >= f && d < n - 1u - j) {  // the bound holds for every rank below n!
-            rank -= f;
+        const uint32_t k = n - 1u - j;
+        const uint64_t f = kFactorial[k];
+        uint64_t d = (uint64_t)((double)rank * kInvFactorial[k]);
+        int64_t rest = (int64_t)rank - (int64_t)(d * f);
+        if (rest < 0) {
+            d--;
+            rest += (int64_t)f;
+        } else if (rest >= (int64_t)f) {
             d++;
+            rest -= (int64_t)f;
         }
-        const uint32_t sh = 4u * d;
+        rank = (uint64_t)rest;
+        d = min(d, (uint64_t)k);  // holds for every rank below n!
+        const uint32_t sh = 4u * (uint32_t)d;
         perm |= ((avail >> sh) & 15ull) << (4u * j);
         const uint64_t low = avail & ((1ull << sh) - 1ull);
         avail = low | (((avail >> sh) >> 4) << sh);
