@@ -241,9 +241,10 @@ typedef struct ko_launch_config {
                             the lane engine launches 2x as many one-wave workgroups
                             (at most 32 per CU) */
     int32_t engine;      /* KO_ENGINE_*; KO_EINVAL if LANES does not apply */
-    int32_t lane_entries; /* lane engine: group entries per lane (1..64); 0 = by set size
-                             (40 up to 10 kernels, 48 up to 12, 64 up to 16).  Fewer
-                             entries send more work items to the wave engine. */
+    int32_t lane_entries; /* lane engine: group entries per lane (1..64, at most 32 used
+                             for sets of up to 10 kernels); 0 = by set size (32 up to 10
+                             kernels, 48 up to 12, 64 up to 16).  Fewer entries send
+                             more orders to the wave engine. */
 } ko_launch_config;
 
 /* ko_plan_create — prepare a batch as ko_simulate_batch takes it (same

@@ -137,8 +137,10 @@ int launch_spill(const SimArgs &a, int slots_per_lane, uint32_t group_slots, int
 // lane_entry_cap(class) group entries per lane in LDS.
 constexpr uint32_t lane_entry_cap(int set_class)
 {
-    return set_class <= 10 ? 40u : (set_class <= 12 ? 48u : 64u);
+    return set_class <= 10 ? 32u : (set_class <= 12 ? 48u : 64u);
 }
+// Most entries per lane a class takes (its entry masks are 32 or 64 bits).
+constexpr uint32_t lane_entry_max(int set_class) { return set_class <= 10 ? 32u : 64u; }
 int launch_simulate_lanes(const SimArgs &a, int set_class, uint32_t entries, int grid, void *stream);
 int launch_hist(const HistArgs &a, uint64_t n_blocks, void *stream);
 int launch_zero_u64(uint64_t *p, uint64_t count, void *stream);

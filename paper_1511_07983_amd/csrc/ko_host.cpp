@@ -1098,8 +1098,9 @@ int ko_plan_create(const ko_gpu_model *gpu, const ko_kernel *kernels, const int3
             delete p;
             return rc;
         }
-        if (config)
-            p->plan.lane_entries = (uint32_t)config->lane_entries;
+        if (config && p->plan.lane_class)
+            p->plan.lane_entries = std::min<uint32_t>((uint32_t)config->lane_entries,
+                                                      ko::lane_entry_max(p->plan.lane_class));
         const size_t kbytes = p->plan.krec.size() * sizeof(ko::KernelRec);
         const size_t sbytes = p->plan.sets.size() * sizeof(ko::SetRec);
         const size_t bbytes = p->plan.block_base.size() * sizeof(uint64_t);

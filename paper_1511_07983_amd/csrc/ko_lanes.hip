@@ -128,13 +128,17 @@ __device__ __forceinline__ uint64_t identity_nibbles(uint32_t n)
     return n >= 16 ? all : (all & ((1ull << (4u * n)) - 1ull));
 }
 
-template <int RC, int GC>
+// Entry masks: 32 bits when a variant holds at most 32 entries per lane.
+__device__ __forceinline__ uint32_t lowest_bit(uint32_t m) { return (uint32_t)__builtin_ctz(m); }
+__device__ __forceinline__ uint32_t lowest_bit(uint64_t m) { return (uint32_t)__builtin_ctzll(m); }
+
+template <int RC, int GC, typename Mask>
 struct LaneSim {
     uint32_t A[RC], B[RC], cap[RC];
     uint32_t R;
     uint32_t rel[GC];
-    uint64_t gm[GC];
-    uint64_t used;
+    Mask gm[GC];
+    Mask used;
     uint64_t t;
     uint32_t ptr, pos, k, rem;  // the front kernel's parameters are read from the LDS table
     bool ovf;
@@ -316,8 +320,9 @@ struct LaneSim {
         split(c1, n_cu);
         if (ovf)
             return false;
-        const uint64_t full = (ecap_mask_bits >= 64) ? ~0ull : ((1ull << ecap_mask_bits) - 1ull);
-        uint64_t mask = 0;
+        constexpr uint32_t kBits = 8 * sizeof(Mask);
+        const Mask full = (ecap_mask_bits >= kBits) ? (Mask)~(Mask)0 : (Mask)(((Mask)1 << ecap_mask_bits) - 1);
+        Mask mask = 0;
         bool open = false;
         uint32_t es = 0, ec = 0;
 #pragma unroll
@@ -332,9 +337,9 @@ struct LaneSim {
                     if (used == full) {
                         ovf = true;
                     } else {
-                        const uint32_t e = (uint32_t)__builtin_ctzll(~used);
-                        used |= 1ull << e;
-                        mask |= 1ull << e;
+                        const uint32_t e = lowest_bit((Mask)~used);
+                        used |= (Mask)1 << e;
+                        mask |= (Mask)1 << e;
                         ent[e * kWave + lane] = es | (s << 8) | (ec << 17) | (k << 24);
                     }
                     open = false;
@@ -350,9 +355,9 @@ struct LaneSim {
             if (used == full) {
                 ovf = true;
             } else {
-                const uint32_t e = (uint32_t)__builtin_ctzll(~used);
-                used |= 1ull << e;
-                mask |= 1ull << e;
+                const uint32_t e = lowest_bit((Mask)~used);
+                used |= (Mask)1 << e;
+                mask |= (Mask)1 << e;
                 ent[e * kWave + lane] = es | (n_cu << 8) | (ec << 17) | (k << 24);
             }
         }
@@ -391,7 +396,7 @@ struct LaneSim {
         if (dt == kFree)
             return false;
         t += dt;
-        uint64_t ending = 0;
+        Mask ending = 0;
 #pragma unroll
         for (int s = 0; s < GC; s++) {
             if (rel[s] != kFree) {
@@ -405,8 +410,8 @@ struct LaneSim {
         }
         used &= ~ending;
         while (ending) {
-            const uint32_t e = (uint32_t)__builtin_ctzll(ending);
-            ending &= ending - 1ull;
+            const uint32_t e = lowest_bit(ending);
+            ending &= ending - 1;
             const uint32_t w = ent[e * kWave + lane];
             const uint32_t s = w & 255u, en = (w >> 8) & 511u, c = (w >> 17) & 127u, kk = (w >> 24) & 15u;
             const uint32_t dua = c * tab[kTUa + kk], dub = c * tab[kTUb + kk];
@@ -437,7 +442,7 @@ struct LaneSim {
     }
 };
 
-template <int RC, int GC>
+template <int RC, int GC, typename Mask>
 __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t ecap)
 {
     extern __shared__ uint32_t lane_lds[];
@@ -495,7 +500,7 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
         int64_t mn = INT64_MAX, mx = INT64_MIN;
         uint32_t imn = 0, imx = 0, n_less = 0, n_eq = 0, n_gt = 0;
         bool item_ovf = false;
-        LaneSim<RC, GC> L;
+        LaneSim<RC, GC, Mask> L;
         for (;;) {
             // The cursor is indexed by a zero that passes through an empty asm
             // in a vector register, so its address counts as lane-varying: the
@@ -634,22 +639,22 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
 int launch_simulate_lanes(const SimArgs &a, int set_class, uint32_t entries, int grid, void *stream)
 {
     hipStream_t st = (hipStream_t)stream;
-    if (entries > 64)
-        return (int)hipErrorInvalidValue;
     const uint32_t ecap = entries ? entries : lane_entry_cap(set_class);
+    if (ecap > (set_class <= 10 ? 32u : 64u))
+        return (int)hipErrorInvalidValue;
     const size_t lds = (size_t)(kEntBase + ecap * kWave) * sizeof(uint32_t);
     switch (set_class) {
     case 8:
-        hipLaunchKernelGGL((simulate_lanes_kernel<12, 8>), dim3(grid), dim3(64), lds, st, a, ecap);
+        hipLaunchKernelGGL((simulate_lanes_kernel<12, 8, uint32_t>), dim3(grid), dim3(64), lds, st, a, ecap);
         break;
     case 10:
-        hipLaunchKernelGGL((simulate_lanes_kernel<12, 10>), dim3(grid), dim3(64), lds, st, a, ecap);
+        hipLaunchKernelGGL((simulate_lanes_kernel<12, 10, uint32_t>), dim3(grid), dim3(64), lds, st, a, ecap);
         break;
     case 12:
-        hipLaunchKernelGGL((simulate_lanes_kernel<16, 12>), dim3(grid), dim3(64), lds, st, a, ecap);
+        hipLaunchKernelGGL((simulate_lanes_kernel<16, 12, uint64_t>), dim3(grid), dim3(64), lds, st, a, ecap);
         break;
     case 16:
-        hipLaunchKernelGGL((simulate_lanes_kernel<20, 16>), dim3(grid), dim3(64), lds, st, a, ecap);
+        hipLaunchKernelGGL((simulate_lanes_kernel<20, 16, uint64_t>), dim3(grid), dim3(64), lds, st, a, ecap);
         break;
     default:
         return (int)hipErrorInvalidValue;

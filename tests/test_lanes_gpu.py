@@ -230,7 +230,7 @@ def test_engine_choice():
     kernels, offsets = kb.concat_sets([ks])
     say("engine choice: auto, and lanes refused for n=20")
     p = ko.Plan(w.model, kernels, offsets, ko.OrderSpec.sampled([64], 1))
-    assert p.engine()[:2] == (ko.ENGINE_LANES, 40)
+    assert p.engine()[:2] == (ko.ENGINE_LANES, 32)
     p.close()
     big = synth.draw_kernels(np.random.default_rng(3), 20, 64, 512)
     k20, o20 = kb.concat_sets([big])
