@@ -152,16 +152,21 @@ def percentiles(gpu, sets, *, config=None, n_bins: int = 0, want_makespans: bool
     return out
 
 
-def report(*, workload: int = 2, sets: int = 4096, tune_sets: int = 512, reps: int = 5, out=print):
+def report(*, workload: int = 2, sets: int = 4096, tune_sets: int = 512, reps: int = 5, tune: bool = True,
+           out=print):
     """Exact evaluations per second over every order of a batch of kernel sets:
-    autotune on a subset, then replay a captured graph of the whole batch."""
+    autotune on a subset (or take the library's defaults), then replay a
+    captured graph of the whole batch."""
     import torch
 
     import synth
     w = synth.WORKLOADS[workload]
     all_sets = [synth.draw_set(workload, s) for s in range(sets)]
-    k_t, o_t = concat_sets(all_sets[:tune_sets])
-    cfg, rows = autotune(w.model, k_t, o_t, OrderSpec.all(), reps=2, use_cache=False)
+    if tune:
+        k_t, o_t = concat_sets(all_sets[:tune_sets])
+        cfg, rows = autotune(w.model, k_t, o_t, OrderSpec.all(), reps=2, use_cache=False)
+    else:
+        cfg, rows = {"chunk_log2": 0, "wg_per_cu": 0}, []
     kernels, offsets = concat_sets(all_sets)
     plan = Plan(w.model, kernels, offsets, OrderSpec.all(), chunk_log2=cfg["chunk_log2"],
                 wg_per_cu=cfg["wg_per_cu"])
@@ -182,8 +187,11 @@ def report(*, workload: int = 2, sets: int = 4096, tune_sets: int = 512, reps: i
         b.synchronize()
         times.append(a.elapsed_time(b) / 1e3)
     plan.status(stream)
+    engine, entries, spilled, handed = plan.engine(stream)
     t = float(np.median(times))
     out(json.dumps({"workload": w.name, "sets": sets, "orders": int(plan.total_orders),
+                    "engine": {"engine": engine, "lane_entries": entries, "spilled_orders": spilled,
+                               "items_re_run": handed},
                     "config": {"chunk_log2": cfg["chunk_log2"], "wg_per_cu": cfg["wg_per_cu"]},
                     "tuning": rows, "graph_replay_s": t, "orders_per_s": plan.total_orders / t,
                     "work_items": int(plan.work_items)}), flush=True)
@@ -192,9 +200,18 @@ def report(*, workload: int = 2, sets: int = 4096, tune_sets: int = 512, reps: i
 
 
 if __name__ == "__main__":
+    import argparse
     import os
     import sys
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    ap = argparse.ArgumentParser(description="exact orders/s over every order of a batch of sets")
+    ap.add_argument("--workload", type=int, default=2, help="synthetic workload (default 2: 4096 sets, n=4..9)")
+    ap.add_argument("--sets", type=int, default=4096)
+    ap.add_argument("--tune-sets", type=int, default=512)
+    ap.add_argument("--no-tune", action="store_true", help="library defaults instead of the autotuner")
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
-    report()
+    report(workload=args.workload, sets=args.sets, tune_sets=args.tune_sets, reps=args.reps,
+           tune=not args.no_tune)
