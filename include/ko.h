@@ -230,8 +230,8 @@ typedef struct ko_graph ko_graph;
  *   KO_ENGINE_LANES  one lane per order, the CUs' free resources held as runs
  *                    of equal values (n <= 16, N_CU <= 256, registers per CU
  *                    < 2^23, LDS per CU < 2^18 bytes, waves and blocks per CU
- *                    < 128); work items whose orders outgrow its per-lane
- *                    capacities are re-run by the wave engine;
+ *                    < 128); orders that outgrow its per-lane capacities
+ *                    are evaluated by the wave engine, one wavefront each;
  *   KO_ENGINE_AUTO   the lane engine where it applies, else the wave engine. */
 enum { KO_ENGINE_AUTO = 0, KO_ENGINE_WAVE = 1, KO_ENGINE_LANES = 2 };
 

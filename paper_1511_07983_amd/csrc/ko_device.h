@@ -7,10 +7,9 @@
 namespace ko {
 
 // Largest kernel set the device path handles.  Live block groups never
-// exceed the set size (see ko_sim.hip), so the per-wave group ring has
-// kMaxSet slots, one per lane of the lower half-wave.
+// exceed the set size (see ko_wave.h), so the wave engine's per-wave group
+// ring has at most kMaxSet slots.
 constexpr int kMaxSet = 20;
-constexpr int kGroupSlots = 32;
 constexpr int kWave = 64;
 
 // One kernel of a set, derived on the host from ko_kernel and the GPU model.
