@@ -442,6 +442,47 @@ struct LaneSim {
     }
 };
 
+// The next order of the item for this lane: index from the LDS cursor, the
+// permutation by mode, the lane's state reset.  False when the item is done.
+// The cursor is indexed by a zero that passes through an empty asm in a
+// vector register, so its address counts as lane-varying: the atomic stays one
+// LDS atomic per active lane instead of becoming a compiler-built scan and
+// broadcast inside lane-divergent code.
+template <int RC, int GC, typename Mask>
+__device__ __forceinline__ bool take_order(const SimArgs &a, const SetRec &st, int set, uint64_t first,
+                                           uint64_t index0, bool ranked, uint64_t count, const uint32_t *tab,
+                                           uint32_t *cursor, LaneSim<RC, GC, Mask> &L, uint32_t &i,
+                                           uint64_t &perm)
+{
+    uint32_t zero = 0;
+    asm volatile("" : "+v"(zero));
+    i = atomicAdd(cursor + zero, 1u);
+    if ((uint64_t)i >= count)
+        return false;
+    const uint32_t n = st.n;
+    if (ranked) {
+        perm = unrank_nibbles(index0 + i, n);
+    } else if (a.mode == kModeSampled) {
+        perm = unrank_nibbles(sampled_rank(a.seed, (uint32_t)set, first + i, n), n);
+    } else {
+        const uint8_t *o = a.orders + st.list_base + (first + i) * n;
+        uint32_t seen = 0;
+        perm = 0;
+        for (uint32_t j = 0; j < n; j++) {
+            const uint32_t v = o[j];
+            seen |= (v < n) ? (1u << v) : 0x80000000u;
+            perm |= (uint64_t)(v & 15u) << (4u * j);
+        }
+        if (seen != (1u << n) - 1u) {
+            atomicOr(a.status, kStatusBadOrder);
+            perm = identity_nibbles(n);
+        }
+    }
+    L.reset(a);
+    L.load_kernel(tab, (uint32_t)(perm & 15ull));
+    return true;
+}
+
 template <int RC, int GC, typename Mask>
 __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t ecap)
 {
@@ -500,66 +541,45 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
         int64_t mn = INT64_MAX, mx = INT64_MIN;
         uint32_t imn = 0, imx = 0, n_less = 0, n_eq = 0, n_gt = 0;
         bool item_ovf = false;
+        // One flat loop per lane.  Each pass makes at most one bulk step of the
+        // placement at the lane's current cycle; once that placement is over
+        // (the front kernel is blocked, or every block is placed) the same pass
+        // advances to the next release, or records the finished order and
+        // takes the next one.  Lanes therefore move through their orders
+        // independently (no lane waits for the wave's longest order), and a
+        // pass costs one bulk step whatever the lanes' phases (a new order's
+        // first cycle places several kernels, over several passes).
         LaneSim<RC, GC, Mask> L;
-        for (;;) {
-            // The cursor is indexed by a zero that passes through an empty asm
-            // in a vector register, so its address counts as lane-varying: the
-            // atomic stays one LDS atomic per active lane instead of becoming
-            // a compiler-built scan and broadcast inside this divergent loop.
-            uint32_t zero = 0;
-            asm volatile("" : "+v"(zero));
-            const uint32_t i = atomicAdd(cursor + zero, 1u);
-            if ((uint64_t)i >= count)
-                break;
-            uint64_t perm;
-            if (ranked) {
-                perm = unrank_nibbles(index0 + i, n);
-            } else if (a.mode == kModeSampled) {
-                perm = unrank_nibbles(sampled_rank(a.seed, (uint32_t)set, first + i, n), n);
-            } else {
-                const uint8_t *o = a.orders + st.list_base + (first + i) * n;
-                uint32_t seen = 0;
-                perm = 0;
-                for (uint32_t j = 0; j < n; j++) {
-                    const uint32_t v = o[j];
-                    seen |= (v < n) ? (1u << v) : 0x80000000u;
-                    perm |= (uint64_t)(v & 15u) << (4u * j);
-                }
-                if (seen != (1u << n) - 1u) {
-                    atomicOr(a.status, kStatusBadOrder);
-                    perm = identity_nibbles(n);
+        uint32_t i = 0;
+        uint64_t perm = 0;
+        bool live = take_order(a, st, set, first, index0, ranked, count, tab, cursor, L, i, perm);
+        while (live) {
+            if (L.bulk_step(n_cu, tab, ent, ecap) && L.rem == 0) {
+                L.pos++;
+                if (L.pos < n) {
+                    // the next kernel may still place blocks at this cycle
+                    L.load_kernel(tab, (uint32_t)((perm >> (4u * L.pos)) & 15ull));
+                    if (!L.ovf)
+                        continue;
                 }
             }
-            L.reset(a);
-            L.load_kernel(tab, (uint32_t)(perm & 15ull));
             int64_t m = -1;
-            for (;;) {
-                // placement at the current cycle: bulk steps until blocked
-                for (;;) {
-                    if (!L.bulk_step(n_cu, tab, ent, ecap) || L.rem != 0)
-                        break;
-                    L.pos++;
-                    if (L.pos >= n)
-                        break;
-                    L.load_kernel(tab, (uint32_t)((perm >> (4u * L.pos)) & 15ull));
-                }
-                if (L.ovf)
-                    break;
+            bool fin = false;
+            if (!L.ovf) {
                 if (L.pos >= n) {
                     m = (int64_t)(L.t + L.max_left());
-                    break;
-                }
-                if (!L.advance(n_cu, tab, ent)) {
+                    fin = true;
+                } else if (!L.advance(n_cu, tab, ent)) {
                     atomicOr(a.status, kStatusGroupOverflow);
-                    break;
+                    fin = true;
                 }
-                if (L.ovf)
-                    break;
             }
             if (L.ovf) {
                 // recorded for spill_kernel (the wave engine, one wavefront
                 // per order); if the record list is full, the whole item goes
                 // to simulate_kernel instead
+                uint32_t zero = 0;
+                asm volatile("" : "+v"(zero));
                 const unsigned long long slot = atomicAdd(a.spill_count + zero, 1ull);
                 if (slot < a.spill_cap) {
                     SpillRec r;
@@ -572,8 +592,11 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
                 } else {
                     item_ovf = true;
                 }
+                live = take_order(a, st, set, first, index0, ranked, count, tab, cursor, L, i, perm);
                 continue;
             }
+            if (!fin)
+                continue;
             if (m < mn || (m == mn && i < imn)) {
                 mn = m;
                 imn = i;
@@ -589,6 +612,7 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
             }
             if (a.makespans)
                 a.makespans[out_base + i] = m;
+            live = take_order(a, st, set, first, index0, ranked, count, tab, cursor, L, i, perm);
         }
 
         // combine the lanes' statistics (ties -> smaller index)

@@ -17,7 +17,9 @@ mask:
     exec state that OR-ing it back restores;
   * at control-flow joins PARTIAL wins and disagreeing saved masks are lost.
 
-A cross-lane instruction reached with exec possibly PARTIAL is reported.
+A cross-lane instruction reached with exec possibly PARTIAL is reported,
+except a readfirstlane of a value that the same block computed from scalar
+operands with lane-independent arithmetic (every active lane holds it).
 Readlane of the VGPRs that hold SGPR spills is exempt (spill code is
 independent of exec), as are writelanes; a saved mask that is spilled to a VGPR
 lane and reloaded keeps what it restores.
@@ -296,6 +298,48 @@ def _is_xlane(inst: Inst, spill: set) -> bool:
     return any(d in inst.text for d in _DPP)
 
 
+# VALU operations whose result depends only on their operands (no lane mask,
+# lane id or cross-lane read): with only scalar operands, every active lane
+# computes the same value.
+_UNIFORM_VALU = ("v_add_u32", "v_add_co_u32", "v_sub_u32", "v_sub_co_u32", "v_subrev_u32",
+                 "v_subrev_co_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_lshlrev_b32", "v_lshlrev_b64",
+                 "v_lshrrev_b32", "v_lshrrev_b64", "v_ashrrev_i32", "v_and_b32", "v_or_b32", "v_xor_b32",
+                 "v_mov_b32", "v_mov_b64", "v_bfe_u32", "v_min_u32", "v_max_u32", "v_not_b32", "v_add3_u32")
+
+
+def _scalar_operand(op: str) -> bool:
+    return bool(re.fullmatch(r"s\d+|s\[\d+:\d+\]|-?\d+|0x[0-9a-fA-F]+", op))
+
+
+def _uniform_source(insts, k: int) -> bool:
+    """A readfirstlane at insts[k] whose source VGPR was last written, in the
+    same block, by a lane-independent VALU operation on scalar operands only:
+    all active lanes hold the same value, so reading the first one is exact."""
+    src = insts[k].ops[1] if len(insts[k].ops) > 1 else ""
+    m = re.fullmatch(r"v(\d+)", src)
+    if not m:
+        return False
+    reg = int(m.group(1))
+    for inst in reversed(insts[:k]):
+        if not inst.ops:
+            continue
+        d = inst.ops[0]
+        md = re.fullmatch(r"v(\d+)|v\[(\d+):(\d+)\]", d)
+        if not md:
+            continue
+        lo, hi = (int(md.group(1)),) * 2 if md.group(1) else (int(md.group(2)), int(md.group(3)))
+        if not lo <= reg <= hi:
+            continue
+        base = re.sub(r"_e(32|64)$", "", inst.mnem)
+        if base not in _UNIFORM_VALU:
+            return False
+        srcs = inst.ops[1:]
+        if "_co_" in base and srcs:
+            srcs = srcs[1:]  # the carry-out mask is a destination
+        return all(_scalar_operand(o) for o in srcs)
+    return False
+
+
 def _merge(a, b):
     if a is None:
         return b
@@ -331,11 +375,12 @@ def analyse(func: Function):
             continue
         e, t = state_in[i]
         t = dict(t)
-        for inst in b.insts:
+        for k, inst in enumerate(b.insts):
             if inst.mnem == "s_andn2_b64" and inst.ops[:2] == ["exec", "exec"]:
                 div_loops += 1
             if e != FULL and _is_xlane(inst, func.spill_vgprs):
-                bad.append((inst.line, inst.text))
+                if not (inst.mnem == "v_readfirstlane_b32" and _uniform_source(b.insts, k)):
+                    bad.append((inst.line, inst.text))
             e = _transfer(inst, e, t)
     return bad, div_loops
 

@@ -161,3 +161,30 @@ def test_analysis_accepts_branch_free_fetch(tmp_path):
     (name,) = _pick(report, "threaded_loop")
     bad, div_loops = report[name]
     assert bad == [] and div_loops == 0, (bad[:5], div_loops)
+
+
+SCALAR_SOURCE_ASM = """
+kern:
+	s_and_saveexec_b64 s[4:5], vcc
+	v_sub_co_u32_e64 v0, s[6:7], s2, 1
+	v_readfirstlane_b32 s1, v0
+	s_or_b64 exec, exec, s[4:5]
+	s_endpgm
+.Lfunc_end0:
+"""
+
+
+def test_readfirstlane_of_a_scalar_computed_value_is_accepted():
+    """Under a partial exec mask, a readfirstlane of n - 1 computed from an SGPR
+    reads the same value in every active lane."""
+    (bad, _), = ic.check(SCALAR_SOURCE_ASM).values()
+    assert bad == []
+
+
+@pytest.mark.parametrize("define", ["v_mbcnt_lo_u32_b32 v0, -1, 0",
+                                    "v_add_u32_e32 v0, s2, v7",
+                                    "v_cndmask_b32_e64 v0, 0, 1, s[6:7]"])
+def test_readfirstlane_of_a_lane_varying_value_is_reported(define):
+    asm = SCALAR_SOURCE_ASM.replace("v_sub_co_u32_e64 v0, s[6:7], s2, 1", define)
+    (bad, _), = ic.check(asm).values()
+    assert [t for _, t in bad] == ["v_readfirstlane_b32 s1, v0"]
