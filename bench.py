@@ -148,7 +148,7 @@ def main():
     b_total = int(ks["n_tblk"].sum())
 
     # the kernel the all-orders leg runs (the library picks the engine by set size)
-    probe = ko.Plan(w.model, kernels, off, ko.OrderSpec.sampled([1], 0))
+    probe = ko.Plan(w.model, kernels, off, ko.OrderSpec.all())
     engine = probe.engine()[0]
     probe.close()
     if engine == ko.ENGINE_LANES:

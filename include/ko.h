@@ -232,7 +232,8 @@ typedef struct ko_graph ko_graph;
  *                    < 2^23, LDS per CU < 2^18 bytes, waves and blocks per CU
  *                    < 128); orders that outgrow its per-lane capacities
  *                    are evaluated by the wave engine, one wavefront each;
- *   KO_ENGINE_AUTO   the lane engine where it applies, else the wave engine. */
+ *   KO_ENGINE_AUTO   the lane engine where it applies to a batch of at least
+ *                    8192 orders, else the wave engine. */
 enum { KO_ENGINE_AUTO = 0, KO_ENGINE_WAVE = 1, KO_ENGINE_LANES = 2 };
 
 typedef struct ko_launch_config {

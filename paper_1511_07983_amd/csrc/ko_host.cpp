@@ -648,6 +648,9 @@ int radix_pass(Workspace &w, hipStream_t stream, uint32_t shift, uint64_t *prefi
 // The lane kernel packs a CU's free resources into two words (registers
 // below 2^23, LDS bytes below 2^18, waves and block slots below 128, CU index
 // below 2^8) and takes sets of up to 16 kernels.
+// Smallest batch the automatic engine choice sends to the lane engine.
+constexpr uint64_t kLaneMinOrders = 8192;
+
 int lane_class_for(const ko_gpu_model &g, uint32_t max_n)
 {
     if (g.n_cu > 256 || g.reg_cu >= (1 << 23) || g.lds_cu >= (1 << 18) || g.wave_cu > 127 || g.blk_cu > 127 ||
@@ -685,6 +688,10 @@ int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *
     plan->slots = slots_for(gpu->n_cu);
     plan->grid = std::max(1, cu_count * wg_per_cu);
     plan->lane_class = engine == KO_ENGINE_WAVE ? 0 : lane_class_for(*gpu, plan->max_n);
+    // a batch too small to fill the lanes finishes sooner with one wavefront
+    // per order (one order alone: about 5 us against 0.35 ms for one lane)
+    if (engine == KO_ENGINE_AUTO && plan->total < kLaneMinOrders)
+        plan->lane_class = 0;
     if (engine == KO_ENGINE_LANES && plan->lane_class == 0)
         return fail(KO_EINVAL, "the lane engine takes sets of at most 16 kernels on at most 256 CUs");
     // one-wave workgroups, at least as many as the chip holds at once (8 to 12

@@ -229,8 +229,12 @@ def test_engine_choice():
     ks = synth.draw_set(1, 0)
     kernels, offsets = kb.concat_sets([ks])
     say("engine choice: auto, and lanes refused for n=20")
-    p = ko.Plan(w.model, kernels, offsets, ko.OrderSpec.sampled([64], 1))
+    p = ko.Plan(w.model, kernels, offsets, ko.OrderSpec.sampled([8192], 1))
     assert p.engine()[:2] == (ko.ENGINE_LANES, 32)
+    p.close()
+    # too few orders to fill the lanes: one wavefront per order
+    p = ko.Plan(w.model, kernels, offsets, ko.OrderSpec.sampled([8191], 1))
+    assert p.engine()[0] == ko.ENGINE_WAVE
     p.close()
     big = synth.draw_kernels(np.random.default_rng(3), 20, 64, 512)
     k20, o20 = kb.concat_sets([big])
