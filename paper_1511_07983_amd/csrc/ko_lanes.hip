@@ -244,6 +244,9 @@ struct LaneSim {
         const uint32_t u_reg = tab[kTReg + k], u_lds = tab[kTLds + k], u_wave = tab[kTWave + k];
         const float i_reg = __uint_as_float(tab[kTIReg + k]), i_lds = __uint_as_float(tab[kTILds + k]),
                     i_wave = __uint_as_float(tab[kTIWave + k]);
+        // read once: the entry stores below are LDS stores the compiler cannot
+        // tell apart from the table
+        const uint32_t ua = tab[kTUa + k], ub = tab[kTUb + k], dur = tab[kTDur + k];
         uint32_t T = 0, cmax = 0;
 #pragma unroll
         for (int j = 0; j < RC; j++) {
@@ -331,8 +334,8 @@ struct LaneSim {
                 const uint32_t s = A[j] & 511u;
                 const bool inside = (p0 <= cut) ? (s >= p0 && s <= cut) : (s >= p0 || s <= cut);
                 const uint32_t c = min(cap[j], r - 1u) + ((cap[j] >= r && inside) ? 1u : 0u);
-                A[j] -= c * tab[kTUa + k];
-                B[j] -= c * tab[kTUb + k];
+                A[j] -= c * ua;
+                B[j] -= c * ub;
                 if (open && c != ec) {
                     if (used == full) {
                         ovf = true;
@@ -367,7 +370,6 @@ struct LaneSim {
         // the set size); written as a search that assigns as it goes, which
         // keeps rel and gm in registers
         bool placed = false;
-        const uint32_t dur = tab[kTDur + k];
 #pragma unroll
         for (int s = 0; s < GC; s++) {
             const bool take = !placed && rel[s] == kFree;
