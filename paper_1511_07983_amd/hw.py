@@ -47,6 +47,25 @@ def spearman(a, b) -> float:
     return float((ra * rb).sum() / den) if den > 0 else float("nan")
 
 
+def calibrate(rows) -> dict:
+    """Least-squares fit of measured milliseconds against model cycles over every
+    order of every set: ms = a * cycles / scale + b, where scale divides the
+    synthetic kernels' work.  Returns ns per model cycle at full scale (a / scale
+    in ns), the offset b in ms and R^2.  The within-set Spearman asks whether the
+    model ranks orders; this asks whether its cycles predict time across sets."""
+    c = np.concatenate([np.asarray(r["simulated_cycles"], dtype=np.float64) / r["scale"] for r in rows])
+    m = np.concatenate([np.asarray(r["measured_ms"], dtype=np.float64) for r in rows])
+    A = np.vstack([c, np.ones_like(c)]).T
+    (a, b), *_ = np.linalg.lstsq(A, m, rcond=None)
+    pred = A @ np.array([a, b])
+    ss = float(((m - m.mean()) ** 2).sum())
+    r2 = 1.0 - float(((m - pred) ** 2).sum()) / ss if ss > 0 else float("nan")
+    scales = {int(r["scale"]) for r in rows}
+    per_cycle_ns = a * 1e6 / scales.pop() if len(scales) == 1 else float("nan")
+    return {"ns_per_model_cycle": per_cycle_ns, "ms_per_scaled_cycle": float(a), "offset_ms": float(b),
+            "r2": r2, "points": int(len(m))}
+
+
 def hardware_kernels(kernels) -> np.ndarray:
     """The set as the model should see the hardware stand-ins: registers per
     thread replaced by the VGPR count of the compiled variant."""
@@ -117,6 +136,7 @@ def main(argv=None):
                                               "heuristic_rank_simulated", "measured_ms", "simulated_cycles")}),
               flush=True)
     rho = [r["spearman"] for r in rows]
+    print(json.dumps({"calibration": True, "hw_queues": queues, **calibrate(rows)}), flush=True)
     print(json.dumps({"summary": True, "hw_queues": queues, "sets": a.sets, "orders_per_set": a.random_orders + 1,
                       "spearman_mean": float(np.nanmean(rho)), "spearman_min": float(np.nanmin(rho)),
                       "spearman_max": float(np.nanmax(rho))}), flush=True)
