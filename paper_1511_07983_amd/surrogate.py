@@ -284,11 +284,27 @@ def score_and_rerank(sur: "nn.Surrogate", table: SetTable, set_index: int, *, n_
                         exact=ms.cpu().numpy(), n_scored=n_score)
 
 
+def _capped_best(scores: np.ndarray, parent: np.ndarray, keep: int, max_children: int) -> np.ndarray:
+    """Indices of the `keep` best (lowest) scores, ties by index, taking at most
+    `max_children` candidates that share a parent."""
+    order = np.lexsort((np.arange(len(scores)), scores))
+    ps = parent[order]
+    by_parent = np.argsort(ps, kind="stable")
+    sorted_ps = ps[by_parent]
+    starts = np.r_[0, np.flatnonzero(np.diff(sorted_ps)) + 1]
+    run_start = np.repeat(starts, np.diff(np.r_[starts, len(sorted_ps)]))
+    rank = np.empty(len(order), dtype=np.int64)
+    rank[by_parent] = np.arange(len(sorted_ps)) - run_start
+    return order[rank < max_children][:keep]
+
+
 def beam_search(sur: "nn.Surrogate", table: SetTable, set_index: int, *, width: int = 256,
-                device="cuda:0") -> SearchResult:
+                max_children: int = 0, device="cuda:0") -> SearchResult:
     """Grow orders position by position, keeping the `width` best-scored
     prefixes (kernels not yet placed are "unplaced"); re-simulate the final
-    complete orders exactly."""
+    complete orders exactly.  With max_children > 0, at most that many children
+    of one prefix survive a step (a diversity rule: the beam cannot collapse
+    onto the descendants of a few prefixes)."""
     torch = _torch()
     n = table.n
     tab = sur.layer1_table(table.feat[set_index])
@@ -307,9 +323,15 @@ def beam_search(sur: "nn.Surrogate", table: SetTable, set_index: int, *, width: 
         scores = sur.forward_positions(tab, torch.from_numpy(pos).to(device))
         n_scored += len(cand)
         keep = min(width, len(cand))
-        idx, v = ko_topk_f32(scores, keep)
-        beams = cand[idx.cpu().numpy()]
-        val = v
+        if max_children > 0:
+            sc = scores.cpu().numpy()
+            sel = _capped_best(sc, parent, keep, max_children)
+            beams = cand[sel]
+            val = torch.from_numpy(sc[sel])
+        else:
+            idx, v = ko_topk_f32(scores, keep)
+            beams = cand[idx.cpu().numpy()]
+            val = v
     K = len(beams)
     orders = torch.from_numpy(beams.astype(np.uint8).ravel().copy()).to(device)
     ms = torch.empty(K, dtype=torch.int64, device=device)
@@ -410,7 +432,8 @@ def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: i
 
 def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets: int = 512, per_set: int = 8192,
                  eval_sets: int = 1024, width: int = 256, q_samples: int = 4096, steps: int = 8192,
-                 batch: int = 4096, lr: float = 1e-3, mask_frac: float = 0.25, seed: int = 2016, out=print):
+                 batch: int = 4096, lr: float = 1e-3, mask_frac: float = 0.25, seed: int = 2016,
+                 max_children: int = 0, out=print):
     """Beam search (width `width`) against uniform sampling at the same exact
     budget (`width` exact simulations per set).  The top-1% threshold of each
     set is the ceil(q_samples/100)-th smallest of `q_samples` exact random
@@ -454,7 +477,7 @@ def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets:
     t0 = time.perf_counter()
     rows = []
     for s in range(S):
-        res = beam_search(sur, etab, s, width=width)
+        res = beam_search(sur, etab, s, width=width, max_children=max_children)
         hit_b = np.flatnonzero(res.exact <= thr[s])
         hit_r = np.flatnonzero(rnd[s] <= thr[s])
         rows.append((int(res.exact.min()), int(rnd[s].min()), len(hit_b), len(hit_r),
@@ -464,6 +487,7 @@ def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets:
     better = float(np.mean(a[:, 0] < a[:, 1]))
     tie = float(np.mean(a[:, 0] == a[:, 1]))
     out(json.dumps({"phase": "beam_vs_random", "eval_sets": S, "n": etab.n, "width": width,
+                    "max_children": max_children,
                     "exact_budget_per_set": width, "q_samples": q_samples,
                     "best_ratio_beam_over_random_mean": float(np.mean(a[:, 0] / a[:, 1])),
                     "beam_better_frac": better, "tie_frac": tie,
@@ -495,12 +519,14 @@ if __name__ == "__main__":
     ap.add_argument("--beam", action="store_true", help="n=16 beam search vs random sampling instead")
     ap.add_argument("--eval-sets", type=int, default=1024)
     ap.add_argument("--width", type=int, default=256)
+    ap.add_argument("--max-children", type=int, default=0,
+                    help="beam: at most this many children of one prefix per step (0 = no cap)")
     a = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     if a.beam:
         report_beam(train_sets=a.train_sets, per_set=a.per_set, eval_sets=a.eval_sets, width=a.width,
-                    steps=a.steps, batch=a.batch, lr=a.lr)
+                    steps=a.steps, batch=a.batch, lr=a.lr, max_children=a.max_children)
         raise SystemExit(0)
     report(train_workload=a.train_workload, heldout_workload=a.heldout_workload, train_sets=a.train_sets,
            per_set=a.per_set, heldout=a.heldout, n_score=a.n_score, top_k=a.top_k, steps=a.steps,
