@@ -433,7 +433,7 @@ def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: i
 def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets: int = 512, per_set: int = 8192,
                  eval_sets: int = 1024, width: int = 256, q_samples: int = 4096, steps: int = 8192,
                  batch: int = 4096, lr: float = 1e-3, mask_frac: float = 0.25, seed: int = 2016,
-                 max_children: int = 0, out=print):
+                 max_children: int = 2, out=print):
     """Beam search (width `width`) against uniform sampling at the same exact
     budget (`width` exact simulations per set).  The top-1% threshold of each
     set is the ceil(q_samples/100)-th smallest of `q_samples` exact random
@@ -519,7 +519,7 @@ if __name__ == "__main__":
     ap.add_argument("--beam", action="store_true", help="n=16 beam search vs random sampling instead")
     ap.add_argument("--eval-sets", type=int, default=1024)
     ap.add_argument("--width", type=int, default=256)
-    ap.add_argument("--max-children", type=int, default=0,
+    ap.add_argument("--max-children", type=int, default=2,
                     help="beam: at most this many children of one prefix per step (0 = no cap)")
     a = ap.parse_args()
     import torch
