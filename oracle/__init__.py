@@ -10,7 +10,9 @@ is ``synth``, which draws inputs and holds none of the method's arithmetic.
 Parts:
   * ``ko_oracle.c``  discrete-event dispatch model, one block at a time
                       (Section 2 and Table 1), lexicographic unranking, many
-                      orders over threads.  Loaded here through ctypes.
+                      orders over threads, and the round-synchronous reading
+                      of Section 2's execution rounds.  Loaded here through
+                      ctypes.
   * ``heuristic``    Algorithm 1 (ScoreGen, ProfileCombine, execution rounds)
                       in binary64 Python floats.
   * ``tick``         a second formulation of the dispatch model that advances
@@ -74,6 +76,8 @@ def lib():
         L.oc_makespans_orders.argtypes = [i64p, ctypes.c_int32, i64p, i32p,
                                           ctypes.c_int64, i64p, ctypes.c_int32]
         L.oc_makespans_orders.restype = ctypes.c_int
+        L.oc_rounds_makespans.argtypes = [i64p, ctypes.c_int32, i64p, i32p, ctypes.c_int64, i64p]
+        L.oc_rounds_makespans.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -176,4 +180,21 @@ def makespans_orders(gpu, kernels, orders, threads: int | None = None) -> np.nda
                                    threads or default_threads())
     if rc:
         raise ValueError("invalid input")
+    return out
+
+
+def rounds_makespans(gpu, kernels, orders) -> np.ndarray:
+    """Makespans under the round-synchronous reading of Section 2's execution
+    rounds: a round closes when the head block fits on no CU and lasts as long
+    as its longest block; the makespan is the sum of the rounds.  orders is an
+    int array [count, n] of permutations."""
+    g, k = gpu_array(gpu), kernel_array(kernels)
+    o = np.ascontiguousarray(orders, dtype=np.int32)
+    if o.ndim != 2 or o.shape[1] != k.shape[0]:
+        raise ValueError("orders must be [count, n]")
+    out = np.zeros(o.shape[0], dtype=np.int64)
+    rc = lib().oc_rounds_makespans(_ptr(g, ctypes.c_int64), k.shape[0], _ptr(k, ctypes.c_int64),
+                                   _ptr(o, ctypes.c_int32), o.shape[0], _ptr(out, ctypes.c_int64))
+    if rc:
+        raise ValueError("invalid input (bad descriptor or an order is not a permutation)")
     return out

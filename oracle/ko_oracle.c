@@ -371,3 +371,93 @@ int oc_makespans_orders(const int64_t *gpu, int32_t n, const int64_t *kern, cons
     oc_job b = {gpu, kern, n, 2, 0, NULL, orders, 0, 0, out, 0};
     return run_many(b, count, threads);
 }
+
+/* ---- round-synchronous reading of the execution rounds (Section 2) ----
+ *
+ * Section 2 describes the blocks of a kernel set as split into execution
+ * rounds that run one after another.  In this second model a round is
+ * closed as soon as the head block of the stream fits on no CU; the next
+ * round starts only when every block of the closed round has finished, so
+ * each round lasts as long as its longest block, and the makespan is the
+ * sum of the round lengths.  Placement inside a round is the one above
+ * (stream order, cyclic pointer, first CU that fits); the pointer carries
+ * over from one round to the next.  Blocks never release resources in the
+ * middle of a round. */
+static int64_t simulate_rounds(oc_sim *s, const int32_t *order)
+{
+    const int32_t N = s->n_cu;
+    for (int32_t c = 0; c < N; c++)
+        for (int x = 0; x < 4; x++)
+            s->freec[4 * c + x] = s->cap[x];
+    int32_t ptr = 0;
+    int32_t pos = 0;
+    int64_t left = s->tblk[order[0]];
+    int64_t t = 0;          /* start of the open round */
+    int64_t longest = 0;    /* longest block placed in the open round */
+
+    while (pos < s->n) {
+        int32_t k = order[pos];
+        int32_t found = -1;
+        for (int32_t i = 0; i < N; i++) {
+            int32_t c = (ptr + i) % N;
+            if (fits(s, c, k)) {
+                found = c;
+                break;
+            }
+        }
+        if (found < 0) {
+            /* close the round: wait for all of its blocks, free every CU */
+            if (longest == 0)
+                return OC_EINVAL;   /* cannot happen for derived kernels */
+            t += longest;
+            longest = 0;
+            for (int32_t c = 0; c < N; c++)
+                for (int x = 0; x < 4; x++)
+                    s->freec[4 * c + x] = s->cap[x];
+            continue;
+        }
+        for (int x = 0; x < 4; x++)
+            s->freec[4 * found + x] -= s->use[4 * k + x];
+        if (s->dur[k] > longest)
+            longest = s->dur[k];
+        ptr = (found + 1) % N;
+        if (--left == 0) {
+            pos++;
+            if (pos < s->n)
+                left = s->tblk[order[pos]];
+        }
+    }
+    return t + longest;
+}
+
+/* Round-synchronous makespans of `count` explicit orders (orders[count*n],
+ * each a permutation of 0..n-1). */
+int oc_rounds_makespans(const int64_t *gpu, int32_t n, const int64_t *kern, const int32_t *orders,
+                        int64_t count, int64_t *out)
+{
+    int64_t use[4 * 32], dur[32], tblk[32];
+    if (n < 1 || n > 32 || count < 0)
+        return OC_EINVAL;
+    for (int64_t j = 0; j < count; j++) {
+        int seen[32] = {0};
+        const int32_t *o = orders + j * n;
+        for (int32_t p = 0; p < n; p++) {
+            if (o[p] < 0 || o[p] >= n || seen[o[p]])
+                return OC_EINVAL;
+            seen[o[p]] = 1;
+        }
+    }
+    oc_sim s;
+    int rc = sim_init(&s, gpu, n, kern, use, dur, tblk);
+    if (rc)
+        return rc;
+    for (int64_t j = 0; j < count; j++) {
+        out[j] = simulate_rounds(&s, orders + j * n);
+        if (out[j] < 0) {
+            rc = (int)out[j];
+            break;
+        }
+    }
+    sim_free(&s);
+    return rc;
+}
