@@ -42,7 +42,7 @@ EXPORTED = ("ko_heuristic_order", "ko_count_orders", "ko_simulate_batch", "ko_ra
             "ko_sync", "ko_shutdown", "ko_plan_create", "ko_plan_info", "ko_plan_launch", "ko_plan_status",
             "ko_plan_engine",
             "ko_plan_destroy", "ko_graph_capture", "ko_graph_launch", "ko_graph_destroy",
-            "ko_sample_orders", "ko_topk_f32", "ko_kth_smallest_i64",
+            "ko_sample_orders", "ko_topk_f32", "ko_kth_smallest_i64", "ko_simulate_rounds",
             "ko_set_kernel_timing", "ko_last_kernel_ms", "ko_hw_vgprs", "ko_hw_time_orders",
             "ko_hw_last_error", "ko_last_error")
 
@@ -153,6 +153,9 @@ def _L():
                                           ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p]
         lib.ko_sample_orders.restype = ctypes.c_int
+        lib.ko_simulate_rounds.argtypes = [ctypes.POINTER(KoGpuModel), ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
+        lib.ko_simulate_rounds.restype = ctypes.c_int
         lib.ko_topk_f32.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]
         lib.ko_topk_f32.restype = ctypes.c_int
@@ -461,6 +464,26 @@ def ko_sample_orders(n: int, set_index: int, seed: int, count: int, *, first: in
         ix = _dev_ptr(indices, indices.dtype, count, "indices")
     _check(_L().ko_sample_orders(int(n), int(set_index), int(seed) & ((1 << 64) - 1), int(first), ix,
                                  int(count), o, p, _stream_handle(stream)))
+
+
+def ko_simulate_rounds(gpu, kernels, orders, makespans=None, stream=None):
+    """Round-synchronous makespans (execution rounds of Section 2) of the launch
+    orders in the uint8 device tensor orders [count, n]; writes and returns the
+    int64 device tensor makespans [count].  Asynchronous on the stream."""
+    import torch
+    g = gpu_model(gpu)
+    k = kernel_array(kernels)
+    n = len(k)
+    if orders.dim() != 2 or orders.shape[1] != n:
+        raise ValueError("orders must be [count, n]")
+    count = orders.shape[0]
+    o = _dev_ptr(orders, torch.uint8, count * n, "orders")
+    if makespans is None:
+        makespans = torch.empty(count, dtype=torch.int64, device=orders.device)
+    m = _dev_ptr(makespans, torch.int64, count, "makespans")
+    _check(_L().ko_simulate_rounds(ctypes.byref(g), k.ctypes.data if n else None, n, o, int(count), m,
+                                   _stream_handle(stream)))
+    return makespans
 
 
 def ko_topk_f32(y, k: int, *, idx_out=None, val_out=None, stream=None):

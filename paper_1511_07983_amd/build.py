@@ -2,7 +2,8 @@
 
     python paper_1511_07983_amd/build.py
 
-compiles csrc/ko_host.cpp, ko_sim.hip, ko_lanes.hip, ko_select.hip and ko_hw.hip into
+compiles csrc/ko_host.cpp, ko_sim.hip, ko_lanes.hip, ko_rounds.hip, ko_select.hip and
+ko_hw.hip into
 paper_1511_07983_amd/libko.so,
 and csrc/ko_nn.hip (the learned surrogate) into paper_1511_07983_amd/libko_nn.so.
 Host code is built with -ffp-contract=off so the binary64 scores of the
@@ -60,8 +61,10 @@ def build(verbose: bool = True) -> str:
     lanes_o = os.path.join(objdir, "ko_lanes.o")
     _run([HIPCC, *COMMON, *DEVICE, *EXTRA.get("ko_lanes.hip", []), "-c", os.path.join(CSRC, "ko_lanes.hip"),
           "-o", lanes_o])
+    rounds_o = os.path.join(objdir, "ko_rounds.o")
+    _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_rounds.hip"), "-o", rounds_o])
     tmp = LIB + ".tmp"
-    _run([HIPCC, *DEVICE, "-shared", "-fPIC", host_o, sim_o, sel_o, hw_o, lanes_o, "-o", tmp])
+    _run([HIPCC, *DEVICE, "-shared", "-fPIC", host_o, sim_o, sel_o, hw_o, lanes_o, rounds_o, "-o", tmp])
     os.replace(tmp, LIB)
     nn_o = os.path.join(objdir, "ko_nn.o")
     _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ko_nn.hip"), "-o", nn_o])

@@ -17,6 +17,7 @@
 
 #include "ko.h"
 #include "ko_device.h"
+#include "ko_rounds.h"
 #include "ko_select.h"
 
 namespace {
@@ -1393,6 +1394,47 @@ int ko_shutdown(void)
         release_workspace(w);
     g_ws.clear();
     return KO_OK;
+}
+
+int ko_simulate_rounds(const ko_gpu_model *gpu, const ko_kernel *kernels, int32_t n,
+                       const uint8_t *orders_dev, uint64_t count, int64_t *makespans_dev, void *hip_stream)
+{
+    try {
+        int rc = check_gpu(gpu);
+        if (rc)
+            return rc;
+        if (!kernels)
+            return fail(KO_EINVAL, "kernels must not be NULL");
+        if (n < 1 || n > ko::kMaxSet)
+            return fail(KO_EINVAL, "n %d outside 1..%d", n, ko::kMaxSet);
+        if (count > (uint64_t(1) << 40))
+            return fail(KO_ERANGE, "count above 2^40");
+        if (count && (!orders_dev || !makespans_dev))
+            return fail(KO_EINVAL, "orders_dev and makespans_dev must not be NULL");
+        std::vector<ko::KernelRec> recs;
+        if ((rc = derive_set(*gpu, kernels, n, 0, &recs)))
+            return rc;
+        if (count == 0)
+            return KO_OK;
+        ko::RoundsArgs a{};
+        for (int32_t i = 0; i < n; i++)
+            a.k[i] = recs[i];
+        a.orders = orders_dev;
+        a.makespans = makespans_dev;
+        a.count = count;
+        a.n = (uint32_t)n;
+        a.n_cu = (uint32_t)gpu->n_cu;
+        a.cap_reg = (uint32_t)gpu->reg_cu;
+        a.cap_lds = (uint32_t)gpu->lds_cu;
+        a.cap_wave = (uint32_t)gpu->wave_cu;
+        a.cap_blk = (uint32_t)gpu->blk_cu;
+        int e = ko::launch_rounds(a, hip_stream);
+        if (e)
+            return hip_fail((hipError_t)e, "rounds launch");
+        return KO_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(KO_ENOMEM, "host allocation failed");
+    }
 }
 
 int ko_sample_orders(int32_t n, int32_t set_index, uint64_t seed, uint64_t first,

@@ -1,0 +1,22 @@
+// Launcher of ko_rounds.hip (internal to libko): makespans under the
+// round-synchronous model.  Returns a hipError_t value as int.
+#pragma once
+
+#include <stdint.h>
+
+#include "ko_device.h"
+
+namespace ko {
+
+struct RoundsArgs {
+    KernelRec k[kMaxSet];     // derived records of the set, by kernel index
+    const uint8_t *orders;    // [count][n], order[j] = kernel at position j
+    int64_t *makespans;       // [count]; -1 for an order with an index >= n
+    uint64_t count;
+    uint32_t n, n_cu;
+    uint32_t cap_reg, cap_lds, cap_wave, cap_blk;
+};
+
+int launch_rounds(const RoundsArgs &a, void *stream);
+
+}  // namespace ko

@@ -1,0 +1,216 @@
+// Round-synchronous execution rounds (Section 2 of Li, Narayana & El-Ghazawi
+// 2015): the blocks of a kernel set, in launch order, are split into rounds
+// that run one after another.  A round takes blocks from the front of the
+// stream, each on the first CU at or after a cyclic pointer that has room
+// (registers, LDS, waves, block slots; Table 1), until the front block fits on
+// no CU.  The round then lasts as long as its longest block, every CU is freed,
+// and the next round starts with that block.  The pointer carries over.  No
+// block releases its resources in the middle of a round, so the makespan is
+// the sum of the round lengths.
+//
+// Mapping.  One wavefront per launch order; lane l holds the free resources of
+// CUs l, l+64, l+128, l+192 (S slots).  Because nothing is released inside a
+// round, the blocks of one kernel that enter a round are placed in one bulk
+// step: with cap[c] = blocks of the kernel that CU c can still take, a cyclic
+// sweep from the pointer places one block on every CU with cap >= 1, then one
+// on every CU with cap >= 2, and so on.  Placing q blocks therefore gives each
+// CU min(cap, r-1) blocks plus one more to the first q - A(r-1) CUs of
+// {cap >= r} in pointer order, where A(r) = sum of min(cap, r) and r is the
+// first pass with A(r) >= q; the pointer ends just past the last of them.  A
+// kernel needs one bulk step per round it spans.  All control flow depends on
+// wave-uniform values only, so wave collectives always run with every lane.
+#include <hip/hip_runtime.h>
+
+#include "ko_device.h"
+#include "ko_rounds.h"
+#include "ko_wave.h"
+
+namespace ko {
+namespace {
+
+constexpr int kRoundsWaves = 4;          // wavefronts per workgroup
+constexpr uint32_t kRoundsGridCap = 4096;
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+    for (int o = 32; o >= 1; o >>= 1)
+        v += (uint32_t)__shfl_xor((int)v, o);
+    return v;
+}
+
+// Bits of word s (CUs 64s .. 64s+63) that are at or after CU `from`.
+__device__ __forceinline__ uint64_t at_or_after(uint32_t from, int s)
+{
+    const uint32_t base = 64u * (uint32_t)s;
+    if (from <= base)
+        return ~0ull;
+    if (from >= base + 64u)
+        return 0ull;
+    return ~0ull << (from - base);
+}
+
+// CU of the j-th member (1-based) of `mem` among CUs >= from, ascending; the
+// caller guarantees there are at least j.  Uniform scalar work.
+template <int S>
+__device__ uint32_t nth_from(const uint64_t (&mem)[S], uint32_t from, uint32_t j)
+{
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        uint64_t w = mem[s] & at_or_after(from, s);
+        const uint32_t pc = (uint32_t)__popcll(w);
+        if (j <= pc) {
+            for (uint32_t i = 1; i < j; ++i)
+                w &= w - 1;
+            return 64u * (uint32_t)s + (uint32_t)__builtin_ctzll(w);
+        }
+        j -= pc;
+    }
+    return 0;
+}
+
+// CU that receives the j-th block of the last pass: the j-th member of `mem`
+// counted cyclically from the pointer.
+template <int S>
+__device__ uint32_t cyclic_nth(const uint64_t (&mem)[S], uint32_t ptr, uint32_t j)
+{
+    uint32_t upper = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        upper += (uint32_t)__popcll(mem[s] & at_or_after(ptr, s));
+    return j <= upper ? nth_from<S>(mem, ptr, j) : nth_from<S>(mem, 0, j - upper);
+}
+
+template <int S>
+__device__ int64_t rounds_order(const RoundsArgs &a, const KernelRec *tab, uint32_t mine, uint32_t lane)
+{
+    const uint32_t n = a.n, ncu = a.n_cu;
+    uint32_t fr_reg[S], fr_lds[S], fr_wave[S], fr_blk[S];
+    auto reset = [&]() {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            fr_reg[s] = a.cap_reg;
+            fr_lds[s] = a.cap_lds;
+            fr_wave[s] = a.cap_wave;
+            fr_blk[s] = lane + 64u * (uint32_t)s < ncu ? a.cap_blk : 0u;   // absent CUs take nothing
+        }
+    };
+    reset();
+    int64_t t = 0;          // start of the open round
+    uint32_t longest = 0;   // longest block placed in the open round
+    uint32_t ptr = 0;
+    for (uint32_t pos = 0; pos < n; ++pos) {
+        const uint32_t k = read_lane(mine, pos);
+        if (k >= n)
+            return -1;
+        const KernelRec kr = tab[k];
+        uint32_t rem = kr.tblk;
+        while (rem) {
+            uint32_t cap[S];
+            uint32_t tot = 0, cmax = 0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                uint32_t c = div_clamp(fr_reg[s], kr.u_reg, kr.inv_reg, fr_blk[s]);
+                c = div_clamp(fr_wave[s], kr.u_wave, kr.inv_wave, c);
+                if (kr.u_lds)
+                    c = div_clamp(fr_lds[s], kr.u_lds, kr.inv_lds, c);
+                cap[s] = c;
+                tot += c;
+                cmax = max(cmax, c);
+            }
+            tot = uniform(wave_sum(tot));
+            if (tot == 0) {
+                // the front block fits nowhere: the round ends with its longest block
+                if (longest == 0)
+                    return -1;   // a block that fits no empty CU (rejected by the host)
+                t += longest;
+                longest = 0;
+                reset();
+                continue;
+            }
+            cmax = uniform(wave_max(cmax));
+            const uint32_t q = min(tot, rem);
+            uint32_t r = cmax;
+            if (q < tot) {
+                uint32_t lo = 1, hi = cmax;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    uint32_t part = 0;
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        part += min(cap[s], mid);
+                    if (uniform(wave_sum(part)) >= q)
+                        hi = mid;
+                    else
+                        lo = mid + 1;
+                }
+                r = lo;
+            }
+            uint32_t below = 0;
+            uint64_t mem[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                below += min(cap[s], r - 1);
+                mem[s] = ballot(cap[s] >= r);
+            }
+            below = uniform(wave_sum(below));
+            const uint32_t cut = uniform(cyclic_nth<S>(mem, ptr, q - below));
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const uint32_t c = lane + 64u * (uint32_t)s;
+                const bool in = ptr <= cut ? (c >= ptr && c <= cut) : (c >= ptr || c <= cut);
+                const uint32_t cnt = min(cap[s], r - 1) + ((cap[s] >= r && in) ? 1u : 0u);
+                fr_reg[s] -= cnt * kr.u_reg;
+                fr_lds[s] -= cnt * kr.u_lds;
+                fr_wave[s] -= cnt * kr.u_wave;
+                fr_blk[s] -= cnt;
+            }
+            ptr = cut + 1 == ncu ? 0u : cut + 1;
+            longest = max(longest, kr.dur);
+            rem -= q;
+        }
+    }
+    return t + longest;
+}
+
+template <int S>
+__global__ __launch_bounds__(64 * kRoundsWaves) void rounds_kernel(RoundsArgs a)
+{
+    __shared__ KernelRec tab[kMaxSet];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kMaxSet; ++i)
+            if (i < (int)a.n)
+                tab[i] = a.k[i];
+    }
+    __syncthreads();
+    const uint32_t lane = lane_id();
+    const uint64_t first = (uint64_t)blockIdx.x * kRoundsWaves + uniform(threadIdx.x >> 6);
+    const uint64_t stride = (uint64_t)gridDim.x * kRoundsWaves;
+    for (uint64_t i = first; i < a.count; i += stride) {
+        const uint32_t mine = lane < a.n ? (uint32_t)a.orders[i * a.n + lane] : 0u;
+        const int64_t m = rounds_order<S>(a, tab, mine, lane);
+        // every lane stores the same value: no lane-dependent branch in the loop
+        a.makespans[i] = m;
+    }
+}
+
+}  // namespace
+
+int launch_rounds(const RoundsArgs &a, void *stream)
+{
+    if (a.count == 0)
+        return (int)hipSuccess;
+    const uint64_t want = (a.count + kRoundsWaves - 1) / kRoundsWaves;
+    const dim3 grid((uint32_t)(want < kRoundsGridCap ? want : kRoundsGridCap));
+    const dim3 block(64 * kRoundsWaves);
+    hipStream_t s = (hipStream_t)stream;
+    switch ((a.n_cu + 63) / 64) {
+    case 1: hipLaunchKernelGGL(rounds_kernel<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(rounds_kernel<2>, grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(rounds_kernel<3>, grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL(rounds_kernel<4>, grid, block, 0, s, a); break;
+    }
+    return (int)hipGetLastError();
+}
+
+}  // namespace ko

@@ -61,6 +61,12 @@ def lanes_report(tmp_path_factory):
 
 
 @pytest.fixture(scope="module")
+def rounds_report(tmp_path_factory):
+    d = tmp_path_factory.mktemp("isa")
+    return ic.check(_asm(os.path.join(CSRC, "ko_rounds.hip"), str(d / "ko_rounds.s")))
+
+
+@pytest.fixture(scope="module")
 def nn_report(tmp_path_factory):
     d = tmp_path_factory.mktemp("isa")
     return ic.check(_asm(os.path.join(CSRC, "ko_nn.hip"), str(d / "ko_nn.s")))
@@ -89,6 +95,17 @@ def test_lane_kernels_collectives_full_exec(lanes_report, needle):
     for name in _pick(lanes_report, needle):
         bad, _ = lanes_report[name]
         assert bad == [], (name, bad[:5])
+
+
+@pytest.mark.parametrize("needle", ["rounds_kernelILi1E", "rounds_kernelILi2E", "rounds_kernelILi3E",
+                                    "rounds_kernelILi4E"])
+def test_rounds_collectives_full_exec(rounds_report, needle):
+    """The round-synchronous kernel branches on wave-uniform values only: no
+    collective under a partial exec mask and no lane-divergent loop."""
+    for name in _pick(rounds_report, needle):
+        bad, div_loops = rounds_report[name]
+        assert bad == [], (name, bad[:5])
+        assert div_loops == 0, (name, div_loops)
 
 
 def test_spill_kernel_collectives_full_exec(sim_report):

@@ -1,0 +1,111 @@
+"""Round-synchronous execution rounds (Section 2) on the GPU: ko_simulate_rounds
+against the oracle's block-by-block simulation, element by element."""
+
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ko = pytest.importorskip("paper_1511_07983_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _gpu_rounds(gpu, ks, orders):
+    o = torch.from_numpy(np.ascontiguousarray(orders, dtype=np.uint8)).cuda()
+    m = ko.ko_simulate_rounds(gpu, ks, o)
+    torch.cuda.synchronize()
+    return m.cpu().numpy()
+
+
+def _check(gpu, ks, orders, label):
+    print(f"rounds parity: {label} n={len(ks)} orders={len(orders)}", flush=True)
+    sys.stdout.flush()
+    want = oracle.rounds_makespans(gpu, ks, orders)
+    got = _gpu_rounds(gpu, ks, orders)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, (label, bad[:5].tolist(), got[bad[:5]].tolist(), want[bad[:5]].tolist())
+
+
+def test_rounds_hand_trace(golden):
+    g = golden("e4_rounds.json")
+    got = _gpu_rounds(g["gpu"], g["kernels"], g["orders"])
+    assert got.tolist() == g["rounds_makespans"]
+
+
+@pytest.mark.parametrize("n_cu", [1, 3, 16, 64, 65, 100, 130, 200, 256])
+def test_rounds_all_orders_small_sets(n_cu):
+    # every order of random sets; CU counts cover 1..4 slots per lane and
+    # ragged last slots
+    model = synth.GpuModel(n_cu=n_cu, wave_size=64, wave_cu=32, blk_cu=8,
+                           reg_cu=131072, lds_cu=163840, rb_milli=10000)
+    rng = np.random.default_rng(1000 + n_cu)
+    for rep in range(3):
+        n = int(rng.integers(3, 7))
+        ks = synth.random_tiny_set(rng, n, model, tblk_hi=max(4, 3 * n_cu), inst_hi=5000)
+        orders = np.array(list(itertools.permutations(range(n))), dtype=np.int32)
+        _check(model.as_dict(), ks, orders, f"n_cu={n_cu} rep={rep}")
+
+
+@pytest.mark.parametrize("model_name", ["SMALL_MODEL", "GTX580_MODEL"])
+def test_rounds_all_orders_seven_kernels(model_name):
+    model = getattr(synth, model_name)
+    rng = np.random.default_rng(77)
+    ks = synth.random_tiny_set(rng, 7, model, tblk_hi=200, inst_hi=900)
+    orders = np.array(list(itertools.permutations(range(7))), dtype=np.int32)
+    _check(model.as_dict(), ks, orders, model_name)
+
+
+def test_rounds_n10_workload_sampled():
+    # the n=10 set of the all-orders workload on the MI355X-shaped model,
+    # 20,000 seeded orders
+    wl = synth.WORKLOADS[1]
+    ks = synth.draw_set(1, 0)
+    rng = np.random.default_rng(2015)
+    orders = np.array([rng.permutation(10) for _ in range(20000)], dtype=np.int32)
+    _check(wl.model.as_dict(), ks, orders, wl.name)
+
+
+def test_rounds_largest_sets():
+    # n = 20, the largest set the ABI takes, and n = 16 search-workload sets
+    model = synth.MI355X_MODEL
+    rng = np.random.default_rng(20)
+    ks = synth.draw_kernels(rng, 20, 64, 8192)
+    orders = np.array([rng.permutation(20) for _ in range(500)], dtype=np.int32)
+    _check(model.as_dict(), ks, orders, "n=20")
+    for s in range(4):
+        ks = synth.draw_set(4, s)
+        orders = np.array([rng.permutation(16) for _ in range(500)], dtype=np.int32)
+        _check(model.as_dict(), ks, orders, f"n=16 set {s}")
+
+
+def test_rounds_paper_sets():
+    from synth import paper_sets
+    for name, ks in paper_sets.EXPERIMENTS.items():
+        n = len(ks)
+        orders = np.array(list(itertools.permutations(range(n))), dtype=np.int32)
+        _check(paper_sets.MODEL.as_dict(), ks, orders, name)
+
+
+def test_rounds_bad_index_and_empty():
+    model = synth.SMALL_MODEL
+    ks = synth.random_tiny_set(np.random.default_rng(4), 4, model)
+    orders = np.array([[0, 1, 2, 3], [0, 1, 9, 3], [3, 2, 1, 0]], dtype=np.uint8)
+    got = _gpu_rounds(model.as_dict(), ks, orders)
+    want = oracle.rounds_makespans(model.as_dict(), ks, orders[[0, 2]].astype(np.int32))
+    assert got.tolist() == [int(want[0]), -1, int(want[1])]
+    empty = torch.empty((0, 4), dtype=torch.uint8, device="cuda")
+    assert ko.ko_simulate_rounds(model.as_dict(), ks, empty).numel() == 0
