@@ -18,7 +18,8 @@
 // {cap >= r} in pointer order, where A(r) = sum of min(cap, r) and r is the
 // first pass with A(r) >= q; the pointer ends just past the last of them.  A
 // kernel needs one bulk step per round it spans.  All control flow depends on
-// wave-uniform values only, so wave collectives always run with every lane.
+// wave-uniform values only, so wave collectives always run with every lane;
+// sums and maxima over CUs are DPP reductions within the wave.
 #include <hip/hip_runtime.h>
 
 #include "ko_device.h"
@@ -31,11 +32,38 @@ namespace {
 constexpr int kRoundsWaves = 4;          // wavefronts per workgroup
 constexpr uint32_t kRoundsGridCap = 4096;
 
+// Lane-shifted copy of v through DPP: lanes whose source lies outside their
+// row of 16 read 0, lanes in rows left out of RowMask read 0.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ uint32_t dpp(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, RowMask, 0xf, true);
+}
+
+// Sum and maximum over the 64 lanes, in every lane.  Shifts by 1, 2, 4 and 8
+// within each row of 16 make lane 15 of a row hold the row's total; the row
+// broadcasts of lane 15 (into rows 1 and 3) and of lane 31 (into rows 2 and 3)
+// then leave the wave's total in lane 63, which is read back as a scalar.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
-    for (int o = 32; o >= 1; o >>= 1)
-        v += (uint32_t)__shfl_xor((int)v, o);
-    return v;
+    v += dpp<0x111, 0xf>(v);   // row_shr:1
+    v += dpp<0x112, 0xf>(v);   // row_shr:2
+    v += dpp<0x114, 0xf>(v);   // row_shr:4
+    v += dpp<0x118, 0xf>(v);   // row_shr:8
+    v += dpp<0x142, 0xa>(v);   // row_bcast:15
+    v += dpp<0x143, 0xc>(v);   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ uint32_t wave_umax(uint32_t v)
+{
+    v = max(v, dpp<0x111, 0xf>(v));
+    v = max(v, dpp<0x112, 0xf>(v));
+    v = max(v, dpp<0x114, 0xf>(v));
+    v = max(v, dpp<0x118, 0xf>(v));
+    v = max(v, dpp<0x142, 0xa>(v));
+    v = max(v, dpp<0x143, 0xc>(v));
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Bits of word s (CUs 64s .. 64s+63) that are at or after CU `from`.
@@ -117,7 +145,7 @@ __device__ int64_t rounds_order(const RoundsArgs &a, const KernelRec *tab, uint3
                 tot += c;
                 cmax = max(cmax, c);
             }
-            tot = uniform(wave_sum(tot));
+            tot = wave_sum(tot);
             if (tot == 0) {
                 // the front block fits nowhere: the round ends with its longest block
                 if (longest == 0)
@@ -127,7 +155,7 @@ __device__ int64_t rounds_order(const RoundsArgs &a, const KernelRec *tab, uint3
                 reset();
                 continue;
             }
-            cmax = uniform(wave_max(cmax));
+            cmax = wave_umax(cmax);
             const uint32_t q = min(tot, rem);
             uint32_t r = cmax;
             if (q < tot) {
@@ -138,7 +166,7 @@ __device__ int64_t rounds_order(const RoundsArgs &a, const KernelRec *tab, uint3
 #pragma unroll
                     for (int s = 0; s < S; ++s)
                         part += min(cap[s], mid);
-                    if (uniform(wave_sum(part)) >= q)
+                    if (wave_sum(part) >= q)
                         hi = mid;
                     else
                         lo = mid + 1;
@@ -152,7 +180,7 @@ __device__ int64_t rounds_order(const RoundsArgs &a, const KernelRec *tab, uint3
                 below += min(cap[s], r - 1);
                 mem[s] = ballot(cap[s] >= r);
             }
-            below = uniform(wave_sum(below));
+            below = wave_sum(below);
             const uint32_t cut = uniform(cyclic_nth<S>(mem, ptr, q - below));
 #pragma unroll
             for (int s = 0; s < S; ++s) {
