@@ -77,6 +77,23 @@ __device__ __forceinline__ uint64_t at_or_after(uint32_t from, int s)
     return ~0ull << (from - base);
 }
 
+// Position of the j-th set bit (1-based) of w, which has at least j: halve
+// the window six times, skipping its low half when that holds fewer than j.
+__device__ __forceinline__ uint32_t nth_bit(uint64_t w, uint32_t j)
+{
+    uint32_t pos = 0;
+#pragma unroll
+    for (int width = 32; width >= 1; width >>= 1) {
+        const uint32_t c = (uint32_t)__popcll(w & ((1ull << width) - 1));
+        if (j > c) {
+            j -= c;
+            w >>= width;
+            pos += (uint32_t)width;
+        }
+    }
+    return pos;
+}
+
 // CU of the j-th member (1-based) of `mem` among CUs >= from, ascending; the
 // caller guarantees there are at least j.  Uniform scalar work.
 template <int S>
@@ -84,13 +101,10 @@ __device__ uint32_t nth_from(const uint64_t (&mem)[S], uint32_t from, uint32_t j
 {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        uint64_t w = mem[s] & at_or_after(from, s);
+        const uint64_t w = mem[s] & at_or_after(from, s);
         const uint32_t pc = (uint32_t)__popcll(w);
-        if (j <= pc) {
-            for (uint32_t i = 1; i < j; ++i)
-                w &= w - 1;
-            return 64u * (uint32_t)s + (uint32_t)__builtin_ctzll(w);
-        }
+        if (j <= pc)
+            return 64u * (uint32_t)s + nth_bit(w, j);
         j -= pc;
     }
     return 0;
