@@ -109,3 +109,20 @@ def test_rounds_bad_index_and_empty():
     assert got.tolist() == [int(want[0]), -1, int(want[1])]
     empty = torch.empty((0, 4), dtype=torch.uint8, device="cuda")
     assert ko.ko_simulate_rounds(model.as_dict(), ks, empty).numel() == 0
+
+
+def test_rounds_in_paper_report():
+    # the report's round-model columns against the oracle over all orders
+    from paper_1511_07983_amd import paper_report
+    from synth import paper_sets
+    rows = paper_report.report(out=lambda *a, **k: None)
+    assert [r["experiment"] for r in rows] == list(paper_sets.EXPERIMENTS)
+    for row in rows:
+        ks = paper_sets.EXPERIMENTS[row["experiment"]]
+        orders = np.array(list(itertools.permutations(range(len(ks)))), dtype=np.int32)
+        want = oracle.rounds_makespans(paper_sets.MODEL.as_dict(), ks, orders)
+        h = int(oracle.rounds_makespans(paper_sets.MODEL.as_dict(), ks, [row["algorithm_order"]])[0])
+        r = row["rounds"]
+        assert (r["best_cycles"], r["worst_cycles"], r["algorithm_cycles"]) == \
+            (int(want.min()), int(want.max()), h), row["experiment"]
+        assert r["percentile_inclusive"] == round(100.0 * float((want >= h).mean()), 2)
