@@ -299,7 +299,7 @@ int ko_graph_launch(ko_graph *graph, void *hip_stream);
 /* ko_graph_destroy — wait for the device, free the graph (NULL is a no-op). */
 int ko_graph_destroy(ko_graph *graph);
 
-/* ko_simulate_rounds — makespans of explicit launch orders under the
+/* ko_simulate_rounds — makespans of launch orders under the
  * round-synchronous reading of Section 2's execution rounds.  Blocks are taken
  * from the front of the kernel-major stream and placed as in
  * ko_simulate_batch (first CU at or after the cyclic pointer with room for
@@ -311,14 +311,18 @@ int ko_graph_destroy(ko_graph *graph);
  *                    as in ko_simulate_batch
  *   orders_dev       uint8 [count][n], device: order[j] = kernel at position j;
  *                    each row must be a permutation of 0..n-1 (repeats are not
- *                    detected; a row with an entry >= n gets makespan -1)
+ *                    detected; a row with an entry >= n gets makespan -1).
+ *                    NULL: the orders of lexicographic ranks first ..
+ *                    first+count-1 among all n! orders, unranked on the device
+ *   first            first rank when orders_dev is NULL, else 0
  *   makespans_dev    int64 [count], device, written: cycles
  * count <= 2^40; count 0 validates and returns.  Asynchronous on hip_stream;
  * the caller keeps both buffers alive until the stream has passed the call.
- * Errors: KO_EINVAL (model, kernels, n, NULL buffers), KO_ERANGE (count),
- * KO_EHIP (launch). */
+ * Errors: KO_EINVAL (model, kernels, n, NULL makespans, first with explicit
+ * orders), KO_ERANGE (count, ranks past n!), KO_EHIP (launch). */
 int ko_simulate_rounds(const ko_gpu_model *gpu, const ko_kernel *kernels, int32_t n,
-                       const uint8_t *orders_dev, uint64_t count, int64_t *makespans_dev, void *hip_stream);
+                       const uint8_t *orders_dev, uint64_t first, uint64_t count, int64_t *makespans_dev,
+                       void *hip_stream);
 
 /* ko_sample_orders — the launch orders that ko_simulate_batch evaluates in
  * KO_ORDERS_SAMPLED mode for the set at batch index set_index (seed as in

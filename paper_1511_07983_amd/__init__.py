@@ -154,7 +154,8 @@ def _L():
                                           ctypes.c_void_p, ctypes.c_void_p]
         lib.ko_sample_orders.restype = ctypes.c_int
         lib.ko_simulate_rounds.argtypes = [ctypes.POINTER(KoGpuModel), ctypes.c_void_p, ctypes.c_int32,
-                                            ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
+                                            ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p,
+                                            ctypes.c_void_p]
         lib.ko_simulate_rounds.restype = ctypes.c_int
         lib.ko_topk_f32.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]
@@ -466,23 +467,31 @@ def ko_sample_orders(n: int, set_index: int, seed: int, count: int, *, first: in
                                  int(count), o, p, _stream_handle(stream)))
 
 
-def ko_simulate_rounds(gpu, kernels, orders, makespans=None, stream=None):
+def ko_simulate_rounds(gpu, kernels, orders=None, makespans=None, *, first: int = 0, count=None, stream=None):
     """Round-synchronous makespans (execution rounds of Section 2) of the launch
-    orders in the uint8 device tensor orders [count, n]; writes and returns the
-    int64 device tensor makespans [count].  Asynchronous on the stream."""
+    orders in the uint8 device tensor orders [count, n], or with orders=None of
+    the lexicographic ranks first .. first+count-1; writes and returns the int64
+    device tensor makespans [count].  Asynchronous on the stream."""
     import torch
     g = gpu_model(gpu)
     k = kernel_array(kernels)
     n = len(k)
-    if orders.dim() != 2 or orders.shape[1] != n:
-        raise ValueError("orders must be [count, n]")
-    count = orders.shape[0]
-    o = _dev_ptr(orders, torch.uint8, count * n, "orders")
+    if orders is not None:
+        if orders.dim() != 2 or orders.shape[1] != n:
+            raise ValueError("orders must be [count, n]")
+        count = orders.shape[0]
+        o = _dev_ptr(orders, torch.uint8, count * n, "orders")
+        dev = orders.device
+    else:
+        if count is None:
+            raise ValueError("count is required when orders is None")
+        o = None
+        dev = makespans.device if makespans is not None else torch.device("cuda", torch.cuda.current_device())
     if makespans is None:
-        makespans = torch.empty(count, dtype=torch.int64, device=orders.device)
-    m = _dev_ptr(makespans, torch.int64, count, "makespans")
-    _check(_L().ko_simulate_rounds(ctypes.byref(g), k.ctypes.data if n else None, n, o, int(count), m,
-                                   _stream_handle(stream)))
+        makespans = torch.empty(int(count), dtype=torch.int64, device=dev)
+    m = _dev_ptr(makespans, torch.int64, int(count), "makespans")
+    _check(_L().ko_simulate_rounds(ctypes.byref(g), k.ctypes.data if n else None, n, o, int(first), int(count),
+                                   m, _stream_handle(stream)))
     return makespans
 
 

@@ -1397,7 +1397,8 @@ int ko_shutdown(void)
 }
 
 int ko_simulate_rounds(const ko_gpu_model *gpu, const ko_kernel *kernels, int32_t n,
-                       const uint8_t *orders_dev, uint64_t count, int64_t *makespans_dev, void *hip_stream)
+                       const uint8_t *orders_dev, uint64_t first, uint64_t count, int64_t *makespans_dev,
+                       void *hip_stream)
 {
     try {
         int rc = check_gpu(gpu);
@@ -1409,8 +1410,12 @@ int ko_simulate_rounds(const ko_gpu_model *gpu, const ko_kernel *kernels, int32_
             return fail(KO_EINVAL, "n %d outside 1..%d", n, ko::kMaxSet);
         if (count > (uint64_t(1) << 40))
             return fail(KO_ERANGE, "count above 2^40");
-        if (count && (!orders_dev || !makespans_dev))
-            return fail(KO_EINVAL, "orders_dev and makespans_dev must not be NULL");
+        if (count && !makespans_dev)
+            return fail(KO_EINVAL, "makespans_dev must not be NULL");
+        if (orders_dev && first != 0)
+            return fail(KO_EINVAL, "first must be 0 with explicit orders");
+        if (!orders_dev && (first > factorial(n) || count > factorial(n) - first))
+            return fail(KO_ERANGE, "ranks first .. first+count-1 must stay below n!");
         std::vector<ko::KernelRec> recs;
         if ((rc = derive_set(*gpu, kernels, n, 0, &recs)))
             return rc;
@@ -1421,6 +1426,7 @@ int ko_simulate_rounds(const ko_gpu_model *gpu, const ko_kernel *kernels, int32_
             a.k[i] = recs[i];
         a.orders = orders_dev;
         a.makespans = makespans_dev;
+        a.first = first;
         a.count = count;
         a.n = (uint32_t)n;
         a.n_cu = (uint32_t)gpu->n_cu;

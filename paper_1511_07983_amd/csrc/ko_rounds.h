@@ -10,8 +10,10 @@ namespace ko {
 
 struct RoundsArgs {
     KernelRec k[kMaxSet];     // derived records of the set, by kernel index
-    const uint8_t *orders;    // [count][n], order[j] = kernel at position j
+    const uint8_t *orders;    // [count][n], order[j] = kernel at position j; or NULL:
+                              // lexicographic ranks first .. first+count-1
     int64_t *makespans;       // [count]; -1 for an order with an index >= n
+    uint64_t first;
     uint64_t count;
     uint32_t n, n_cu;
     uint32_t cap_reg, cap_lds, cap_wave, cap_blk;

@@ -229,7 +229,8 @@ __global__ __launch_bounds__(64 * kRoundsWaves) void rounds_kernel(RoundsArgs a)
     const uint64_t first = (uint64_t)blockIdx.x * kRoundsWaves + uniform(threadIdx.x >> 6);
     const uint64_t stride = (uint64_t)gridDim.x * kRoundsWaves;
     for (uint64_t i = first; i < a.count; i += stride) {
-        const uint32_t mine = lane < a.n ? (uint32_t)a.orders[i * a.n + lane] : 0u;
+        const uint32_t mine = a.orders ? (lane < a.n ? (uint32_t)a.orders[i * a.n + lane] : 0u)
+                                       : unrank_lanes(a.first + i, a.n);
         const int64_t m = rounds_order<S>(a, tab, mine, lane);
         // every lane stores the same value: no lane-dependent branch in the loop
         a.makespans[i] = m;

@@ -194,13 +194,15 @@ def test_sampling_and_selection_reject_bad_arguments_before_device_work():
     ks = ko.kernel_array(synth.random_tiny_set(np.random.default_rng(0), 4, synth.SMALL_MODEL))
     kp = ks.ctypes.data
     rounds = lib.ko_simulate_rounds
-    assert rounds(ctypes.byref(g), kp, 0, fake, 4, fake, None) == ko.KO_EINVAL
-    assert rounds(ctypes.byref(g), kp, 21, fake, 4, fake, None) == ko.KO_EINVAL
-    assert rounds(ctypes.byref(g), kp, 4, None, 4, fake, None) == ko.KO_EINVAL
-    assert rounds(ctypes.byref(g), kp, 4, fake, 4, None, None) == ko.KO_EINVAL
-    assert rounds(ctypes.byref(g), kp, 4, fake, (1 << 40) + 1, fake, None) == ko.KO_ERANGE
-    assert rounds(None, kp, 4, fake, 4, fake, None) == ko.KO_EINVAL
-    assert rounds(ctypes.byref(g), kp, 4, None, 0, None, None) == ko.KO_OK
+    assert rounds(ctypes.byref(g), kp, 0, fake, 0, 4, fake, None) == ko.KO_EINVAL
+    assert rounds(ctypes.byref(g), kp, 21, fake, 0, 4, fake, None) == ko.KO_EINVAL
+    assert rounds(ctypes.byref(g), kp, 4, fake, 0, 4, None, None) == ko.KO_EINVAL
+    assert rounds(ctypes.byref(g), kp, 4, fake, 1, 4, fake, None) == ko.KO_EINVAL
+    assert rounds(ctypes.byref(g), kp, 4, fake, 0, (1 << 40) + 1, fake, None) == ko.KO_ERANGE
+    assert rounds(ctypes.byref(g), kp, 4, None, 20, 5, fake, None) == ko.KO_ERANGE
+    assert rounds(ctypes.byref(g), kp, 4, None, 25, 0, fake, None) == ko.KO_ERANGE
+    assert rounds(None, kp, 4, fake, 0, 4, fake, None) == ko.KO_EINVAL
+    assert rounds(ctypes.byref(g), kp, 4, None, 24, 0, None, None) == ko.KO_OK
     assert lib.ko_topk_f32(None, 10, 1, fake, None, None) == ko.KO_EINVAL
     assert lib.ko_topk_f32(fake, 10, 0, fake, None, None) == ko.KO_EINVAL
     assert lib.ko_topk_f32(fake, 10, 11, fake, None, None) == ko.KO_EINVAL

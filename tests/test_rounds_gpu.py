@@ -126,3 +126,23 @@ def test_rounds_in_paper_report():
         assert (r["best_cycles"], r["worst_cycles"], r["algorithm_cycles"]) == \
             (int(want.min()), int(want.max()), h), row["experiment"]
         assert r["percentile_inclusive"] == round(100.0 * float((want >= h).mean()), 2)
+
+
+def test_rounds_rank_mode():
+    # orders unranked on the device from lexicographic ranks: all 5040 orders of
+    # a 7-kernel set, and a window of ranks inside the n=10 set
+    model = synth.GTX580_MODEL
+    ks = synth.random_tiny_set(np.random.default_rng(88), 7, model, tblk_hi=200, inst_hi=900)
+    got = ko.ko_simulate_rounds(model.as_dict(), ks, None, count=5040).cpu().numpy()
+    orders = np.array([oracle.unrank(7, r) for r in range(5040)], dtype=np.int32)
+    want = oracle.rounds_makespans(model.as_dict(), ks, orders)
+    assert np.array_equal(got, want)
+    ks10 = synth.draw_set(1, 0)
+    first = 1_234_567
+    got = ko.ko_simulate_rounds(synth.MI355X_MODEL.as_dict(), ks10, None, first=first, count=5000).cpu().numpy()
+    orders = np.array([oracle.unrank(10, first + r) for r in range(5000)], dtype=np.int32)
+    want = oracle.rounds_makespans(synth.MI355X_MODEL.as_dict(), ks10, orders)
+    assert np.array_equal(got, want)
+    last = ko.ko_simulate_rounds(synth.MI355X_MODEL.as_dict(), ks10, None, first=3628799, count=1).cpu().numpy()
+    assert last.tolist() == oracle.rounds_makespans(synth.MI355X_MODEL.as_dict(), ks10,
+                                                    [list(range(9, -1, -1))]).tolist()
