@@ -17,7 +17,10 @@
 // CU min(cap, r-1) blocks plus one more to the first q - A(r-1) CUs of
 // {cap >= r} in pointer order, where A(r) = sum of min(cap, r) and r is the
 // first pass with A(r) >= q; the pointer ends just past the last of them.  A
-// kernel needs one bulk step per round it spans.  All control flow depends on
+// kernel needs one bulk step per round it spans.  The first step of a round
+// meets empty CUs with equal caps and has a closed form; a step that fills
+// every CU while blocks of its kernel remain closes the round without another
+// look at the CUs.  All control flow depends on
 // wave-uniform values only, so wave collectives always run with every lane;
 // sums and maxima over CUs are DPP reductions within the wave.
 #include <hip/hip_runtime.h>
@@ -140,74 +143,116 @@ __device__ int64_t rounds_order(const RoundsArgs &a, const KernelRec *tab, uint3
     int64_t t = 0;          // start of the open round
     uint32_t longest = 0;   // longest block placed in the open round
     uint32_t ptr = 0;
+    bool fresh = true;      // nothing placed since the last reset: every CU empty
     for (uint32_t pos = 0; pos < n; ++pos) {
         const uint32_t k = read_lane(mine, pos);
         if (k >= n)
             return -1;
         const KernelRec kr = tab[k];
         uint32_t rem = kr.tblk;
+        bool full = false;  // the last step gave every CU all the blocks it can take
         while (rem) {
-            uint32_t cap[S];
-            uint32_t tot = 0, cmax = 0;
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                uint32_t c = div_clamp(fr_reg[s], kr.u_reg, kr.inv_reg, fr_blk[s]);
-                c = div_clamp(fr_wave[s], kr.u_wave, kr.inv_wave, c);
-                if (kr.u_lds)
-                    c = div_clamp(fr_lds[s], kr.u_lds, kr.inv_lds, c);
-                cap[s] = c;
-                tot += c;
-                cmax = max(cmax, c);
-            }
-            tot = wave_sum(tot);
-            if (tot == 0) {
-                // the front block fits nowhere: the round ends with its longest block
-                if (longest == 0)
-                    return -1;   // a block that fits no empty CU (rejected by the host)
+            if (full) {
+                // blocks of this kernel remain and fit nowhere: the round ends
+                // with its longest block, and the next one starts empty
                 t += longest;
                 longest = 0;
                 reset();
+                fresh = true;
+                full = false;
                 continue;
             }
-            cmax = wave_umax(cmax);
-            const uint32_t q = min(tot, rem);
-            uint32_t r = cmax;
-            if (q < tot) {
-                uint32_t lo = 1, hi = cmax;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    uint32_t part = 0;
+            uint32_t tot, q, r, cut;
+            if (fresh) {
+                // every CU empty: the same cap c0 everywhere, so pass r is
+                // ceil(q / n_CU) and the cut lies q - n_CU (r-1) CUs past the
+                // pointer
+                uint32_t c0 = min(a.cap_blk, a.cap_reg / kr.u_reg);
+                c0 = min(c0, a.cap_wave / kr.u_wave);
+                if (kr.u_lds)
+                    c0 = min(c0, a.cap_lds / kr.u_lds);
+                if (c0 == 0)
+                    return -1;   // a block that fits no empty CU (rejected by the host)
+                tot = ncu * c0;
+                q = min(tot, rem);
+                r = (q + ncu - 1) / ncu;
+                const uint32_t end = ptr + (q - ncu * (r - 1)) - 1;
+                cut = end >= ncu ? end - ncu : end;
 #pragma unroll
-                    for (int s = 0; s < S; ++s)
-                        part += min(cap[s], mid);
-                    if (wave_sum(part) >= q)
-                        hi = mid;
-                    else
-                        lo = mid + 1;
+                for (int s = 0; s < S; ++s) {
+                    const uint32_t c = lane + 64u * (uint32_t)s;
+                    const bool in = ptr <= cut ? (c >= ptr && c <= cut) : (c >= ptr || c <= cut);
+                    const uint32_t cnt = c < ncu ? (r - 1) + (in ? 1u : 0u) : 0u;
+                    fr_reg[s] -= cnt * kr.u_reg;
+                    fr_lds[s] -= cnt * kr.u_lds;
+                    fr_wave[s] -= cnt * kr.u_wave;
+                    fr_blk[s] -= cnt;
                 }
-                r = lo;
-            }
-            uint32_t below = 0;
-            uint64_t mem[S];
+                fresh = false;
+            } else {
+                uint32_t cap[S];
+                uint32_t cmax = 0;
+                tot = 0;
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                below += min(cap[s], r - 1);
-                mem[s] = ballot(cap[s] >= r);
-            }
-            below = wave_sum(below);
-            const uint32_t cut = uniform(cyclic_nth<S>(mem, ptr, q - below));
+                for (int s = 0; s < S; ++s) {
+                    uint32_t c = div_clamp(fr_reg[s], kr.u_reg, kr.inv_reg, fr_blk[s]);
+                    c = div_clamp(fr_wave[s], kr.u_wave, kr.inv_wave, c);
+                    if (kr.u_lds)
+                        c = div_clamp(fr_lds[s], kr.u_lds, kr.inv_lds, c);
+                    cap[s] = c;
+                    tot += c;
+                    cmax = max(cmax, c);
+                }
+                tot = wave_sum(tot);
+                if (tot == 0) {
+                    // the front block fits nowhere: the round ends with its longest block
+                    t += longest;
+                    longest = 0;
+                    reset();
+                    fresh = true;
+                    continue;
+                }
+                cmax = wave_umax(cmax);
+                q = min(tot, rem);
+                r = cmax;
+                if (q < tot) {
+                    uint32_t lo = 1, hi = cmax;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        uint32_t part = 0;
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const uint32_t c = lane + 64u * (uint32_t)s;
-                const bool in = ptr <= cut ? (c >= ptr && c <= cut) : (c >= ptr || c <= cut);
-                const uint32_t cnt = min(cap[s], r - 1) + ((cap[s] >= r && in) ? 1u : 0u);
-                fr_reg[s] -= cnt * kr.u_reg;
-                fr_lds[s] -= cnt * kr.u_lds;
-                fr_wave[s] -= cnt * kr.u_wave;
-                fr_blk[s] -= cnt;
+                        for (int s = 0; s < S; ++s)
+                            part += min(cap[s], mid);
+                        if (wave_sum(part) >= q)
+                            hi = mid;
+                        else
+                            lo = mid + 1;
+                    }
+                    r = lo;
+                }
+                uint32_t below = 0;
+                uint64_t mem[S];
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    below += min(cap[s], r - 1);
+                    mem[s] = ballot(cap[s] >= r);
+                }
+                below = wave_sum(below);
+                cut = uniform(cyclic_nth<S>(mem, ptr, q - below));
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const uint32_t c = lane + 64u * (uint32_t)s;
+                    const bool in = ptr <= cut ? (c >= ptr && c <= cut) : (c >= ptr || c <= cut);
+                    const uint32_t cnt = min(cap[s], r - 1) + ((cap[s] >= r && in) ? 1u : 0u);
+                    fr_reg[s] -= cnt * kr.u_reg;
+                    fr_lds[s] -= cnt * kr.u_lds;
+                    fr_wave[s] -= cnt * kr.u_wave;
+                    fr_blk[s] -= cnt;
+                }
             }
             ptr = cut + 1 == ncu ? 0u : cut + 1;
             longest = max(longest, kr.dur);
+            full = q == tot && rem > q;
             rem -= q;
         }
     }
