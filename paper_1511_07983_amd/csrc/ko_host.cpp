@@ -1422,8 +1422,15 @@ int ko_simulate_rounds(const ko_gpu_model *gpu, const ko_kernel *kernels, int32_
         if (count == 0)
             return KO_OK;
         ko::RoundsArgs a{};
-        for (int32_t i = 0; i < n; i++)
+        for (int32_t i = 0; i < n; i++) {
             a.k[i] = recs[i];
+            int64_t c0 = std::min<int64_t>(gpu->blk_cu, gpu->reg_cu / recs[i].u_reg);
+            c0 = std::min<int64_t>(c0, gpu->wave_cu / recs[i].u_wave);
+            if (recs[i].u_lds)
+                c0 = std::min<int64_t>(c0, gpu->lds_cu / recs[i].u_lds);
+            a.c0[i] = (uint32_t)c0;
+        }
+        a.inv_ncu = inv_up(gpu->n_cu);
         a.orders = orders_dev;
         a.makespans = makespans_dev;
         a.first = first;

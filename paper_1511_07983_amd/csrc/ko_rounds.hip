@@ -126,7 +126,8 @@ __device__ uint32_t cyclic_nth(const uint64_t (&mem)[S], uint32_t ptr, uint32_t 
 }
 
 template <int S>
-__device__ int64_t rounds_order(const RoundsArgs &a, const KernelRec *tab, uint32_t mine, uint32_t lane)
+__device__ int64_t rounds_order(const RoundsArgs &a, const KernelRec *tab, const uint32_t *c0s, uint32_t mine,
+                                uint32_t lane)
 {
     const uint32_t n = a.n, ncu = a.n_cu;
     uint32_t fr_reg[S], fr_lds[S], fr_wave[S], fr_blk[S];
@@ -167,15 +168,12 @@ __device__ int64_t rounds_order(const RoundsArgs &a, const KernelRec *tab, uint3
                 // every CU empty: the same cap c0 everywhere, so pass r is
                 // ceil(q / n_CU) and the cut lies q - n_CU (r-1) CUs past the
                 // pointer
-                uint32_t c0 = min(a.cap_blk, a.cap_reg / kr.u_reg);
-                c0 = min(c0, a.cap_wave / kr.u_wave);
-                if (kr.u_lds)
-                    c0 = min(c0, a.cap_lds / kr.u_lds);
+                const uint32_t c0 = c0s[k];
                 if (c0 == 0)
                     return -1;   // a block that fits no empty CU (rejected by the host)
                 tot = ncu * c0;
                 q = min(tot, rem);
-                r = (q + ncu - 1) / ncu;
+                r = div_clamp(q + ncu - 1, ncu, a.inv_ncu, c0);   // ceil(q / n_CU) <= c0
                 const uint32_t end = ptr + (q - ncu * (r - 1)) - 1;
                 cut = end >= ncu ? end - ncu : end;
 #pragma unroll
@@ -263,11 +261,14 @@ template <int S>
 __global__ __launch_bounds__(64 * kRoundsWaves) void rounds_kernel(RoundsArgs a)
 {
     __shared__ KernelRec tab[kMaxSet];
+    __shared__ uint32_t c0s[kMaxSet];
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int i = 0; i < kMaxSet; ++i)
-            if (i < (int)a.n)
+            if (i < (int)a.n) {
                 tab[i] = a.k[i];
+                c0s[i] = a.c0[i];
+            }
     }
     __syncthreads();
     const uint32_t lane = lane_id();
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(64 * kRoundsWaves) void rounds_kernel(RoundsArgs a)
     for (uint64_t i = first; i < a.count; i += stride) {
         const uint32_t mine = a.orders ? (lane < a.n ? (uint32_t)a.orders[i * a.n + lane] : 0u)
                                        : unrank_lanes(a.first + i, a.n);
-        const int64_t m = rounds_order<S>(a, tab, mine, lane);
+        const int64_t m = rounds_order<S>(a, tab, c0s, mine, lane);
         // every lane stores the same value: no lane-dependent branch in the loop
         a.makespans[i] = m;
     }
