@@ -16,7 +16,8 @@
 // on every CU with cap >= 2, and so on.  Placing q blocks therefore gives each
 // CU min(cap, r-1) blocks plus one more to the first q - A(r-1) CUs of
 // {cap >= r} in pointer order, where A(r) = sum of min(cap, r) and r is the
-// first pass with A(r) >= q; the pointer ends just past the last of them.  A
+// first pass with A(r) >= q (found pass by pass from ballot popcounts); the
+// pointer ends just past the last of them.  A
 // kernel needs one bulk step per round it spans.  The first step of a round
 // meets empty CUs with equal caps and has a closed form; a step that fills
 // every CU while blocks of its kernel remain closes the round without another
@@ -210,42 +211,56 @@ __device__ int64_t rounds_order(const RoundsArgs &a, const KernelRec *tab, const
                     fresh = true;
                     continue;
                 }
-                cmax = wave_umax(cmax);
                 q = min(tot, rem);
-                r = cmax;
-                if (q < tot) {
-                    uint32_t lo = 1, hi = cmax;
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        uint32_t part = 0;
-#pragma unroll
-                        for (int s = 0; s < S; ++s)
-                            part += min(cap[s], mid);
-                        if (wave_sum(part) >= q)
-                            hi = mid;
-                        else
-                            lo = mid + 1;
-                    }
-                    r = lo;
-                }
-                uint32_t below = 0;
                 uint64_t mem[S];
+                if (q == tot) {
+                    // every block that fits is placed: each CU gets its cap, and
+                    // the last block lands on the last CU of the final pass
+                    // (cap == max cap) in pointer order
+                    const uint32_t cm = wave_umax(cmax);
+                    uint32_t members = 0;
 #pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    below += min(cap[s], r - 1);
-                    mem[s] = ballot(cap[s] >= r);
-                }
-                below = wave_sum(below);
-                cut = uniform(cyclic_nth<S>(mem, ptr, q - below));
+                    for (int s = 0; s < S; ++s) {
+                        mem[s] = ballot(cap[s] >= cm);
+                        members += (uint32_t)__popcll(mem[s]);
+                    }
+                    cut = uniform(cyclic_nth<S>(mem, ptr, members));
 #pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    const uint32_t c = lane + 64u * (uint32_t)s;
-                    const bool in = ptr <= cut ? (c >= ptr && c <= cut) : (c >= ptr || c <= cut);
-                    const uint32_t cnt = min(cap[s], r - 1) + ((cap[s] >= r && in) ? 1u : 0u);
-                    fr_reg[s] -= cnt * kr.u_reg;
-                    fr_lds[s] -= cnt * kr.u_lds;
-                    fr_wave[s] -= cnt * kr.u_wave;
-                    fr_blk[s] -= cnt;
+                    for (int s = 0; s < S; ++s) {
+                        fr_reg[s] -= cap[s] * kr.u_reg;
+                        fr_lds[s] -= cap[s] * kr.u_lds;
+                        fr_wave[s] -= cap[s] * kr.u_wave;
+                        fr_blk[s] -= cap[s];
+                    }
+                } else {
+                    // passes one by one: pass r adds |{cap >= r}| blocks (ballot
+                    // popcounts); it ends at the first r with A(r) >= q, which
+                    // comes no later than the max cap because A(max cap) = tot > q
+                    uint32_t below = 0;
+                    r = 0;
+                    for (;;) {
+                        ++r;
+                        uint32_t m = 0;
+#pragma unroll
+                        for (int s = 0; s < S; ++s) {
+                            mem[s] = ballot(cap[s] >= r);
+                            m += (uint32_t)__popcll(mem[s]);
+                        }
+                        if (below + m >= q)
+                            break;
+                        below += m;
+                    }
+                    cut = uniform(cyclic_nth<S>(mem, ptr, q - below));
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        const uint32_t c = lane + 64u * (uint32_t)s;
+                        const bool in = ptr <= cut ? (c >= ptr && c <= cut) : (c >= ptr || c <= cut);
+                        const uint32_t cnt = min(cap[s], r - 1) + ((cap[s] >= r && in) ? 1u : 0u);
+                        fr_reg[s] -= cnt * kr.u_reg;
+                        fr_lds[s] -= cnt * kr.u_lds;
+                        fr_wave[s] -= cnt * kr.u_wave;
+                        fr_blk[s] -= cnt;
+                    }
                 }
             }
             ptr = cut + 1 == ncu ? 0u : cut + 1;
