@@ -17,13 +17,12 @@
 // CU min(cap, r-1) blocks plus one more to the first q - A(r-1) CUs of
 // {cap >= r} in pointer order, where A(r) = sum of min(cap, r) and r is the
 // first pass with A(r) >= q (found pass by pass from ballot popcounts); the
-// pointer ends just past the last of them.  A
-// kernel needs one bulk step per round it spans.  The first step of a round
-// meets empty CUs with equal caps and has a closed form; a step that fills
-// every CU while blocks of its kernel remain closes the round without another
-// look at the CUs.  All control flow depends on
-// wave-uniform values only, so wave collectives always run with every lane;
-// sums and maxima over CUs are DPP reductions within the wave.
+// pointer ends just past the last of them.  A kernel needs one bulk step per
+// round it spans.  The first step of a round meets empty CUs with equal caps
+// and has a closed form; a step that fills every CU while blocks of its kernel
+// remain closes the round without another look at the CUs.  All control flow
+// depends on wave-uniform values only, so wave collectives always run with
+// every lane; sums and maxima over CUs are DPP reductions within the wave.
 #include <hip/hip_runtime.h>
 
 #include "ko_device.h"
