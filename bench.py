@@ -122,6 +122,23 @@ def surrogate_leg(heldout: int) -> dict:
             "score_rerank_s_per_set": round(float(sum(r["score_rerank_s"] for r in rows) / max(1, len(rows))), 3)}
 
 
+def rounds_leg(ops_per_order: int):
+    """The round-synchronous reading of the execution rounds on the same set, all
+    orders unranked on the device (not in `value`): HIP-event time per launch,
+    the same ALU fraction, and Algorithm 1's exact percentile under that model."""
+    from paper_1511_07983_amd import rounds
+    try:
+        rec = rounds.report(reps=5, all_orders=True, out=lambda text: None)
+    except Exception as exc:  # keep the throughput line even if this leg fails
+        return {"error": f"{type(exc).__name__}: {exc}"}
+    print("[bench] rounds done", file=sys.stderr, flush=True)
+    achieved = ops_per_order * rec["orders"] / (rec["ms_per_launch"] / 1e3) / 1e12
+    return {"kernel": "ko::rounds_kernel<4>", "orders": rec["orders"], "ms_per_launch": rec["ms_per_launch"],
+            "orders_per_s": rec["orders_per_s"], "achieved": achieved, "frac": achieved / ALU_PEAK_TOPS,
+            "heuristic_pct_inclusive": rec["heuristic_percentile"],
+            "min_makespan": rec["best"], "max_makespan": rec["worst"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -232,6 +249,7 @@ def main():
         "heuristic": {"order": ko.ko_heuristic_order(w.model, kernels), "pct_inclusive": pct,
                       "min_makespan": int(rec["min_makespan"]), "max_makespan": int(rec["max_makespan"])},
     }
+    out["rounds"] = rounds_leg(ops_per_order)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(args.surrogate_heldout)
     if args.cpu_seconds > 0:
