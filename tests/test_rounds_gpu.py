@@ -146,3 +146,22 @@ def test_rounds_rank_mode():
     last = ko.ko_simulate_rounds(synth.MI355X_MODEL.as_dict(), ks10, None, first=3628799, count=1).cpu().numpy()
     assert last.tolist() == oracle.rounds_makespans(synth.MI355X_MODEL.as_dict(), ks10,
                                                     [list(range(9, -1, -1))]).tolist()
+
+
+def test_rounds_large_grids_and_long_blocks():
+    # many rounds per kernel, and makespans far above 2^32 cycles (int64
+    # accumulation), near the host's limit on total block time
+    model = synth.MI355X_MODEL
+    ks = np.zeros(3, dtype=synth.KERNEL_DTYPE)
+    ks["n_tblk"] = [20000, 7000, 13001]
+    ks["n_inst"] = [1 << 30, 3 << 28, 123456789]
+    ks["lds_blk"] = [0, 40000, 1000]
+    ks["waves_blk"] = [16, 4, 1]
+    ks["regs_thr"] = [32, 128, 8]
+    ks["r_milli"] = [model.rb_milli, 2 * model.rb_milli, model.rb_milli // 3]
+    orders = np.array(list(itertools.permutations(range(3))), dtype=np.int32)
+    want = oracle.rounds_makespans(model.as_dict(), ks, orders)
+    assert want.max() > (1 << 32)
+    _check(model.as_dict(), ks, orders, "large")
+    got = ko.ko_simulate_rounds(model.as_dict(), ks, None, count=6).cpu().numpy()
+    assert np.array_equal(got, want)
