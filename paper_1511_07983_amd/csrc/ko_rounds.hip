@@ -34,6 +34,7 @@ namespace {
 
 constexpr int kRoundsWaves = 4;          // wavefronts per workgroup
 constexpr uint32_t kRoundsGridCap = 4096;
+constexpr uint64_t kRankRun = 16;        // consecutive ranks per wavefront in rank mode
 
 // Lane-shifted copy of v through DPP: lanes whose source lies outside their
 // row of 16 read 0, lanes in rows left out of RowMask read 0.
@@ -288,12 +289,27 @@ __global__ __launch_bounds__(64 * kRoundsWaves) void rounds_kernel(RoundsArgs a)
     const uint32_t lane = lane_id();
     const uint64_t first = (uint64_t)blockIdx.x * kRoundsWaves + uniform(threadIdx.x >> 6);
     const uint64_t stride = (uint64_t)gridDim.x * kRoundsWaves;
-    for (uint64_t i = first; i < a.count; i += stride) {
-        const uint32_t mine = a.orders ? (lane < a.n ? (uint32_t)a.orders[i * a.n + lane] : 0u)
-                                       : unrank_lanes(a.first + i, a.n);
-        const int64_t m = rounds_order<S>(a, tab, c0s, mine, lane);
-        // every lane stores the same value: no lane-dependent branch in the loop
-        a.makespans[i] = m;
+    // every lane stores the same makespan: no lane-dependent branch in the loops
+    if (a.orders) {
+        for (uint64_t i = first; i < a.count; i += stride) {
+            const uint32_t mine = lane < a.n ? (uint32_t)a.orders[i * a.n + lane] : 0u;
+            a.makespans[i] = rounds_order<S>(a, tab, c0s, mine, lane);
+        }
+    } else {
+        // runs of kRankRun consecutive ranks per wavefront: one unranking, then
+        // next-permutation steps (never past the run's last rank, which is < n!)
+        const uint64_t runs = (a.count + kRankRun - 1) / kRankRun;
+        for (uint64_t g = first; g < runs; g += stride) {
+            const uint64_t base = g * kRankRun;
+            const uint64_t end = min(base + kRankRun, a.count);
+            uint32_t perm = unrank_lanes(a.first + base, a.n);
+            for (uint64_t i = base;;) {
+                a.makespans[i] = rounds_order<S>(a, tab, c0s, perm, lane);
+                if (++i == end)
+                    break;
+                perm = next_perm_lanes(perm, a.n);
+            }
+        }
     }
 }
 
