@@ -165,3 +165,13 @@ def test_rounds_large_grids_and_long_blocks():
     _check(model.as_dict(), ks, orders, "large")
     got = ko.ko_simulate_rounds(model.as_dict(), ks, None, count=6).cpu().numpy()
     assert np.array_equal(got, want)
+
+
+def test_rounds_one_block_per_cu():
+    # every block takes a whole CU: rounds are windows of n_CU blocks
+    model = synth.GpuModel(n_cu=70, wave_size=64, wave_cu=32, blk_cu=1,
+                           reg_cu=131072, lds_cu=163840, rb_milli=10000)
+    rng = np.random.default_rng(71)
+    ks = synth.random_tiny_set(rng, 6, model, tblk_hi=150, inst_hi=4000)
+    orders = np.array(list(itertools.permutations(range(6))), dtype=np.int32)
+    _check(model.as_dict(), ks, orders, "blk_cu=1")

@@ -101,3 +101,20 @@ def test_rounds_rejects_bad_orders():
     ks = synth.random_tiny_set(np.random.default_rng(1), 3, synth.SMALL_MODEL)
     with pytest.raises(ValueError):
         oracle.rounds_makespans(synth.SMALL_MODEL.as_dict(), ks, [[0, 0, 1]])
+
+
+def test_rounds_one_block_per_cu_equal_durations_order_free():
+    # Section 3: when every block takes a whole CU the order does not matter;
+    # in this model that holds for equal block durations: every round but the
+    # last is full, so the makespan is ceil(blocks / CUs) block durations
+    model = synth.GpuModel(n_cu=4, wave_size=32, wave_cu=64, blk_cu=1,
+                           reg_cu=65536, lds_cu=65536, rb_milli=8000)
+    rng = np.random.default_rng(13)
+    for _ in range(8):
+        n = int(rng.integers(2, 6))
+        ks = synth.random_tiny_set(rng, n, model, tblk_hi=9, equal_d=True)
+        _, dur = oracle.derive(model.as_dict(), ks)
+        assert len(set(dur.tolist())) == 1
+        got = oracle.rounds_makespans(model.as_dict(), ks, _orders(n))
+        want = math.ceil(int(ks["n_tblk"].sum()) / model.n_cu) * int(dur[0])
+        assert set(got.tolist()) == {want}
