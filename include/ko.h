@@ -121,7 +121,9 @@ typedef struct ko_rank_result {
 /* Which orders of each set to evaluate.
  * SAMPLED: sample i of set s has rank floor(x * n! / 2^64) where x is output
  * number (s << 40) | i of SplitMix64 (Steele, Lea & Flood 2014) seeded with
- * `seed`, i.e. the SplitMix64 mix of seed + (c + 1) * 0x9E3779B97F4A7C15. */
+ * `seed`, i.e. the SplitMix64 mix of seed + (c + 1) * 0x9E3779B97F4A7C15.
+ * So a SAMPLED spec takes at most 2^40 samples per set and 2^24 sets
+ * (KO_ERANGE otherwise): past those, counters would repeat other streams. */
 typedef struct ko_order_spec {
     int32_t mode;                  /* KO_ORDERS_* */
     int32_t reserved;              /* must be 0 */
@@ -160,7 +162,8 @@ int ko_heuristic_order(const ko_gpu_model *gpu, const ko_kernel *k, int32_t n, u
  *   per_set_out  host uint64[n_sets] or NULL
  *   total_out    host uint64[1]: the sum (the length of the makespan output)
  * Errors: KO_EINVAL (bad offsets, set size outside 1..20, bad spec), KO_ERANGE
- * (n! or the total does not fit in uint64).
+ * (n! or the total does not fit in uint64; SAMPLED past 2^40 samples per set
+ * or 2^24 sets).
  */
 int ko_count_orders(const int32_t *set_offsets, int32_t n_sets, const ko_order_spec *spec,
                     uint64_t *per_set_out, uint64_t *total_out);
@@ -310,8 +313,8 @@ int ko_graph_destroy(ko_graph *graph);
  *   gpu, kernels, n  host model and set (1 <= n <= 20), validated and derived
  *                    as in ko_simulate_batch
  *   orders_dev       uint8 [count][n], device: order[j] = kernel at position j;
- *                    each row must be a permutation of 0..n-1 (repeats are not
- *                    detected; a row with an entry >= n gets makespan -1).
+ *                    each row must be a permutation of 0..n-1; a row with an
+ *                    entry >= n or a repeated entry gets makespan -1.
  *                    NULL: the orders of lexicographic ranks first ..
  *                    first+count-1 among all n! orders, unranked on the device
  *   first            first rank when orders_dev is NULL, else 0

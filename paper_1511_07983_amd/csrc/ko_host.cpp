@@ -50,6 +50,8 @@ int hip_fail(hipError_t e, const char *what)
 constexpr int64_t kCapLimit = (int64_t(1) << 24) - 1;  // resources must stay exact in float
 constexpr int64_t kDurLimit = (int64_t(1) << 31) - 1;
 constexpr int64_t kSerialLimit = int64_t(1) << 46;
+constexpr uint64_t kSampleLimit = uint64_t(1) << 40;     // samples per set in SAMPLED mode
+constexpr uint64_t kSampleSetLimit = uint64_t(1) << 24;  // sets in SAMPLED mode
 
 // ---------------------------------------------------------------- validation
 
@@ -174,6 +176,8 @@ int count_orders(const int32_t *off, int32_t n_sets, const ko_order_spec *spec,
     if ((spec->mode == KO_ORDERS_EXPLICIT || spec->mode == KO_ORDERS_SAMPLED) &&
         !spec->orders_per_set)
         return fail(KO_EINVAL, "spec: EXPLICIT and SAMPLED need orders_per_set");
+    if (spec->mode == KO_ORDERS_SAMPLED && (uint64_t)n_sets > kSampleSetLimit)
+        return fail(KO_ERANGE, "spec: SAMPLED takes at most 2^24 sets (got %d)", n_sets);
     per_set->assign(n_sets, 0);
     unsigned __int128 sum = 0;
     for (int32_t s = 0; s < n_sets; s++) {
@@ -198,6 +202,11 @@ int count_orders(const int32_t *off, int32_t n_sets, const ko_order_spec *spec,
             if (spec->orders_per_set[s] < 0)
                 return fail(KO_EINVAL, "set %d: negative order count", s);
             c = (uint64_t)spec->orders_per_set[s];
+            // a sample's counter is set * 2^40 + index: indices at or past 2^40
+            // would repeat another set's stream, sets past 2^24 overflow it
+            if (spec->mode == KO_ORDERS_SAMPLED && c > kSampleLimit)
+                return fail(KO_ERANGE, "set %d: %llu samples (at most 2^40 per set)", s,
+                            (unsigned long long)c);
         }
         (*per_set)[s] = c;
         sum += c;

@@ -146,10 +146,12 @@ __device__ int64_t rounds_order(const RoundsArgs &a, const KernelRec *tab, const
     uint32_t longest = 0;   // longest block placed in the open round
     uint32_t ptr = 0;
     bool fresh = true;      // nothing placed since the last reset: every CU empty
+    uint32_t seen = 0;      // kernels met so far (a row must be a permutation)
     for (uint32_t pos = 0; pos < n; ++pos) {
         const uint32_t k = read_lane(mine, pos);
-        if (k >= n)
+        if (k >= n || ((seen >> k) & 1u))
             return -1;
+        seen |= 1u << k;
         const KernelRec kr = tab[k];
         uint32_t rem = kr.tblk;
         bool full = false;  // the last step gave every CU all the blocks it can take

@@ -91,6 +91,24 @@ def test_count_orders():
     assert e.value.code == ko.KO_EINVAL
 
 
+def test_count_orders_sampled_counter_limits():
+    """A sample's counter is set * 2^40 + index: at most 2^40 samples per set
+    and 2^24 sets, else the streams of two samples would coincide."""
+    per, total = ko.ko_count_orders([0, 3], ko.OrderSpec.sampled([1 << 40], seed=1))
+    assert total == 1 << 40
+    with pytest.raises(ko.KoError) as e:
+        ko.ko_count_orders([0, 3], ko.OrderSpec.sampled([(1 << 40) + 1], seed=1))
+    assert e.value.code == ko.KO_ERANGE
+    n_sets = (1 << 24) + 1
+    off = np.arange(n_sets + 1, dtype=np.int32)
+    with pytest.raises(ko.KoError) as e:
+        ko.ko_count_orders(off, ko.OrderSpec.sampled(np.ones(n_sets, dtype=np.int64), seed=1))
+    assert e.value.code == ko.KO_ERANGE
+    # the same batch of all orders is not limited by the counter
+    per, total = ko.ko_count_orders(off, ko.OrderSpec.all())
+    assert total == n_sets
+
+
 def _call_simulate(gpu, ks, off, spec, n_bins=0, want_hist=False, want_stats=False):
     """Invoke the raw ABI with dummy non-null device pointers where a buffer is
     'given': every case here must be rejected before any device access."""

@@ -86,3 +86,37 @@ def test_flatten_roundtrip():
     assert v.size == mlp.n_params()
     q = mlp.unflatten(v)
     assert all(np.array_equal(p[k], q[k]) for k in p)
+
+
+def _hand_params(spec):
+    p = {name: np.zeros(shape) for name, shape in mlp.SHAPES}
+    for name, entries in spec.items():
+        for e in entries:
+            p[name][tuple(int(i) for i in e[:-1])] = e[-1]
+    return p
+
+
+def _hand_tokens(positions):
+    X = np.zeros((1, 2, mlp.D_IN))
+    X[0, 0, 0], X[0, 1, 0] = 1.0, 2.0
+    for tok, pos in enumerate(positions):
+        X[0, tok, mlp.N_FEAT + pos] = 1.0
+    return X
+
+
+@pytest.mark.parametrize("bf16_points", [True, False])
+def test_forward_and_backward_hand_worked(golden, bf16_points):
+    """Forward outputs of two launch orders and every gradient element of one,
+    worked by hand (tests/golden/mlp_hand.json)."""
+    g = golden("mlp_hand.json")
+    params = _hand_params(g["params"])
+    for case in g["cases"]:
+        y, _ = mlp.forward(params, _hand_tokens(case["positions"]), bf16_points)
+        assert y[0] == case["y"]
+    case = g["cases"][0]
+    loss, y, grads = mlp.loss_and_grads(params, _hand_tokens(case["positions"]), [case["target"]],
+                                        bf16_points)
+    assert loss == case["loss"] and y[0] == case["y"]
+    for name, shape in mlp.SHAPES:
+        want = _hand_params({name: case["grads"].get(name, [])})[name]
+        assert np.array_equal(grads[name].reshape(shape), want), name

@@ -265,3 +265,40 @@ def test_histogram_bins():
     h = ostats.histogram(ms, 4, 10, 20)
     # width 11: bins floor(0*4/11)=0, 0, floor(4/11)=0, floor(12/11)=1, floor(40/11)=3
     assert h.tolist() == [3, 1, 0, 1]
+
+
+# ---------------------------------------------------------------- surrogate inputs
+
+def test_lower_bound_hand_worked(golden):
+    """The area lower bound on E1 (the longest block decides) and on E2 (the
+    LDS area decides), worked by hand in tests/golden/features_lb.json."""
+    from oracle import features as ofeat
+    g = golden("features_lb.json")
+    e1, e2 = golden("e1_two_cu.json"), golden("e2_heuristic.json")
+    assert ofeat.lower_bound(e1["gpu"], e1["kernels"]) == g["e1"]["lower_bound"] == e1["lower_bound"]
+    assert ofeat.lower_bound(e2["gpu"], e2["kernels"]) == g["e2"]["lower_bound"]
+    # the bound is a bound: every order of E1 and E2 ends no earlier
+    assert min(all_makespans(e1["gpu"], e1["kernels"])) >= g["e1"]["lower_bound"]
+    assert min(all_makespans(e2["gpu"], e2["kernels"])) >= g["e2"]["lower_bound"]
+
+
+def test_features_hand_worked(golden):
+    """The 8 per-kernel features of E3's kernel and of E2's kernel 2 (whose
+    ratio lies below R_B), worked by hand."""
+    from oracle import features as ofeat
+    g = golden("features_lb.json")
+    e2, e3 = golden("e2_heuristic.json"), golden("e3_single_kernel.json")
+    got = ofeat.features(e3["gpu"], e3["kernels"])[0]
+    assert got == pytest.approx(g["e3_kernel"]["features"], rel=1e-12, abs=1e-15)
+    got = ofeat.features(e2["gpu"], e2["kernels"])[2]
+    assert got == pytest.approx(g["e2_k2"]["features"], rel=1e-12, abs=1e-15)
+
+
+def test_sampled_rank_from_published_outputs(golden):
+    """Ranks of the first two SplitMix64 outputs for seed 1234567 under the
+    multiply-shift range reduction, worked out in tests/golden/sampled_rank.json."""
+    g = golden("sampled_rank.json")
+    for s in g["samples"]:
+        assert splitmix64_at(g["seed"], s["index"]) == s["x"]
+        for n_orders, want in s["ranks"].items():
+            assert sampled_rank(g["seed"], g["set"], s["index"], int(n_orders)) == want

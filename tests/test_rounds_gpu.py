@@ -103,10 +103,15 @@ def test_rounds_paper_sets():
 def test_rounds_bad_index_and_empty():
     model = synth.SMALL_MODEL
     ks = synth.random_tiny_set(np.random.default_rng(4), 4, model)
-    orders = np.array([[0, 1, 2, 3], [0, 1, 9, 3], [3, 2, 1, 0]], dtype=np.uint8)
+    # rows 1, 3 and 4 are not permutations: an index past n, a repeated
+    # index at the end, a repeated index at the front
+    orders = np.array([[0, 1, 2, 3], [0, 1, 9, 3], [3, 2, 1, 0], [0, 1, 2, 2], [1, 1, 2, 3]],
+                      dtype=np.uint8)
     got = _gpu_rounds(model.as_dict(), ks, orders)
     want = oracle.rounds_makespans(model.as_dict(), ks, orders[[0, 2]].astype(np.int32))
-    assert got.tolist() == [int(want[0]), -1, int(want[1])]
+    assert got.tolist() == [int(want[0]), -1, int(want[1]), -1, -1]
+    with pytest.raises(ValueError):
+        oracle.rounds_makespans(model.as_dict(), ks, orders[[3]].astype(np.int32))
     empty = torch.empty((0, 4), dtype=torch.uint8, device="cuda")
     assert ko.ko_simulate_rounds(model.as_dict(), ks, empty).numel() == 0
 
