@@ -281,35 +281,105 @@ def test_explicit_non_permutation_reports_device_status():
 
 # ------------------------------------------------------------------ full size
 
-def test_full_size_n10_all_orders_properties():
+def oracle_threads():
+    """The oracle's worker threads: every host core, at most the 16 that one
+    GPU's share of a box holds."""
+    return min(16, oracle.default_threads())
+
+
+def test_full_size_n10_all_orders_against_oracle():
     """All 3,628,800 orders of the n=10 set in the configuration the benchmark
-    times: sampled entries against the oracle one by one, and properties that
-    hold at any size (counts add up, histogram sums to N, extremes agree with
-    the array and with the oracle at their ranks)."""
+    times, element by element against the oracle's full enumeration (Section
+    6's exhaustive evaluation); extremes, argmin/argmax ranks, the histogram
+    and Algorithm 1's rank counts all come from the oracle's array."""
     w = synth.WORKLOADS[1]
     gpu = w.model.as_dict()
     ks = synth.draw_set(1, 0)
     N = math.factorial(10)
     h_order = ko.ko_heuristic_order(w.model, ks)
+    assert h_order == oracle_heuristic(gpu, ks)[0]
     ref = oracle.makespan(gpu, ks, h_order)
-    say("n=10 all 3,628,800 orders")
+    say("n=10 all 3,628,800 orders: oracle")
+    want = oracle.makespans_all(gpu, ks, threads=oracle_threads())
+    say("n=10 all 3,628,800 orders: GPU")
     ms, st, hist, _ = run_batch(w.model, [ks], ko.OrderSpec.all(), ref=[ref], n_bins=1024)
+    assert len(ms) == N
+    bad = np.flatnonzero(ms != want)
+    assert bad.size == 0, f"{bad.size} makespans differ, first at rank {bad[:1]}"
+    o = ostats.set_stats(want, ref=ref)
     rec = st[0]
-    assert rec["n_orders"] == N and len(ms) == N
-    assert rec["min_makespan"] == ms.min() and rec["max_makespan"] == ms.max()
-    assert rec["argmin"] == int(np.argmin(ms)) and rec["argmax"] == int(np.argmax(ms))
-    assert rec["n_less"] == int((ms < ref).sum()) and rec["n_equal"] == int((ms == ref).sum())
-    assert rec["n_less"] + rec["n_equal"] + rec["n_greater"] == N
-    assert int(hist[0].sum()) == N
-    assert np.array_equal(hist[0], ostats.histogram(ms, 1024, ms.min(), ms.max()))
-    rng = np.random.default_rng(8)
-    idx = np.unique(np.concatenate([rng.integers(0, N, 400),
-                                    np.array([0, N - 1, int(rec["argmin"]), int(rec["argmax"])], dtype=np.int64)]))
-    want = oracle.makespans_ranks(gpu, ks, idx.astype(np.uint64))
-    assert np.array_equal(ms[idx], want)
+    assert rec["n_orders"] == N
+    assert (rec["min_makespan"], rec["max_makespan"]) == (o["min"], o["max"])
+    assert (rec["argmin"], rec["argmax"]) == (o["argmin"], o["argmax"])
+    assert (rec["n_less"], rec["n_equal"], rec["n_greater"]) == (o["n_less"], o["n_equal"], o["n_greater"])
+    assert np.array_equal(hist[0], ostats.histogram(want, 1024, o["min"], o["max"]))
     r = ko.ko_rank_percentile(w.model, ks, h_order)
     assert r["makespan"] == ref
-    assert (r["n_less"], r["n_equal"], r["n_greater"]) == (rec["n_less"], rec["n_equal"], rec["n_greater"])
+    assert (r["n_less"], r["n_equal"], r["n_greater"]) == (o["n_less"], o["n_equal"], o["n_greater"])
+
+
+def test_batch_sets_n7_to_n9_full_enumeration_against_oracle():
+    """A stratified subset of the 4096-set batch: the first six sets of each
+    size n = 7, 8 and 9 in one call, every order of each set element by
+    element against the oracle, with Algorithm 1's order as each set's
+    reference (Table 3's percentile) and per-set statistics from the oracle."""
+    w = synth.WORKLOADS[2]
+    gpu = w.model.as_dict()
+    picked = {7: [], 8: [], 9: []}
+    s = 0
+    while any(len(v) < 6 for v in picked.values()):
+        ks = synth.draw_set(2, s)
+        if len(ks) in picked and len(picked[len(ks)]) < 6:
+            picked[len(ks)].append((s, ks))
+        s += 1
+    sets = [ks for n in (7, 8, 9) for _, ks in picked[n]]
+    say("batch sets", [i for n in (7, 8, 9) for i, _ in picked[n]], "n = 7, 8, 9: oracle")
+    refs, wants = [], []
+    for ks in sets:
+        refs.append(oracle.makespan(gpu, ks, oracle_heuristic(gpu, ks)[0]))
+        wants.append(oracle.makespans_all(gpu, ks, threads=oracle_threads()))
+    say("batch sets n = 7, 8, 9: GPU")
+    ms, st, hist, per = run_batch(w.model, sets, ko.OrderSpec.all(), ref=refs, n_bins=256)
+    off = 0
+    for i, (ks, want, ref) in enumerate(zip(sets, wants, refs)):
+        got = ms[off:off + len(want)]
+        off += len(want)
+        assert per[i] == len(want) == math.factorial(len(ks))
+        assert np.array_equal(got, want), f"set {i} (n={len(ks)})"
+        o = ostats.set_stats(want, ref=ref)
+        rec = st[i]
+        assert (rec["min_makespan"], rec["max_makespan"], rec["argmin"], rec["argmax"]) == \
+            (o["min"], o["max"], o["argmin"], o["argmax"])
+        assert (rec["n_less"], rec["n_equal"], rec["n_greater"]) == (o["n_less"], o["n_equal"], o["n_greater"])
+        assert np.array_equal(hist[i], ostats.histogram(want, 256, o["min"], o["max"]))
+    assert off == len(ms)
+
+
+@pytest.mark.parametrize("workload,n_samples", [(13, 65536), (4, 16384)])
+def test_rank_percentile_sampled_against_oracle(workload, n_samples):
+    """Percentile of Algorithm 1's order over sampled orders (Section 6's
+    random order choice), the only percentile there is for n = 16: the counts
+    equal the oracle's over the same counter-based sample ranks."""
+    w = synth.WORKLOADS[workload]
+    gpu = w.model.as_dict()
+    ks = synth.draw_set(workload, 0)
+    n = len(ks)
+    seed = 0x5EED0000 + n
+    order = oracle_heuristic(gpu, ks)[0]
+    ref = oracle.makespan(gpu, ks, order)
+    ranks = np.array([sampled_rank(seed, 0, i, math.factorial(n)) for i in range(n_samples)],
+                     dtype=np.uint64)
+    say(f"sampled percentile n={n}, {n_samples} samples: oracle")
+    want = oracle.makespans_ranks(gpu, ks, ranks, threads=oracle_threads())
+    say(f"sampled percentile n={n}: GPU")
+    r = ko.ko_rank_percentile(w.model, ks, order, n_samples=n_samples, seed=seed)
+    assert r["makespan"] == ref
+    assert r["n_total"] == n_samples
+    assert (r["min_makespan"], r["max_makespan"]) == (int(want.min()), int(want.max()))
+    assert (r["n_less"], r["n_equal"], r["n_greater"]) == \
+        (int((want < ref).sum()), int((want == ref).sum()), int((want > ref).sum()))
+    o = ostats.percentiles(int((want < ref).sum()), int((want == ref).sum()), int((want > ref).sum()))
+    assert r["pct_inclusive"] == pytest.approx(o["inclusive"], abs=1e-9)
 
 
 # ------------------------------------------------------------------ degenerate cases
