@@ -11,8 +11,9 @@ Parts:
   * ``ko_oracle.c``  discrete-event dispatch model, one block at a time
                       (Section 2 and Table 1), lexicographic unranking, many
                       orders over threads, and the round-synchronous reading
-                      of Section 2's execution rounds.  Loaded here through
-                      ctypes.
+                      of Section 2's execution rounds, and a third model in
+                      which resident blocks share the chip's memory
+                      throughput (Section 4).  Loaded here through ctypes.
   * ``heuristic``    Algorithm 1 (ScoreGen, ProfileCombine, execution rounds)
                       in binary64 Python floats.
   * ``tick``         a second formulation of the dispatch model that advances
@@ -78,6 +79,9 @@ def lib():
         L.oc_makespans_orders.restype = ctypes.c_int
         L.oc_rounds_makespans.argtypes = [i64p, ctypes.c_int32, i64p, i32p, ctypes.c_int64, i64p]
         L.oc_rounds_makespans.restype = ctypes.c_int
+        L.oc_contended_makespans.argtypes = [i64p, ctypes.c_int64, ctypes.c_int32, i64p, i32p,
+                                             ctypes.c_uint64, ctypes.c_int64, i64p]
+        L.oc_contended_makespans.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -197,4 +201,29 @@ def rounds_makespans(gpu, kernels, orders) -> np.ndarray:
                                    _ptr(o, ctypes.c_int32), o.shape[0], _ptr(out, ctypes.c_int64))
     if rc:
         raise ValueError("invalid input (bad descriptor or an order is not a permutation)")
+    return out
+
+
+def contended_makespans(gpu, kernels, mem_blocks: int, orders=None, *, first: int = 0,
+                        count: int | None = None) -> np.ndarray:
+    """Makespans when the resident blocks share the chip's memory throughput
+    (Section 4's balance of instructions and memory accesses): mem_blocks
+    memory-bound blocks run at full speed at once, more slow every resident
+    block down by the same factor.  orders: int array [count, n] of
+    permutations, or None for lexicographic ranks first .. first+count-1."""
+    g, k = gpu_array(gpu), kernel_array(kernels)
+    n = k.shape[0]
+    if orders is not None:
+        o = np.ascontiguousarray(orders, dtype=np.int32)
+        if o.ndim != 2 or o.shape[1] != n:
+            raise ValueError("orders must be [count, n]")
+        count = o.shape[0]
+        optr = _ptr(o, ctypes.c_int32)
+    else:
+        optr = None
+    out = np.zeros(count, dtype=np.int64)
+    rc = lib().oc_contended_makespans(_ptr(g, ctypes.c_int64), int(mem_blocks), n, _ptr(k, ctypes.c_int64),
+                                      optr, int(first), int(count), _ptr(out, ctypes.c_int64))
+    if rc:
+        raise ValueError("invalid input (bad descriptor, mem_blocks or order)")
     return out

@@ -461,3 +461,162 @@ int oc_rounds_makespans(const int64_t *gpu, int32_t n, const int64_t *kern, cons
     sim_free(&s);
     return rc;
 }
+
+/* ---- memory-bandwidth contention between resident blocks (Section 4) ----
+ *
+ * Section 4 asks that the blocks running together balance instructions
+ * against memory accesses, because R_B, the GPU's balanced
+ * instruction/memory ratio, is a property of the whole chip.  This third
+ * model lets the resident blocks share the chip's memory throughput:
+ *
+ *   - mem_blocks = B is how many memory-bound blocks the chip's memory
+ *     system serves at their full (isolated) speed at once;
+ *   - a block of kernel i alone keeps the memory system busy for the share
+ *     u_i = min(R_i, R_B) / R_i of its duration (1 for a memory-bound kernel,
+ *     R_B / R_i for a compute-bound one), counted in units of 1/1024 and
+ *     rounded up: uq_i = ceil(1024 * min(r_i, r_B) / r_i);
+ *   - while the resident blocks' shares add up to U (units of 1/1024) and U
+ *     exceeds 1024 * B, every resident block runs slower by the same factor:
+ *     per cycle it completes rate = floor(65536 * 1024 * B / U) units of
+ *     progress, where an isolated cycle is 65536 units (rate = 65536 when
+ *     U <= 1024 * B);
+ *   - a block of kernel i needs d_i * 65536 units of progress; it ends at the
+ *     first whole cycle at which its progress is complete; all blocks ending
+ *     at a cycle release before placement resumes, as in the first model.
+ * Placement is the first model's.  With B large enough that U never exceeds
+ * 1024 * B, every makespan equals the first model's. */
+
+#define OC_UNIT 65536LL
+#define OC_SHARE 1024LL
+
+typedef struct {
+    int64_t target;   /* progress at which the block ends */
+    int32_t cu;
+    int32_t k;
+} oc_cblock;
+
+static int64_t contended_rate(int64_t used, int64_t mem_blocks)
+{
+    const int64_t cap = OC_SHARE * mem_blocks;
+    return used <= cap ? OC_UNIT : (OC_UNIT * cap) / used;
+}
+
+static int64_t simulate_contended(oc_sim *s, const int32_t *order, const int64_t *share,
+                                  int64_t mem_blocks, oc_cblock *run)
+{
+    const int32_t N = s->n_cu;
+    for (int32_t c = 0; c < N; c++)
+        for (int x = 0; x < 4; x++)
+            s->freec[4 * c + x] = s->cap[x];
+    int32_t ptr = 0;
+    int32_t pos = 0;
+    int64_t left = s->tblk[order[0]];
+    int64_t nrun = 0;
+    int64_t t = 0;
+    int64_t progress = 0;  /* progress of every resident block since t = 0 */
+    int64_t used = 0;      /* sum of the resident blocks' shares */
+
+    for (;;) {
+        while (pos < s->n) {
+            int32_t k = order[pos];
+            int32_t found = -1;
+            for (int32_t i = 0; i < N; i++) {
+                int32_t c = (ptr + i) % N;
+                if (fits(s, c, k)) {
+                    found = c;
+                    break;
+                }
+            }
+            if (found < 0)
+                break;
+            for (int x = 0; x < 4; x++)
+                s->freec[4 * found + x] -= s->use[4 * k + x];
+            run[nrun].target = progress + s->dur[k] * OC_UNIT;
+            run[nrun].cu = found;
+            run[nrun].k = k;
+            nrun++;
+            used += share[k];
+            ptr = (found + 1) % N;
+            if (--left == 0) {
+                pos++;
+                if (pos < s->n)
+                    left = s->tblk[order[pos]];
+            }
+        }
+        if (nrun == 0)
+            break;
+        /* the block with the least progress left ends first; whole cycles */
+        int64_t tmin = run[0].target;
+        for (int64_t b = 1; b < nrun; b++)
+            if (run[b].target < tmin)
+                tmin = run[b].target;
+        const int64_t rate = contended_rate(used, mem_blocks);
+        const int64_t dt = (tmin - progress + rate - 1) / rate;
+        t += dt;
+        progress += dt * rate;
+        int64_t keep = 0;
+        for (int64_t b = 0; b < nrun; b++) {
+            if (run[b].target <= progress) {
+                for (int x = 0; x < 4; x++)
+                    s->freec[4 * run[b].cu + x] += s->use[4 * run[b].k + x];
+                used -= share[run[b].k];
+            } else {
+                run[keep++] = run[b];
+            }
+        }
+        nrun = keep;
+    }
+    return t;
+}
+
+/* Memory shares (units of 1/1024) of the kernels, as defined above. */
+static void contended_shares(const int64_t *gpu, int32_t n, const int64_t *kern, int64_t *share)
+{
+    for (int32_t i = 0; i < n; i++) {
+        const int64_t r = kern[6 * i + K_R];
+        const int64_t lo = r < gpu[G_RB] ? r : gpu[G_RB];
+        share[i] = (OC_SHARE * lo + r - 1) / r;
+    }
+}
+
+/* Contended makespans of `count` explicit orders (orders[count*n]), or, when
+ * orders is NULL, of the orders with lexicographic ranks lo .. lo+count-1.
+ * mem_blocks >= 1. */
+int oc_contended_makespans(const int64_t *gpu, int64_t mem_blocks, int32_t n, const int64_t *kern,
+                           const int32_t *orders, uint64_t lo, int64_t count, int64_t *out)
+{
+    int64_t use[4 * 32], dur[32], tblk[32], share[32];
+    int32_t perm[32];
+    if (n < 1 || n > 20 || count < 0 || mem_blocks < 1 || mem_blocks > (1LL << 24))
+        return OC_EINVAL;
+    if (orders) {
+        for (int64_t j = 0; j < count; j++) {
+            int seen[32] = {0};
+            const int32_t *o = orders + j * n;
+            for (int32_t p = 0; p < n; p++) {
+                if (o[p] < 0 || o[p] >= n || seen[o[p]])
+                    return OC_EINVAL;
+                seen[o[p]] = 1;
+            }
+        }
+    }
+    oc_sim s;
+    int rc = sim_init(&s, gpu, n, kern, use, dur, tblk);
+    if (rc)
+        return rc;
+    contended_shares(gpu, n, kern, share);
+    oc_cblock *run = (oc_cblock *)malloc(sizeof(oc_cblock) * (size_t)s.n_cu * (size_t)gpu[G_BLK]);
+    if (!run) {
+        sim_free(&s);
+        return OC_ENOMEM;
+    }
+    for (int64_t j = 0; j < count; j++) {
+        const int32_t *o = orders ? orders + j * n : perm;
+        if (!orders)
+            oc_unrank(n, lo + (uint64_t)j, perm);
+        out[j] = simulate_contended(&s, o, share, mem_blocks, run);
+    }
+    free(run);
+    sim_free(&s);
+    return 0;
+}
