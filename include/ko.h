@@ -368,6 +368,19 @@ int ko_topk_f32(const float *y_dev, uint64_t count, int32_t k, int64_t *idx_out_
 int ko_kth_smallest_i64(const int64_t *v_dev, uint64_t count, uint64_t k, int64_t *value_out,
                         uint64_t *count_le_out, void *hip_stream);
 
+/* ko_sort_i64 — the ranking curve of a full enumeration (Figure 1's
+ * "Ranking"): the makespans v[count] (int64, device) in ascending order into
+ * sorted_out[count] (int64, device, nullable) and, in index_out[count]
+ * (uint64, device, nullable), the position in v of each; equal values keep
+ * their order in v (for a rank-ordered makespan array, ties go to the smaller
+ * rank, so both outputs are unique).  At least one output; either may be v
+ * itself.  1 <= count < 2^32.  A stable LSD radix sort on the device over the
+ * 8-bit digits that v - min(v) uses; its (key, index) buffers are the
+ * library's workspace (12 bytes per value, twice).  Synchronous.
+ * Errors: KO_EINVAL (arguments), KO_ENOMEM, KO_EHIP. */
+int ko_sort_i64(const int64_t *v_dev, uint64_t count, int64_t *sorted_out_dev, uint64_t *index_out_dev,
+                void *hip_stream);
+
 /* ------------------------------------------------------------------ hardware
  * Validation of the model on the GPU itself (not part of the model): each
  * kernel of a set becomes a synthetic HIP kernel with its grid (n_tblk

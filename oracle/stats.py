@@ -13,7 +13,12 @@ Readings:
 * the percentile is reported from exact counts: inclusive (share of orders
   at least as slow as the reference), strict (share strictly slower) and
   mid-rank (strict plus half the ties);
-* histogram bins: bin = floor((M - min) * n_bins / (max - min + 1)).
+* histogram bins: bin = floor((M - min) * n_bins / (max - min + 1));
+* Figure 1's ranking: the makespans of all orders in ascending order, equal
+  makespans by smaller rank;
+* Section 6's "a gain of at least g over a random order with probability at
+  least one half": the largest g for which at least half of all orders have a
+  makespan of at least (1 + g) times the algorithm's.
 """
 
 from __future__ import annotations
@@ -58,3 +63,23 @@ def speedup_over_worst(t_worst: float, t_alg: float) -> float:
 
 def deviation_from_optimal(t_opt: float, t_alg: float) -> float:
     return (t_alg - t_opt) / t_opt
+
+
+def ranking_curve(makespans):
+    """Figure 1's ranking curve: (makespans ascending, rank of each), ties by
+    smaller rank (a stable sort of the rank-ordered array)."""
+    m = np.asarray(makespans, dtype=np.int64)
+    idx = np.argsort(m, kind="stable")
+    return m[idx], idx
+
+
+def median_gain(makespans, t_alg: int) -> float:
+    """Section 6's gain over a random order reached with probability at least
+    one half: over the distinct makespans m, the largest with at least half of
+    all orders at m or slower, as m / t_alg - 1."""
+    m = np.asarray(makespans, dtype=np.int64)
+    n = m.size
+    vals, counts = np.unique(m, return_counts=True)  # ascending
+    at_or_above = n - np.concatenate([[0], np.cumsum(counts)[:-1]])
+    best = int(vals[2 * at_or_above >= n].max())
+    return best / float(t_alg) - 1.0

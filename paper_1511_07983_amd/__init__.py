@@ -42,7 +42,7 @@ EXPORTED = ("ko_heuristic_order", "ko_count_orders", "ko_simulate_batch", "ko_ra
             "ko_sync", "ko_shutdown", "ko_plan_create", "ko_plan_info", "ko_plan_launch", "ko_plan_status",
             "ko_plan_engine",
             "ko_plan_destroy", "ko_graph_capture", "ko_graph_launch", "ko_graph_destroy",
-            "ko_sample_orders", "ko_topk_f32", "ko_kth_smallest_i64", "ko_simulate_rounds",
+            "ko_sample_orders", "ko_topk_f32", "ko_kth_smallest_i64", "ko_sort_i64", "ko_simulate_rounds",
             "ko_set_kernel_timing", "ko_last_kernel_ms", "ko_hw_vgprs", "ko_hw_time_orders",
             "ko_hw_last_error", "ko_last_error")
 
@@ -164,6 +164,9 @@ def _L():
                                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64),
                                              ctypes.c_void_p]
         lib.ko_kth_smallest_i64.restype = ctypes.c_int
+        lib.ko_sort_i64.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+        lib.ko_sort_i64.restype = ctypes.c_int
         lib.ko_hw_vgprs.argtypes = [ctypes.c_int32, _i32p]
         lib.ko_hw_vgprs.restype = ctypes.c_int
         lib.ko_hw_time_orders.argtypes = [ctypes.c_void_p, ctypes.c_int32, _i32p, ctypes.c_int32, ctypes.c_int32,
@@ -519,6 +522,39 @@ def ko_kth_smallest_i64(v, k: int, stream=None, *, with_count: bool = False):
     _check(_L().ko_kth_smallest_i64(_dev_ptr(v, torch.int64, v.numel(), "v"), v.numel(), int(k),
                                     ctypes.byref(out), ctypes.byref(le), _stream_handle(stream)))
     return (int(out.value), int(le.value)) if with_count else int(out.value)
+
+
+def ko_sort_i64(v, *, sorted_out=None, index_out=None, want_index: bool = True, stream=None):
+    """Stable ascending sort of the int64 device tensor v on the device
+    (synchronous): (sorted values, index in v of each) as device tensors
+    (int64, and uint64 read as int64); ties keep their order in v."""
+    import torch
+    n = v.numel()
+    if sorted_out is None:
+        sorted_out = torch.empty(n, dtype=torch.int64, device=v.device)
+    if index_out is None and want_index:
+        index_out = torch.empty(n, dtype=torch.int64, device=v.device)
+    _check(_L().ko_sort_i64(_dev_ptr(v, torch.int64, n, "v"), n, _dev_ptr(sorted_out, torch.int64, n, "sorted_out"),
+                            _dev_ptr(index_out, torch.int64, n, "index_out"), _stream_handle(stream)))
+    return sorted_out, index_out
+
+
+def ranking_curve(makespans, stream=None):
+    """Figure 1's ranking curve of a full enumeration: the makespans of all
+    orders in ascending order and the lexicographic rank of each (ties by
+    smaller rank), both device tensors."""
+    return ko_sort_i64(makespans, stream=stream)
+
+
+def median_gain(makespans, t_alg: int, stream=None) -> float:
+    """The gain over a random order that Algorithm 1's order reaches with
+    probability at least one half (Section 6): g such that at least half of
+    all orders have a makespan >= (1 + g) * t_alg, i.e. the makespan of
+    ascending place floor(N/2) over t_alg, minus 1.  The selection runs on
+    the device (ko_kth_smallest_i64)."""
+    n = makespans.numel()
+    m = ko_kth_smallest_i64(makespans, n // 2 + 1, stream=stream)
+    return m / float(t_alg) - 1.0
 
 
 def ko_hw_vgprs(regs_thr: int) -> int:

@@ -406,6 +406,9 @@ struct Workspace {
     uint64_t *sel_host = nullptr;
     uint64_t *sel_cand = nullptr;
     size_t sel_cand_cap = 0;
+    // radix sort: two (key, index) buffers and the digit counts
+    void *sort_buf = nullptr;
+    size_t sort_cap = 0;
     // optional timing of the simulate kernel (ko_set_kernel_timing)
     hipEvent_t sim_begin = nullptr, sim_end = nullptr;
     bool timing = false;
@@ -502,6 +505,7 @@ void release_workspace(Workspace &w)
     (void)hipEventDestroy(w.done);
     (void)hipFree(w.sel_bins);
     (void)hipFree(w.sel_cand);
+    (void)hipFree(w.sort_buf);
     (void)hipHostFree(w.sel_host);
     (void)hipEventDestroy(w.sim_begin);
     (void)hipEventDestroy(w.sim_end);
@@ -1575,6 +1579,60 @@ int ko_kth_smallest_i64(const int64_t *v_dev, uint64_t count, uint64_t k, int64_
     *value_out = (int64_t)(prefix ^ 0x8000000000000000ull);
     if (count_le_out)
         *count_le_out = k - rem + cls;  // below the k-th value, plus its ties
+    return KO_OK;
+}
+
+int ko_sort_i64(const int64_t *v_dev, uint64_t count, int64_t *sorted_out_dev, uint64_t *index_out_dev,
+                void *hip_stream)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (!v_dev || (!sorted_out_dev && !index_out_dev))
+        return fail(KO_EINVAL, "v_dev and at least one output must not be NULL");
+    if (count < 1 || count >= (uint64_t(1) << 32))
+        return fail(KO_EINVAL, "count %llu outside 1 .. 2^32-1", (unsigned long long)count);
+    Workspace *w = nullptr;
+    int rc = get_workspace(&w);
+    if (rc)
+        return rc;
+    rc = check_status(*w, false);
+    if (rc)
+        return rc;
+    const uint64_t tiles = ko::sort_tiles(count);
+    const size_t key_bytes = (count * 8 + 255) & ~(size_t)255;
+    const size_t idx_bytes = (count * 4 + 255) & ~(size_t)255;
+    const size_t need = 2 * key_bytes + 2 * idx_bytes + tiles * 256 * 4;
+    if ((rc = grow_device(w->done, &w->sort_buf, &w->sort_cap, need)))
+        return rc;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    KO_HIP(hipStreamWaitEvent(stream, w->done, 0), "hipStreamWaitEvent");
+    // the spread of the values fixes the number of digit passes
+    int e = ko::launch_zero_u64((uint64_t *)w->sel_bins, 2, stream);
+    if (e)
+        return hip_fail((hipError_t)e, "zero min/max");
+    e = ko::launch_minmax_i64(v_dev, count, w->sel_bins, std::max(1, w->cu_count * 8), stream);
+    if (e)
+        return hip_fail((hipError_t)e, "min/max launch");
+    KO_HIP(hipMemcpyAsync(w->sel_host, w->sel_bins, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+           "hipMemcpyAsync");
+    KO_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    const uint64_t kmin = ~w->sel_host[0], kmax = w->sel_host[1];
+    const int64_t vmin = (int64_t)(kmin ^ 0x8000000000000000ull);
+    const uint64_t span = kmax - kmin;
+    uint32_t passes = 0;
+    while (passes < 8 && (span >> (8 * passes)) != 0)
+        passes++;
+    char *b = static_cast<char *>(w->sort_buf);
+    uint64_t *keys_a = reinterpret_cast<uint64_t *>(b);
+    uint64_t *keys_b = reinterpret_cast<uint64_t *>(b + key_bytes);
+    uint32_t *idx_a = reinterpret_cast<uint32_t *>(b + 2 * key_bytes);
+    uint32_t *idx_b = reinterpret_cast<uint32_t *>(b + 2 * key_bytes + idx_bytes);
+    uint32_t *counts = reinterpret_cast<uint32_t *>(b + 2 * key_bytes + 2 * idx_bytes);
+    e = ko::launch_sort_i64(v_dev, count, vmin, passes, keys_a, idx_a, keys_b, idx_b, counts, sorted_out_dev,
+                            index_out_dev, stream);
+    if (e)
+        return hip_fail((hipError_t)e, "sort launch");
+    KO_HIP(hipEventRecord(w->done, stream), "hipEventRecord");
+    KO_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
     return KO_OK;
 }
 

@@ -140,6 +140,173 @@ __global__ void unpack_topk_kernel(const uint64_t *keys, uint32_t k, int64_t *id
         val[i] = key_f32((uint32_t)(c >> 32));
 }
 
+// ------------------------------------------------------------------ sorting
+//
+// Stable LSD radix sort of (key, index) pairs, 8-bit digits, for the ranking
+// curve of a full enumeration: keys are makespans minus their minimum, so a
+// set whose makespans span less than 2^24 cycles sorts in three passes.  Each
+// pass: count the digits of every tile, scan the digit-major count table, then
+// scatter each tile in index order.  Within a tile, elements are ranked 256
+// at a time: a wavefront finds the lanes that share a lane's digit with eight
+// ballots, and the four wavefronts' counts are chained through LDS, so equal
+// digits keep their input order (the pass is stable).
+
+constexpr uint32_t kSortThreads = 256;
+constexpr uint32_t kSortItems = 16;
+constexpr uint32_t kSortTile = kSortThreads * kSortItems;
+
+// keys[i] = v[i] - min as an unsigned offset, idx[i] = i
+__global__ __launch_bounds__(256) void sort_init_kernel(const int64_t *v, uint64_t count, int64_t vmin,
+                                                        uint64_t *keys, uint32_t *idx)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        keys[i] = (uint64_t)v[i] - (uint64_t)vmin;
+        idx[i] = (uint32_t)i;
+    }
+}
+
+// minimum and maximum of v as order-preserving unsigned keys: mm[0] becomes
+// the complement of the smallest key, mm[1] the largest (both start at 0)
+__global__ __launch_bounds__(256) void minmax_i64_kernel(const int64_t *v, uint64_t count,
+                                                         unsigned long long *mm)
+{
+    uint64_t lo = ~0ull, hi = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const uint64_t k = i64_key(v[i]);
+        lo = k < lo ? k : lo;
+        hi = k > hi ? k : hi;
+    }
+    __shared__ uint64_t s_lo[256], s_hi[256];
+    s_lo[threadIdx.x] = lo;
+    s_hi[threadIdx.x] = hi;
+    __syncthreads();
+    for (uint32_t h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            const uint64_t a = s_lo[threadIdx.x + h], b = s_hi[threadIdx.x + h];
+            s_lo[threadIdx.x] = a < s_lo[threadIdx.x] ? a : s_lo[threadIdx.x];
+            s_hi[threadIdx.x] = b > s_hi[threadIdx.x] ? b : s_hi[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(&mm[0], (unsigned long long)~s_lo[0]);
+        atomicMax(&mm[1], (unsigned long long)s_hi[0]);
+    }
+}
+
+// counts[d * n_tiles + t] = elements of tile t whose digit is d
+__global__ __launch_bounds__(256) void sort_count_kernel(const uint64_t *keys, uint64_t count, uint32_t shift,
+                                                         uint32_t n_tiles, uint32_t *counts)
+{
+    __shared__ uint32_t local[256];
+    local[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    for (uint32_t r = 0; r < kSortItems; r++) {
+        const uint64_t i = base + (uint64_t)r * kSortThreads + threadIdx.x;
+        if (i < count)
+            atomicAdd(&local[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(uint64_t)threadIdx.x * n_tiles + blockIdx.x] = local[threadIdx.x];
+}
+
+// In-place exclusive prefix sum of counts[0, len) by one workgroup of 1024
+// threads: each thread sums a contiguous segment, the segment sums are scanned
+// in LDS, and each thread rewrites its segment.
+__global__ __launch_bounds__(1024) void sort_scan_kernel(uint32_t *counts, uint64_t len)
+{
+    __shared__ uint32_t part[1024];
+    const uint64_t seg = (len + 1023) / 1024;
+    const uint64_t lo = min((uint64_t)threadIdx.x * seg, len), hi = min(lo + seg, len);
+    uint32_t sum = 0;
+    for (uint64_t i = lo; i < hi; i++)
+        sum += counts[i];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+        const uint32_t add = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - sum;
+    for (uint64_t i = lo; i < hi; i++) {
+        const uint32_t c = counts[i];
+        counts[i] = run;
+        run += c;
+    }
+}
+
+// Scatter tile blockIdx.x to its digits' places: offsets[d * n_tiles + t] is
+// where tile t's first element of digit d goes.  Every thread runs every
+// round (no early exit), so the ballots see a full wavefront; lanes past the
+// end take part as invalid.
+__global__ __launch_bounds__(256) void sort_scatter_kernel(const uint64_t *keys_in, const uint32_t *idx_in,
+                                                           uint64_t count, uint32_t shift, uint32_t n_tiles,
+                                                           const uint32_t *offsets, uint64_t *keys_out,
+                                                           uint32_t *idx_out)
+{
+    __shared__ uint32_t tile_off[256];   // global place of this tile's next element, per digit
+    __shared__ uint32_t wave_cnt[4][256];
+    __shared__ uint32_t wave_off[4][256];
+    const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
+    tile_off[t] = offsets[(uint64_t)t * n_tiles + blockIdx.x];
+    for (uint32_t w = 0; w < 4; w++)
+        wave_cnt[w][t] = 0;
+    __syncthreads();
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    for (uint32_t r = 0; r < kSortItems; r++) {
+        const uint64_t i = base + (uint64_t)r * kSortThreads + t;
+        const bool valid = i < count;
+        const uint64_t key = valid ? keys_in[i] : 0ull;
+        const uint32_t id = valid ? idx_in[i] : 0u;
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        uint64_t same = __ballot(valid);
+        for (uint32_t b = 0; b < 8; b++) {
+            const uint64_t on = __ballot((d >> b) & 1u);
+            same &= ((d >> b) & 1u) ? on : ~on;
+        }
+        const uint32_t rank = (uint32_t)__popcll(same & below);
+        // the lowest valid lane of each digit group records the group's size
+        if (valid && rank == 0)
+            wave_cnt[wave][d] = (uint32_t)__popcll(same);
+        __syncthreads();
+        {
+            uint32_t run = tile_off[t];
+            for (uint32_t w = 0; w < 4; w++) {
+                wave_off[w][t] = run;
+                run += wave_cnt[w][t];
+                wave_cnt[w][t] = 0;
+            }
+            tile_off[t] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t dst = wave_off[wave][d] + rank;
+            keys_out[dst] = key;
+            idx_out[dst] = id;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void sort_unpack_kernel(const uint64_t *keys, const uint32_t *idx,
+                                                          uint64_t count, int64_t vmin, int64_t *sorted,
+                                                          uint64_t *index)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        if (sorted)
+            sorted[i] = (int64_t)(keys[i] + (uint64_t)vmin);
+        if (index)
+            index[i] = idx[i];
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 namespace {
@@ -205,6 +372,49 @@ int launch_bitonic_sort_u64(uint64_t *keys, uint64_t used, uint64_t n_pow2, void
                 return e;
         }
     return 0;
+}
+
+int launch_minmax_i64(const int64_t *v, uint64_t count, unsigned long long *mm, int grid_cap, void *stream)
+{
+    hipLaunchKernelGGL(minmax_i64_kernel, dim3(blocks_for(count, (uint64_t)grid_cap)), dim3(256), 0,
+                       (hipStream_t)stream, v, count, mm);
+    return (int)hipGetLastError();
+}
+
+uint64_t sort_tiles(uint64_t count) { return (count + kSortTile - 1) / kSortTile; }
+
+int launch_sort_i64(const int64_t *v, uint64_t count, int64_t vmin, uint32_t passes, uint64_t *keys_a,
+                    uint32_t *idx_a, uint64_t *keys_b, uint32_t *idx_b, uint32_t *counts, int64_t *sorted,
+                    uint64_t *index, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned g = blocks_for(count, 1ull << 31);
+    hipLaunchKernelGGL(sort_init_kernel, dim3(g), dim3(256), 0, st, v, count, vmin, keys_a, idx_a);
+    int e = (int)hipGetLastError();
+    if (e)
+        return e;
+    const uint32_t tiles = (uint32_t)sort_tiles(count);
+    for (uint32_t p = 0; p < passes; p++) {
+        const uint32_t shift = 8u * p;
+        hipLaunchKernelGGL(sort_count_kernel, dim3(tiles), dim3(256), 0, st, keys_a, count, shift, tiles, counts);
+        if ((e = (int)hipGetLastError()))
+            return e;
+        hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(1024), 0, st, counts, (uint64_t)tiles * 256u);
+        if ((e = (int)hipGetLastError()))
+            return e;
+        hipLaunchKernelGGL(sort_scatter_kernel, dim3(tiles), dim3(256), 0, st, keys_a, idx_a, count, shift,
+                           tiles, counts, keys_b, idx_b);
+        if ((e = (int)hipGetLastError()))
+            return e;
+        uint64_t *tk = keys_a;
+        keys_a = keys_b;
+        keys_b = tk;
+        uint32_t *ti = idx_a;
+        idx_a = idx_b;
+        idx_b = ti;
+    }
+    hipLaunchKernelGGL(sort_unpack_kernel, dim3(g), dim3(256), 0, st, keys_a, idx_a, count, vmin, sorted, index);
+    return (int)hipGetLastError();
 }
 
 int launch_unpack_topk(const uint64_t *keys, uint32_t k, int64_t *idx, float *val, void *stream)

@@ -316,6 +316,13 @@ def test_full_size_n10_all_orders_against_oracle():
     r = ko.ko_rank_percentile(w.model, ks, h_order)
     assert r["makespan"] == ref
     assert (r["n_less"], r["n_equal"], r["n_greater"]) == (o["n_less"], o["n_equal"], o["n_greater"])
+    # Figure 1's ranking curve (device sort) and Section 6's median gain
+    say("n=10 ranking curve")
+    curve, ranks = ko.ranking_curve(torch.from_numpy(ms).to("cuda:0"))
+    want_curve, want_ranks = ostats.ranking_curve(want)
+    assert np.array_equal(curve.cpu().numpy(), want_curve)
+    assert np.array_equal(ranks.cpu().numpy(), want_ranks)
+    assert ko.median_gain(torch.from_numpy(ms).to("cuda:0"), ref) == ostats.median_gain(want, ref)
 
 
 def test_batch_sets_n7_to_n9_full_enumeration_against_oracle():

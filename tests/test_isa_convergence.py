@@ -72,6 +72,12 @@ def nn_report(tmp_path_factory):
     return ic.check(_asm(os.path.join(CSRC, "ko_nn.hip"), str(d / "ko_nn.s")))
 
 
+@pytest.fixture(scope="module")
+def select_report(tmp_path_factory):
+    d = tmp_path_factory.mktemp("isa")
+    return ic.check(_asm(os.path.join(CSRC, "ko_select.hip"), str(d / "ko_select.s")))
+
+
 def _pick(report, needle):
     names = [n for n in report if needle in n]
     assert names, f"no kernel matching {needle} in {sorted(report)}"
@@ -118,6 +124,15 @@ def test_reduce_collectives_full_exec(sim_report):
     for name in _pick(sim_report, "reduce_kernel"):
         bad, _ = sim_report[name]
         assert bad == [], (name, bad[:5])
+
+
+def test_sort_scatter_collectives_full_exec(select_report):
+    """The radix sort's scatter ranks lanes by digit with ballots: every lane
+    of the wavefront must take part in them, also past the end of the data."""
+    for name in _pick(select_report, "sort_scatter_kernel"):
+        bad, _ = select_report[name]
+        assert bad == [], (name, bad[:5])
+
 
 
 @pytest.mark.parametrize("needle", ["out_forward_kernel", "loss_kernel", "out_backward_kernel",

@@ -302,3 +302,33 @@ def test_sampled_rank_from_published_outputs(golden):
         assert splitmix64_at(g["seed"], s["index"]) == s["x"]
         for n_orders, want in s["ranks"].items():
             assert sampled_rank(g["seed"], g["set"], s["index"], int(n_orders)) == want
+
+
+def test_ranking_curve_and_median_gain_hand_worked():
+    """Figure 1's ranking and Section 6's median gain on arrays small enough
+    to work by hand.  [3, 1, 3, 1]: ascending 1, 1, 3, 3 from ranks 1, 3, 0, 2
+    (ties by smaller rank).  Median gain of [5, 1, 4, 2, 3] against t_alg = 2:
+    3 of 5 orders take >= 3 (at least half), only 2 take >= 4, so the gain is
+    3/2 - 1 = 0.5; with [1, 2, 3, 4] two of four take >= 3, again 0.5; with
+    every order equal to t_alg it is 0."""
+    v, r = ostats.ranking_curve([3, 1, 3, 1])
+    assert v.tolist() == [1, 1, 3, 3] and r.tolist() == [1, 3, 0, 2]
+    assert ostats.median_gain([5, 1, 4, 2, 3], 2) == 0.5
+    assert ostats.median_gain([1, 2, 3, 4], 2) == 0.5
+    assert ostats.median_gain([7] * 9, 7) == 0.0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_median_gain_is_the_half_probability_threshold(seed):
+    """The defining property by brute force over every candidate gain: at the
+    returned g at least half the orders are >= (1 + g) * t_alg, and at any
+    larger makespan threshold fewer than half are."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 40))
+    m = rng.integers(10, 20, n)
+    t_alg = int(rng.integers(8, 15))
+    g = ostats.median_gain(m, t_alg)
+    thr = round((1 + g) * t_alg)
+    assert 2 * int((m >= thr).sum()) >= n
+    for v in range(thr + 1, 21):
+        assert 2 * int((m >= v).sum()) < n

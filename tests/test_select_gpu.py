@@ -15,6 +15,7 @@ import pytest
 
 import oracle
 import synth
+from oracle import stats as ostats
 from oracle.sampling import sampled_rank
 
 pytestmark = pytest.mark.gpu
@@ -132,3 +133,37 @@ def test_kth_smallest_i64(count):
         want = int(np.partition(v, k - 1)[k - 1])
         assert ko.ko_kth_smallest_i64(t, k) == want, k
         assert ko.ko_kth_smallest_i64(t, k, with_count=True) == (want, int((v <= want).sum())), k
+
+
+@pytest.mark.parametrize("count,span", [(1, 0), (4096, 0), (4097, 300), (65_537, 1 << 20),
+                                        (1_000_003, 1 << 40), (300_001, None)])
+def test_sort_i64_matches_stable_argsort(count, span):
+    """The device radix sort against numpy's stable argsort: values and
+    positions element by element, on ragged tile counts, all-equal arrays (no
+    digit pass), ties, negative values and the full int64 range (8 passes)."""
+    rng = np.random.default_rng(count)
+    if span is None:
+        v = rng.integers(-(1 << 63), (1 << 63) - 1, size=count, dtype=np.int64, endpoint=True)
+        v[:2] = [-(1 << 63), (1 << 63) - 1]
+    else:
+        v = -5_000 + rng.integers(0, span + 1, size=count, dtype=np.int64)
+    if count > 10:
+        v[rng.integers(0, count, count // 4)] = v[0]  # ties
+    t = torch.from_numpy(v).to(DEV)
+    say(f"sort count={count} span={span}")
+    s, i = ko.ko_sort_i64(t)
+    want_i = np.argsort(v, kind="stable")
+    assert np.array_equal(i.cpu().numpy(), want_i)
+    assert np.array_equal(s.cpu().numpy(), v[want_i])
+    # in place, values only
+    ko.ko_sort_i64(t, sorted_out=t, want_index=False)
+    assert np.array_equal(t.cpu().numpy(), v[want_i])
+
+
+def test_median_gain_on_device_matches_oracle():
+    rng = np.random.default_rng(3)
+    for n in (1, 2, 7, 720, 40_320):
+        m = rng.integers(1000, 1300, n)
+        t_alg = int(rng.integers(900, 1100))
+        got = ko.median_gain(torch.from_numpy(m).to(DEV), t_alg)
+        assert got == ostats.median_gain(m, t_alg), n
