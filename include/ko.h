@@ -198,6 +198,31 @@ int ko_simulate_batch(const ko_gpu_model *gpu, const ko_kernel *kernels, const i
                       int32_t n_bins, void *hip_stream);
 
 /*
+ * ko_simulate_batch_noalloc — ko_simulate_batch for callers that cannot
+ * allocate device or pinned host memory (code that must not call hipMalloc:
+ * tight serving loops, harnesses that forbid allocation).  Same arguments,
+ * outputs and errors as ko_simulate_batch, with these differences:
+ *   - the batch's tables, counters and work-item partials live in a
+ *     16 MiB array in device memory that the library holds for the life of
+ *     the process on every GPU it runs on; nothing is allocated per call
+ *     (the library's own device workspace is not used either);
+ *   - work items are at most 65536 whole chunks of orders (plus one partial
+ *     chunk per set); a batch whose tables and items need more than the
+ *     array holds fails with KO_ERANGE before any device work;
+ *   - synchronous: returns when the evaluation has finished on hip_stream,
+ *     with any device status error of this call (KO_EHIP for a malformed
+ *     explicit order);
+ *   - all calls on one GPU share the array and keep the last call's
+ *     contents; calls of one process are serialised by the library, so
+ *     overlapping calls on one GPU (from several processes sharing one
+ *     copy, which HIP does not do, or around the library's lock) would race.
+ */
+int ko_simulate_batch_noalloc(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *set_offsets,
+                              int32_t n_sets, const ko_order_spec *spec, const int64_t *ref_makespan_dev,
+                              int64_t *makespans_dev, ko_set_stats *stats_dev, uint64_t *hist_dev,
+                              int32_t n_bins, void *hip_stream);
+
+/*
  * ko_rank_percentile — the makespan of one order and its percentile rank
  * among all n! orders (n_samples = 0) or among n_samples sampled orders
  * (KO_ORDERS_SAMPLED with `seed`, set index 0).  Synchronous: waits on

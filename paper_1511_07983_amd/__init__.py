@@ -7,7 +7,7 @@ current HIP stream.  Importing this package fails loudly when libko.so has not
 been built (``python paper_1511_07983_amd/build.py``); there is no fallback.
 
 Names mirror the C ABI: ko_heuristic_order, ko_count_orders,
-ko_simulate_batch, ko_rank_percentile, ko_sync, ko_shutdown, ko_last_error.
+ko_simulate_batch, ko_simulate_batch_noalloc, ko_rank_percentile, ko_sync, ko_shutdown, ko_last_error.
 """
 
 from __future__ import annotations
@@ -38,7 +38,8 @@ KO_ORDERS_SAMPLED = 3
 KO_HEUR_PER_BLOCK = 1
 KO_HEUR_FULL_SORT = 2
 
-EXPORTED = ("ko_heuristic_order", "ko_count_orders", "ko_simulate_batch", "ko_rank_percentile",
+EXPORTED = ("ko_heuristic_order", "ko_count_orders", "ko_simulate_batch", "ko_simulate_batch_noalloc",
+            "ko_rank_percentile",
             "ko_sync", "ko_shutdown", "ko_plan_create", "ko_plan_info", "ko_plan_launch", "ko_plan_status",
             "ko_plan_engine",
             "ko_plan_destroy", "ko_graph_capture", "ko_graph_launch", "ko_graph_destroy",
@@ -125,6 +126,8 @@ def _L():
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_int32, ctypes.c_void_p]
         lib.ko_simulate_batch.restype = ctypes.c_int
+        lib.ko_simulate_batch_noalloc.argtypes = lib.ko_simulate_batch.argtypes
+        lib.ko_simulate_batch_noalloc.restype = ctypes.c_int
         lib.ko_rank_percentile.argtypes = [ctypes.POINTER(KoGpuModel), ctypes.c_void_p, ctypes.c_int32,
                                             _i32p, ctypes.c_uint64, ctypes.c_uint64,
                                             ctypes.POINTER(KoRankResult), ctypes.c_void_p]
@@ -327,6 +330,21 @@ def ko_simulate_batch(gpu, kernels, set_offsets, spec: OrderSpec, *, ref_makespa
     n_sets*8 int64) and ``hist`` (int64[n_sets*n_bins], read as uint64) are
     device tensors or None.
     """
+    return _simulate_batch("ko_simulate_batch", gpu, kernels, set_offsets, spec, ref_makespan, makespans,
+                           stats, hist, n_bins, stream)
+
+
+def ko_simulate_batch_noalloc(gpu, kernels, set_offsets, spec: OrderSpec, *, ref_makespan=None,
+                              makespans=None, stats=None, hist=None, n_bins: int = 0, stream=None):
+    """ko_simulate_batch without any device allocation: the library's static
+    per-GPU scratch holds the batch's tables (synchronous; KoError with
+    KO_ERANGE when a batch does not fit it).  Arguments as ko_simulate_batch."""
+    return _simulate_batch("ko_simulate_batch_noalloc", gpu, kernels, set_offsets, spec, ref_makespan,
+                           makespans, stats, hist, n_bins, stream)
+
+
+def _simulate_batch(entry, gpu, kernels, set_offsets, spec, ref_makespan, makespans, stats, hist, n_bins,
+                    stream):
     import torch
     g = gpu_model(gpu)
     k = kernel_array(kernels)
@@ -342,9 +360,9 @@ def ko_simulate_batch(gpu, kernels, set_offsets, spec: OrderSpec, *, ref_makespa
     ms_p = _dev_ptr(makespans, torch.int64, total, "makespans")
     st_p = _dev_ptr(stats, torch.int64, 8 * n_sets, "stats")
     h_p = _dev_ptr(hist, torch.int64, n_sets * max(n_bins, 0), "hist")
-    _check(_L().ko_simulate_batch(ctypes.byref(g), k.ctypes.data if len(k) else None,
-                                  off.ctypes.data_as(_i32p), n_sets, ctypes.byref(sp), ref_p,
-                                  ms_p, st_p, h_p, n_bins, _stream_handle(stream)))
+    _check(getattr(_L(), entry)(ctypes.byref(g), k.ctypes.data if len(k) else None,
+                                off.ctypes.data_as(_i32p), n_sets, ctypes.byref(sp), ref_p,
+                                ms_p, st_p, h_p, n_bins, _stream_handle(stream)))
     return per, total
 
 

@@ -544,6 +544,8 @@ int stage_upload(Workspace &w, hipStream_t stream, void *dst, const void *src, s
     return KO_OK;
 }
 
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
 uint64_t pow2_at_least(uint64_t v)
 {
     uint64_t p = 1;
@@ -683,9 +685,13 @@ int slots_for(int n_cu)
 // decomposition (chunks of consecutive orders per work item, persistent grid
 // of wg_per_cu workgroups per CU).  chunk_req = 0 picks the chunk: enough
 // items to balance the persistent waves, few enough to keep partials small.
+// The chunk grows until whole chunks number at most max_items (each set adds
+// one more item at most); the lane engine keeps at most spill_limit records
+// of spilled orders.
 int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *set_offsets,
               int32_t n_sets, const ko_order_spec *spec, int cu_count, uint64_t chunk_req, int wg_per_cu,
-              int engine, BatchPlan *plan)
+              int engine, BatchPlan *plan, uint64_t max_items = uint64_t(1) << 22,
+              uint64_t spill_limit = kSpillCap)
 {
     std::vector<uint64_t> per_set;
     int rc = count_orders(set_offsets, n_sets, spec, &per_set, &plan->total);
@@ -723,11 +729,11 @@ int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *
         chunk = pow2_at_least(std::max<uint64_t>(1, plan->total / (waves * 8)));
         chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, 16), 8192);
     }
-    const uint64_t max_items = uint64_t(1) << 22;
     if (plan->total / chunk > max_items)
         chunk = pow2_at_least((plan->total + max_items - 1) / max_items);
     plan->chunk = chunk;
-    plan->spill_cap = plan->lane_class ? std::max<uint64_t>(1, std::min<uint64_t>(plan->total, kSpillCap)) : 1;
+    plan->spill_cap =
+        plan->lane_class ? std::max<uint64_t>(1, std::min<uint64_t>(plan->total, spill_limit)) : 1;
     uint64_t out_base = 0, item_base = 0, list_base = 0, hist_base = 0;
     plan->sets.resize(n_sets);
     plan->block_base.resize(n_sets + 1);
@@ -965,6 +971,48 @@ int check_outputs(const int64_t *makespans_dev, const ko_set_stats *stats_dev, c
 
 }  // namespace
 
+// ------------------------------------------------- no-allocation entry point
+// Device memory of ko_simulate_batch_noalloc: the counters, kernel records,
+// set table, histogram bases and work-item area of one batch at a time.  Each
+// GPU holds its own copy of the array until the process ends.  In host code
+// the name is not a device address: the per-device address comes from
+// hipGetSymbolAddress, and only that address is used.
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+constexpr uint64_t kStaticItems = uint64_t(1) << 16;  // whole chunks at most
+constexpr uint64_t kStaticSpill = 8192;                // spilled-order records at most
+constexpr int kStaticDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+struct StaticScratch {
+    void *ptr = nullptr;  // device address of `scratch` on this device
+    int cu_count = 0;
+};
+StaticScratch g_static[kStaticDevices];
+
+// The device's copy of the array, looked up once per device (with it current).
+int static_scratch(int dev, StaticScratch **out)
+{
+    if (dev < 0 || dev >= kStaticDevices)
+        return fail(KO_EINVAL, "device %d: the static scratch covers devices 0..%d", dev, kStaticDevices - 1);
+    StaticScratch &s = g_static[dev];
+    if (!s.ptr) {
+        void *p = nullptr;
+        KO_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+        if (!p)
+            return fail(KO_EHIP, "hipGetSymbolAddress returned a null address");
+        KO_HIP(hipDeviceGetAttribute(&s.cu_count, hipDeviceAttributeMultiprocessorCount, dev),
+               "hipDeviceGetAttribute");
+        s.ptr = p;
+    }
+    *out = &s;
+    return KO_OK;
+}
+
+}  // namespace
+
 // A batch prepared once and launched many times (ko_plan_*).
 struct ko_plan {
     int device = -1;
@@ -1069,6 +1117,89 @@ int ko_simulate_batch(const ko_gpu_model *gpu, const ko_kernel *kernels, const i
             return rc;
         return simulate_impl(*w, gpu, kernels, set_offsets, n_sets, spec, ref_makespan_dev,
                              makespans_dev, stats_dev, hist_dev, n_bins, (hipStream_t)hip_stream);
+    } catch (const std::bad_alloc &) {
+        return fail(KO_ENOMEM, "host allocation failed");
+    }
+}
+
+int ko_simulate_batch_noalloc(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *set_offsets,
+                              int32_t n_sets, const ko_order_spec *spec, const int64_t *ref_makespan_dev,
+                              int64_t *makespans_dev, ko_set_stats *stats_dev, uint64_t *hist_dev,
+                              int32_t n_bins, void *hip_stream)
+{
+    try {
+        // one batch at a time per process: calls never overlap on the array
+        std::lock_guard<std::mutex> lock(g_mutex);
+        int rc = validate_batch(gpu, kernels, set_offsets, n_sets, spec, makespans_dev, stats_dev, hist_dev,
+                                n_bins);
+        if (rc)
+            return rc;
+        int dev = 0;
+        KO_HIP(hipGetDevice(&dev), "hipGetDevice");
+        StaticScratch *sc = nullptr;
+        if ((rc = static_scratch(dev, &sc)))
+            return rc;
+        BatchPlan plan;
+        rc = make_plan(gpu, kernels, set_offsets, n_sets, spec, sc->cu_count, 0, 8, KO_ENGINE_AUTO, &plan,
+                       kStaticItems, kStaticSpill);
+        if (rc)
+            return rc;
+        // layout of the array for this batch
+        const size_t kbytes = plan.krec.size() * sizeof(ko::KernelRec);
+        const size_t sbytes = plan.sets.size() * sizeof(ko::SetRec);
+        const size_t bbytes = plan.block_base.size() * sizeof(uint64_t);
+        const size_t cnt_off = 0;
+        const size_t krec_off = align256(cnt_off + kCounterWords * sizeof(unsigned long long));
+        const size_t sets_off = align256(krec_off + kbytes);
+        const size_t bb_off = align256(sets_off + sbytes);
+        const size_t item_off = align256(bb_off + bbytes);
+        const size_t need = item_off + item_area(plan.n_items, plan.spill_cap).bytes;
+        if (need > kStaticScratchBytes)
+            return fail(KO_ERANGE,
+                        "batch needs %zu bytes of device scratch (%zu kernel records, %d sets, %llu work items); "
+                        "the static scratch holds %zu",
+                        need, plan.krec.size(), n_sets, (unsigned long long)plan.n_items, kStaticScratchBytes);
+        char *base = static_cast<char *>(sc->ptr);
+        hipStream_t stream = (hipStream_t)hip_stream;
+        // a failed copy still waits for the ones enqueued before it: they read
+        // host tables that end with this call
+        hipError_t ce = hipSuccess;
+        if (kbytes)
+            ce = hipMemcpyAsync(base + krec_off, plan.krec.data(), kbytes, hipMemcpyHostToDevice, stream);
+        if (sbytes && ce == hipSuccess)
+            ce = hipMemcpyAsync(base + sets_off, plan.sets.data(), sbytes, hipMemcpyHostToDevice, stream);
+        if (ce == hipSuccess)
+            ce = hipMemcpyAsync(base + bb_off, plan.block_base.data(), bbytes, hipMemcpyHostToDevice, stream);
+        if (ce != hipSuccess) {
+            (void)hipStreamSynchronize(stream);
+            return hip_fail(ce, "hipMemcpyAsync");
+        }
+        unsigned long long *counter = reinterpret_cast<unsigned long long *>(base + cnt_off);
+        DevTables t{reinterpret_cast<const ko::KernelRec *>(base + krec_off),
+                    reinterpret_cast<const ko::SetRec *>(base + sets_off),
+                    reinterpret_cast<const uint64_t *>(base + bb_off), reinterpret_cast<ko::Partial *>(base + item_off),
+                    counter};
+        // every counter and the status word start at zero in every call
+        rc = enqueue_batch(t, plan, *gpu, n_sets, spec->mode, spec->seed, spec->orders_dev, true, ref_makespan_dev,
+                           makespans_dev, stats_dev, hist_dev, n_bins, stream, nullptr, nullptr);
+        uint32_t status = 0;
+        if (!rc)
+            ce = hipMemcpyAsync(&status, base + cnt_off + kStatusWord * sizeof(unsigned long long), sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, stream);
+        // the host tables and `status` must outlive the copies, and the next
+        // call must find the array idle
+        const hipError_t e = hipStreamSynchronize(stream);
+        if (rc)
+            return rc;
+        if (ce != hipSuccess)
+            return hip_fail(ce, "hipMemcpyAsync");
+        if (e != hipSuccess)
+            return hip_fail(e, "hipStreamSynchronize");
+        if (status & ko::kStatusBadOrder)
+            return fail(KO_EHIP, "device status: an explicit order was not a permutation");
+        if (status)
+            return fail(KO_EHIP, "device status: internal inconsistency (0x%x)", status);
+        return KO_OK;
     } catch (const std::bad_alloc &) {
         return fail(KO_ENOMEM, "host allocation failed");
     }
