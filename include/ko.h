@@ -66,8 +66,25 @@ typedef struct ko_gpu_model {
     int64_t reg_cu;    /* N_reg_SM: lane registers per CU; 1 .. 2^24 */
     int64_t lds_cu;    /* N_shm_SM: LDS / shared-memory bytes per CU; 1 .. 2^24 */
     int32_t rb_milli;  /* R_B, the balanced instruction/memory ratio, times 1000; >= 1 */
-    int32_t reserved;  /* must be 0 */
+    int32_t mem_blocks; /* 0: co-resident blocks do not slow each other (the model above);
+                           1 .. 2^24: they share the chip's memory throughput, which serves
+                           this many memory-bound blocks at full speed (see below) */
 } ko_gpu_model;
+
+/* Memory contention (mem_blocks > 0; Section 4: the blocks that run together
+ * should balance instructions against memory accesses, R_B being a property
+ * of the whole chip).  A block of kernel i alone keeps the memory system busy
+ * for the share min(R_i, R_B) / R_i of its duration, counted in 1/1024 units
+ * and rounded up: s_i = ceil(1024 * min(r_milli, rb_milli) / r_milli).  While
+ * the resident blocks' shares add up to U > 1024 * mem_blocks, every resident
+ * block runs slower by the same factor: a cycle brings
+ * floor(65536 * 1024 * mem_blocks / U) units of progress instead of 65536.  A
+ * block needs duration * 65536 units and ends at the first whole cycle at
+ * which it has them; all blocks ending at a cycle release before placement
+ * resumes; placement is unchanged.  With mem_blocks large enough that U never
+ * exceeds the cap, makespans equal those of mem_blocks = 0.  This model runs
+ * on the wave engine only (KO_ENGINE_LANES is refused); ko_heuristic_order
+ * ignores mem_blocks, ko_simulate_rounds refuses a nonzero value. */
 
 /* The per-kernel parameters of Table 1 (last three rows).  40 bytes. */
 typedef struct ko_kernel {

@@ -52,7 +52,7 @@ class KoGpuModel(ctypes.Structure):
     _fields_ = [("n_cu", ctypes.c_int32), ("wave_size", ctypes.c_int32),
                 ("wave_cu", ctypes.c_int32), ("blk_cu", ctypes.c_int32),
                 ("reg_cu", ctypes.c_int64), ("lds_cu", ctypes.c_int64),
-                ("rb_milli", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("rb_milli", ctypes.c_int32), ("mem_blocks", ctypes.c_int32)]
 
 
 class KoKernel(ctypes.Structure):
@@ -203,13 +203,17 @@ def _check(rc: int):
 
 
 def gpu_model(model) -> KoGpuModel:
-    """A KoGpuModel from a mapping or an object with the same field names."""
+    """A KoGpuModel from a mapping or an object with the same field names
+    (mem_blocks, the memory-contention parameter, is optional: 0 = none)."""
     if isinstance(model, KoGpuModel):
         return model
-    get = model.get if isinstance(model, dict) else (lambda f: getattr(model, f))
+    if isinstance(model, dict):
+        get, mem = model.get, model.get("mem_blocks", 0)
+    else:
+        get, mem = (lambda f: getattr(model, f)), getattr(model, "mem_blocks", 0)
     return KoGpuModel(int(get("n_cu")), int(get("wave_size")), int(get("wave_cu")),
                       int(get("blk_cu")), int(get("reg_cu")), int(get("lds_cu")),
-                      int(get("rb_milli")), 0)
+                      int(get("rb_milli")), int(mem))
 
 
 def kernel_array(kernels) -> np.ndarray:

@@ -96,6 +96,11 @@ struct SimArgs {
     // GPU model
     uint32_t n_cu;
     uint32_t cap_reg, cap_lds, cap_wave, cap_blk;
+    // memory contention (simulate_kernel only): per KernelRec, the memory
+    // share of one block in 1/1024 units, and 1024 times the memory-bound
+    // blocks served at full speed; share = null for the model without it
+    const uint32_t *share;
+    uint64_t mem_cap;
 };
 
 struct ReduceArgs {

@@ -59,8 +59,8 @@ int check_gpu(const ko_gpu_model *g)
 {
     if (!g)
         return fail(KO_EINVAL, "gpu model is NULL");
-    if (g->reserved != 0)
-        return fail(KO_EINVAL, "gpu model: reserved field must be 0");
+    if (g->mem_blocks < 0 || g->mem_blocks > (1 << 24))
+        return fail(KO_EINVAL, "gpu model: mem_blocks %d outside 0..2^24", g->mem_blocks);
     if (g->n_cu < 1 || g->n_cu > 256)
         return fail(KO_EINVAL, "gpu model: n_cu %d outside 1..256", g->n_cu);
     if (g->wave_size < 1)
@@ -121,6 +121,14 @@ float inv_up(int64_t u)
     for (int i = 0; i < 3; i++)
         f = std::nextafter(f, INFINITY);
     return f;
+}
+
+// Memory share of one block of kernel k in 1/1024 units (memory contention,
+// include/ko.h): ceil(1024 * min(R_k, R_B) / R_k).
+uint32_t memory_share(const ko_gpu_model &g, const ko_kernel &k)
+{
+    const int64_t lo = std::min<int64_t>(k.r_milli, g.rb_milli);
+    return (uint32_t)((1024 * lo + k.r_milli - 1) / k.r_milli);
 }
 
 int derive_set(const ko_gpu_model &g, const ko_kernel *k, int32_t n, int32_t first_idx,
@@ -587,6 +595,7 @@ int validate_batch(const ko_gpu_model *gpu, const ko_kernel *kernels, const int3
 
 struct BatchPlan {
     std::vector<ko::KernelRec> krec;
+    std::vector<uint32_t> share;  // per kernel record, under memory contention only
     std::vector<ko::SetRec> sets;
     std::vector<uint64_t> block_base;
     uint64_t total = 0, n_items = 0, chunk = 0, hist_blocks = 0;
@@ -705,9 +714,17 @@ int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *
             return rc;
         plan->max_n = std::max<uint32_t>(plan->max_n, (uint32_t)n);
     }
+    if (gpu->mem_blocks) {
+        plan->share.resize(plan->krec.size());
+        for (size_t i = 0; i < plan->share.size(); i++)
+            plan->share[i] = memory_share(*gpu, kernels[i]);
+    }
     plan->slots = slots_for(gpu->n_cu);
     plan->grid = std::max(1, cu_count * wg_per_cu);
-    plan->lane_class = engine == KO_ENGINE_WAVE ? 0 : lane_class_for(*gpu, plan->max_n);
+    // memory contention runs on the wave engine only
+    plan->lane_class = (engine == KO_ENGINE_WAVE || gpu->mem_blocks) ? 0 : lane_class_for(*gpu, plan->max_n);
+    if (engine == KO_ENGINE_LANES && gpu->mem_blocks)
+        return fail(KO_EINVAL, "the lane engine does not model memory contention (mem_blocks > 0)");
     // a batch too small to fill the lanes finishes sooner with one wavefront
     // per order (one order alone: about 5 us against 0.35 ms for one lane)
     if (engine == KO_ENGINE_AUTO && plan->total < kLaneMinOrders)
@@ -762,6 +779,7 @@ int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *
 // Device tables a batch runs on.
 struct DevTables {
     const ko::KernelRec *krec;
+    const uint32_t *share;  // memory shares per kernel record, or null
     const ko::SetRec *sets;
     const uint64_t *block_base;
     ko::Partial *partials;        // start of the batch's item area (item_area)
@@ -817,6 +835,8 @@ int enqueue_batch(const DevTables &t, const BatchPlan &p, const ko_gpu_model &gp
         a.cap_lds = (uint32_t)gpu.lds_cu;
         a.cap_wave = (uint32_t)gpu.wave_cu;
         a.cap_blk = (uint32_t)gpu.blk_cu;
+        a.share = gpu.mem_blocks ? t.share : nullptr;
+        a.mem_cap = (uint64_t)1024 * (uint64_t)gpu.mem_blocks;
         const int g = (int)std::min<uint64_t>((uint64_t)p.grid, (p.n_items + 3) / 4);
         if (sim_begin)
             KO_HIP(hipEventRecord(sim_begin, stream), "hipEventRecord");
@@ -908,10 +928,13 @@ int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernel
         return rc;
 
     // device buffers
+    // kernel records, then (under memory contention) their shares
     const size_t kbytes = plan.krec.size() * sizeof(ko::KernelRec);
+    const size_t sh_off = align256(kbytes);
+    const size_t shbytes = plan.share.size() * sizeof(uint32_t);
     const size_t sbytes = plan.sets.size() * sizeof(ko::SetRec);
     const size_t bbytes = plan.block_base.size() * sizeof(uint64_t);
-    if ((rc = grow_device(w.done, (void **)&w.krec, &w.krec_cap, kbytes)) ||
+    if ((rc = grow_device(w.done, (void **)&w.krec, &w.krec_cap, sh_off + shbytes)) ||
         (rc = grow_device(w.done, (void **)&w.sets, &w.sets_cap, sbytes)) ||
         (rc = grow_device(w.done, (void **)&w.block_base, &w.block_base_cap, bbytes)) ||
         (rc = grow_device(w.done, (void **)&w.partials, &w.partials_cap,
@@ -919,7 +942,7 @@ int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernel
         return rc;
     // the previous call on any stream must be done with the workspace
     KO_HIP(hipStreamWaitEvent(stream, w.done, 0), "hipStreamWaitEvent");
-    const size_t stage_need = kbytes + sbytes + bbytes + 64;
+    const size_t stage_need = kbytes + shbytes + sbytes + bbytes + 64;
     if (stage_need > w.stage_cap) {
         KO_HIP(hipEventSynchronize(w.staged), "hipEventSynchronize");
         if (w.stage)
@@ -931,14 +954,16 @@ int simulate_impl(Workspace &w, const ko_gpu_model *gpu, const ko_kernel *kernel
     } else {
         KO_HIP(hipEventSynchronize(w.staged), "hipEventSynchronize");
     }
+    uint32_t *share_dev = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(w.krec) + sh_off);
     if ((rc = stage_upload(w, stream, w.krec, plan.krec.data(), kbytes, 0)) ||
         (rc = stage_upload(w, stream, w.sets, plan.sets.data(), sbytes, kbytes)) ||
-        (rc = stage_upload(w, stream, w.block_base, plan.block_base.data(), bbytes, kbytes + sbytes)))
+        (rc = stage_upload(w, stream, w.block_base, plan.block_base.data(), bbytes, kbytes + sbytes)) ||
+        (shbytes && (rc = stage_upload(w, stream, share_dev, plan.share.data(), shbytes, kbytes + sbytes + bbytes))))
         return rc;
     KO_HIP(hipEventRecord(w.staged, stream), "hipEventRecord");
 
     // the status word is cleared only once a reported status has been seen
-    DevTables t{w.krec, w.sets, w.block_base, w.partials, w.counter};
+    DevTables t{w.krec, shbytes ? share_dev : nullptr, w.sets, w.block_base, w.partials, w.counter};
     const bool timing = w.timing && plan.n_items > 0;
     rc = enqueue_batch(t, plan, *gpu, n_sets, spec->mode, spec->seed, spec->orders_dev, w.clear_status,
                        ref_dev, makespans_dev, stats_dev, hist_dev, n_bins, stream,
@@ -1023,6 +1048,7 @@ struct ko_plan {
     const uint8_t *orders = nullptr;
     BatchPlan plan;
     ko::KernelRec *krec = nullptr;
+    uint32_t *share = nullptr;  // inside the krec allocation, under memory contention only
     ko::SetRec *sets = nullptr;
     uint64_t *block_base = nullptr;
     ko::Partial *partials = nullptr;
@@ -1148,9 +1174,11 @@ int ko_simulate_batch_noalloc(const ko_gpu_model *gpu, const ko_kernel *kernels,
         const size_t kbytes = plan.krec.size() * sizeof(ko::KernelRec);
         const size_t sbytes = plan.sets.size() * sizeof(ko::SetRec);
         const size_t bbytes = plan.block_base.size() * sizeof(uint64_t);
+        const size_t shbytes = plan.share.size() * sizeof(uint32_t);
         const size_t cnt_off = 0;
         const size_t krec_off = align256(cnt_off + kCounterWords * sizeof(unsigned long long));
-        const size_t sets_off = align256(krec_off + kbytes);
+        const size_t sh_off = align256(krec_off + kbytes);
+        const size_t sets_off = align256(sh_off + shbytes);
         const size_t bb_off = align256(sets_off + sbytes);
         const size_t item_off = align256(bb_off + bbytes);
         const size_t need = item_off + item_area(plan.n_items, plan.spill_cap).bytes;
@@ -1170,12 +1198,15 @@ int ko_simulate_batch_noalloc(const ko_gpu_model *gpu, const ko_kernel *kernels,
             ce = hipMemcpyAsync(base + sets_off, plan.sets.data(), sbytes, hipMemcpyHostToDevice, stream);
         if (ce == hipSuccess)
             ce = hipMemcpyAsync(base + bb_off, plan.block_base.data(), bbytes, hipMemcpyHostToDevice, stream);
+        if (shbytes && ce == hipSuccess)
+            ce = hipMemcpyAsync(base + sh_off, plan.share.data(), shbytes, hipMemcpyHostToDevice, stream);
         if (ce != hipSuccess) {
             (void)hipStreamSynchronize(stream);
             return hip_fail(ce, "hipMemcpyAsync");
         }
         unsigned long long *counter = reinterpret_cast<unsigned long long *>(base + cnt_off);
         DevTables t{reinterpret_cast<const ko::KernelRec *>(base + krec_off),
+                    shbytes ? reinterpret_cast<const uint32_t *>(base + sh_off) : nullptr,
                     reinterpret_cast<const ko::SetRec *>(base + sets_off),
                     reinterpret_cast<const uint64_t *>(base + bb_off), reinterpret_cast<ko::Partial *>(base + item_off),
                     counter};
@@ -1254,11 +1285,13 @@ int ko_plan_create(const ko_gpu_model *gpu, const ko_kernel *kernels, const int3
             p->plan.lane_entries = std::min<uint32_t>((uint32_t)config->lane_entries,
                                                       ko::lane_entry_max(p->plan.lane_class));
         const size_t kbytes = p->plan.krec.size() * sizeof(ko::KernelRec);
+        const size_t sh_off = align256(kbytes);
+        const size_t shbytes = p->plan.share.size() * sizeof(uint32_t);
         const size_t sbytes = p->plan.sets.size() * sizeof(ko::SetRec);
         const size_t bbytes = p->plan.block_base.size() * sizeof(uint64_t);
         const size_t pbytes = item_area(p->plan.n_items, p->plan.spill_cap).bytes;
         hipError_t e = hipSuccess;
-        if ((e = hipMalloc((void **)&p->krec, std::max<size_t>(kbytes, 64))) != hipSuccess ||
+        if ((e = hipMalloc((void **)&p->krec, std::max<size_t>(sh_off + shbytes, 64))) != hipSuccess ||
             (e = hipMalloc((void **)&p->sets, std::max<size_t>(sbytes, 64))) != hipSuccess ||
             (e = hipMalloc((void **)&p->block_base, std::max<size_t>(bbytes, 64))) != hipSuccess ||
             (e = hipMalloc((void **)&p->partials, pbytes)) != hipSuccess ||
@@ -1266,7 +1299,10 @@ int ko_plan_create(const ko_gpu_model *gpu, const ko_kernel *kernels, const int3
             free_plan(p);
             return fail(KO_ENOMEM, "plan device allocation failed: %s", hipGetErrorString(e));
         }
+        if (shbytes)
+            p->share = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(p->krec) + sh_off);
         if ((kbytes && (e = hipMemcpy(p->krec, p->plan.krec.data(), kbytes, hipMemcpyHostToDevice)) != hipSuccess) ||
+            (shbytes && (e = hipMemcpy(p->share, p->plan.share.data(), shbytes, hipMemcpyHostToDevice)) != hipSuccess) ||
             (sbytes && (e = hipMemcpy(p->sets, p->plan.sets.data(), sbytes, hipMemcpyHostToDevice)) != hipSuccess) ||
             (e = hipMemcpy(p->block_base, p->plan.block_base.data(), bbytes, hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMemset(p->counter, 0, kCounterWords * sizeof(unsigned long long))) != hipSuccess ||
@@ -1276,6 +1312,7 @@ int ko_plan_create(const ko_gpu_model *gpu, const ko_kernel *kernels, const int3
         }
         // the host copies are no longer needed
         p->plan.krec = std::vector<ko::KernelRec>();
+        p->plan.share = std::vector<uint32_t>();
         *out = p;
         return KO_OK;
     } catch (const std::bad_alloc &) {
@@ -1308,7 +1345,7 @@ int ko_plan_launch(ko_plan *plan, const int64_t *ref_makespan_dev, int64_t *make
     int rc = check_outputs(makespans_dev, stats_dev, hist_dev, n_bins);
     if (rc || (rc = check_plan_device(plan)))
         return rc;
-    DevTables t{plan->krec, plan->sets, plan->block_base, plan->partials, plan->counter};
+    DevTables t{plan->krec, plan->share, plan->sets, plan->block_base, plan->partials, plan->counter};
     return enqueue_batch(t, plan->plan, plan->gpu, plan->n_sets, plan->mode, plan->seed, plan->orders, true,
                          ref_makespan_dev, makespans_dev, stats_dev, hist_dev, n_bins, (hipStream_t)hip_stream,
                          nullptr, nullptr);
@@ -1390,7 +1427,7 @@ int ko_graph_capture(ko_plan *plan, const int64_t *ref_makespan_dev, int64_t *ma
         return rc;
     hipStream_t st = (hipStream_t)hip_stream;
     KO_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    DevTables t{plan->krec, plan->sets, plan->block_base, plan->partials, plan->counter};
+    DevTables t{plan->krec, plan->share, plan->sets, plan->block_base, plan->partials, plan->counter};
     rc = enqueue_batch(t, plan->plan, plan->gpu, plan->n_sets, plan->mode, plan->seed, plan->orders, true,
                        ref_makespan_dev, makespans_dev, stats_dev, hist_dev, n_bins, st, nullptr, nullptr);
     hipGraph_t graph = nullptr;
@@ -1548,6 +1585,8 @@ int ko_simulate_rounds(const ko_gpu_model *gpu, const ko_kernel *kernels, int32_
         int rc = check_gpu(gpu);
         if (rc)
             return rc;
+        if (gpu->mem_blocks)
+            return fail(KO_EINVAL, "the round-synchronous model has no memory contention (mem_blocks must be 0)");
         if (!kernels)
             return fail(KO_EINVAL, "kernels must not be NULL");
         if (n < 1 || n > ko::kMaxSet)

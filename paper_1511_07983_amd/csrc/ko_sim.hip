@@ -11,7 +11,8 @@ namespace ko {
 // Persistent kernel: each wavefront repeatedly takes a work item (a chunk of
 // consecutive orders of one set), evaluates its orders one by one, writes the
 // makespans coalesced (64 per store) and one Partial per item.
-template <int S>
+// CONT: resident blocks share the chip's memory throughput (ko_wave.h).
+template <int S, bool CONT>
 __global__ __launch_bounds__(256) void simulate_kernel(SimArgs a, uint32_t gslots)
 {
     extern __shared__ uint32_t lds_ring[];
@@ -42,6 +43,7 @@ __global__ __launch_bounds__(256) void simulate_kernel(SimArgs a, uint32_t gslot
         const int set = lo;
         const uint32_t n = a.sets[set].n;
         const KernelRec *kr = a.krec + a.sets[set].kbase;
+        const uint32_t *sh = CONT ? a.share + a.sets[set].kbase : nullptr;
         const uint64_t first = (item - a.sets[set].item_base) * a.chunk;
         const uint64_t n_orders = a.sets[set].n_orders;
         const uint64_t count = min(a.chunk, n_orders - first);
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(256) void simulate_kernel(SimArgs a, uint32_t gslot
             } else if (a.mode == kModeSampled) {
                 perm = unrank_lanes(sampled_rank(a.seed, (uint32_t)set, first + i, n), n);
             }
-            const int64_t m = simulate_order<S>(a, kr, n, perm, ring, gslots);
+            const int64_t m = simulate_order<S, CONT>(a, kr, sh, n, perm, ring, gslots);
             const uint64_t idx = index0 + i;
             if (m < mn) {
                 mn = m;
@@ -152,7 +154,7 @@ __global__ __launch_bounds__(256) void spill_kernel(SimArgs a, uint32_t gslots)
             if (bad || seen != (1u << n) - 1u)
                 perm = unrank_lanes(0, n);  // the lane kernel raised the status bit
         }
-        const int64_t m = simulate_order<S>(a, a.krec + st.kbase, n, perm, ring, gslots);
+        const int64_t m = simulate_order<S>(a, a.krec + st.kbase, nullptr, n, perm, ring, gslots);
         // every lane stores the same values
         a.spill[r].makespan = m;
         if (a.makespans)
@@ -295,25 +297,33 @@ __global__ void zero_kernel(uint64_t *p, uint64_t count)
         p[i] = 0;
 }
 
-int launch_simulate(const SimArgs &a, int slots_per_lane, uint32_t group_slots, int grid,
-                    void *stream)
+template <bool CONT>
+int launch_simulate_t(const SimArgs &a, int slots_per_lane, uint32_t group_slots, int grid, void *stream)
 {
     const size_t lds = (size_t)4 * group_slots * kWave * sizeof(uint32_t);
     hipStream_t st = (hipStream_t)stream;
     switch (slots_per_lane) {
     case 1:
-        hipLaunchKernelGGL(simulate_kernel<1>, dim3(grid), dim3(256), lds, st, a, group_slots);
+        hipLaunchKernelGGL((simulate_kernel<1, CONT>), dim3(grid), dim3(256), lds, st, a, group_slots);
         break;
     case 2:
-        hipLaunchKernelGGL(simulate_kernel<2>, dim3(grid), dim3(256), lds, st, a, group_slots);
+        hipLaunchKernelGGL((simulate_kernel<2, CONT>), dim3(grid), dim3(256), lds, st, a, group_slots);
         break;
     case 4:
-        hipLaunchKernelGGL(simulate_kernel<4>, dim3(grid), dim3(256), lds, st, a, group_slots);
+        hipLaunchKernelGGL((simulate_kernel<4, CONT>), dim3(grid), dim3(256), lds, st, a, group_slots);
         break;
     default:
         return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
+}
+
+int launch_simulate(const SimArgs &a, int slots_per_lane, uint32_t group_slots, int grid,
+                    void *stream)
+{
+    if (a.share)
+        return launch_simulate_t<true>(a, slots_per_lane, group_slots, grid, stream);
+    return launch_simulate_t<false>(a, slots_per_lane, group_slots, grid, stream);
 }
 
 int launch_spill(const SimArgs &a, int slots_per_lane, uint32_t group_slots, int grid, void *stream)

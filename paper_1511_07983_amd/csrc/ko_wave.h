@@ -34,11 +34,14 @@
 // ever alive: the ring never overflows.
 //
 // Once every block is placed the makespan is the current cycle plus the
-// longest remaining group; the drain is not simulated.
+// longest remaining group; the drain is not simulated (except under memory
+// contention, below).
 
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "ko_device.h"
 #include "ko_orders.h"
@@ -92,6 +95,16 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v)
 {
     for (int o = 32; o >= 1; o >>= 1)
         v = max(v, (uint32_t)__shfl_xor((int)v, o));
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_min64(uint64_t v)
+{
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o);
+        v = min(v, ((uint64_t)hi << 32) | lo);
+    }
     return v;
 }
 
@@ -152,12 +165,30 @@ static __device__ uint32_t next_perm_lanes(uint32_t perm, uint32_t n)
     return (uint32_t)__shfl((int)perm, (int)src);
 }
 
+// Memory contention (CONT = true; Section 4's balance of instructions and
+// memory accesses across the blocks that run together).  Every resident
+// block runs at one common rate: a block of kernel i holds a memory share
+// sh[i] (1/1024 units), and while the resident shares add up to U above
+// mem_cap (1024 times the memory-bound blocks the chip serves at full speed),
+// a cycle brings floor(65536 * mem_cap / U) units of progress instead of
+// 65536.  A block needs dur * 65536 units; it ends at the first whole cycle
+// at which it has them, and all blocks ending at a cycle release before
+// placement resumes.  Because every resident block progresses alike, the
+// blocks of one bulk step still end together: a group keeps its progress
+// left (64 bits) in lane g and its blocks' summed share in lane g of gsh.
+// The drain after the last placement is simulated too, since each release
+// changes the rate.
+
 // Makespan of the order held in `perm` (lane j = kernel at position j).
 // Returns -1 (and sets a status bit) only on an internal inconsistency.
-template <int S>
-__device__ int64_t simulate_order(const SimArgs &a, const KernelRec *__restrict__ kr, uint32_t n,
-                                  uint32_t perm, uint32_t *__restrict__ ring, uint32_t gslots)
+// sh: memory shares of the set's kernels (CONT only).
+template <int S, bool CONT = false>
+__device__ int64_t simulate_order(const SimArgs &a, const KernelRec *__restrict__ kr,
+                                  const uint32_t *__restrict__ sh, uint32_t n, uint32_t perm,
+                                  uint32_t *__restrict__ ring, uint32_t gslots)
 {
+    using Rel = typename std::conditional<CONT, uint64_t, uint32_t>::type;
+    constexpr Rel kFree = ~Rel(0);
     const uint32_t lane = lane_id();
     const uint32_t n_cu = a.n_cu;
     uint32_t fr_reg[S], fr_lds[S], fr_wave[S], fr_blk[S];
@@ -168,8 +199,11 @@ __device__ int64_t simulate_order(const SimArgs &a, const KernelRec *__restrict_
         fr_wave[s] = a.cap_wave;
         fr_blk[s] = (s * kWave + lane < n_cu) ? a.cap_blk : 0u;
     }
-    uint32_t rel = 0xFFFFFFFFu;  // lane g: cycles until group g ends (all ones = free slot)
-    uint32_t gk = 0;             // lane g: kernel of group g
+    // lane g: cycles (CONT: units of progress) until group g ends; all ones = free slot
+    Rel rel = kFree;
+    uint32_t gk = 0;    // lane g: kernel of group g
+    uint32_t gsh = 0;   // CONT, lane g: summed memory share of group g's blocks
+    uint32_t used = 0;  // CONT: summed memory share of every resident block
     uint64_t t = 0;
     uint32_t ptr = 0, pos = 0;
     uint32_t k = uniform(read_lane(perm, 0));
@@ -257,7 +291,7 @@ __device__ int64_t simulate_order(const SimArgs &a, const KernelRec *__restrict_
                 fr_blk[s] -= cnt[s];
                 packed |= cnt[s] << (8 * s);
             }
-            const uint64_t free_slots = ballot(lane < gslots && rel == 0xFFFFFFFFu);
+            const uint64_t free_slots = ballot(lane < gslots && rel == kFree);
             if (free_slots == 0) {
                 flag_status(a.status, kStatusGroupOverflow);
                 return -1;
@@ -265,7 +299,14 @@ __device__ int64_t simulate_order(const SimArgs &a, const KernelRec *__restrict_
             const uint32_t g = (uint32_t)__builtin_ctzll(free_slots);
             ring[g * kWave + lane] = packed;
             const uint32_t dur = kr[k].dur;
-            rel = (lane == g) ? dur : rel;
+            if constexpr (CONT) {
+                const uint32_t share = q * sh[k];
+                rel = (lane == g) ? ((uint64_t)dur << 16) : rel;
+                gsh = (lane == g) ? share : gsh;
+                used += share;
+            } else {
+                rel = (lane == g) ? dur : rel;
+            }
             gk = (lane == g) ? k : gk;
             rem -= q;
             if (rem)
@@ -276,25 +317,46 @@ __device__ int64_t simulate_order(const SimArgs &a, const KernelRec *__restrict_
                 rem = kr[k].tblk;
             }
         }
-        const bool live = rel != 0xFFFFFFFFu;
-        if (pos >= n) {
-            // every block is placed: the makespan is set by the longest group left
-            return (int64_t)(t + uniform(wave_max(live ? rel : 0u)));
+        const bool live = rel != kFree;
+        uint64_t ending;
+        if constexpr (CONT) {
+            // ---- next event: the first whole cycle at which a group is done ----
+            const uint64_t left = uniform64(wave_min64(rel));
+            if (left == kFree) {
+                if (pos >= n)
+                    return (int64_t)t;  // every block placed and ended
+                flag_status(a.status, kStatusGroupOverflow);  // the front block fits nowhere
+                return -1;
+            }
+            const uint64_t rate = (uint64_t)used <= a.mem_cap ? 65536ull : (65536ull * a.mem_cap) / used;
+            const uint64_t dt = (left + rate - 1) / rate;
+            const uint64_t adv = dt * rate;
+            t += dt;
+            const bool done = live && rel <= adv;
+            ending = ballot(done);
+            rel = done ? kFree : (live ? rel - adv : rel);
+        } else {
+            if (pos >= n) {
+                // every block is placed: the makespan is set by the longest group left
+                return (int64_t)(t + uniform(wave_max(live ? rel : 0u)));
+            }
+            // ---- next event: the earliest group end ----
+            const uint32_t dt = uniform(wave_min(rel));
+            if (dt == 0xFFFFFFFFu) {  // nothing running yet the front block does not fit
+                flag_status(a.status, kStatusGroupOverflow);
+                return -1;
+            }
+            t += dt;
+            rel = live ? rel - dt : rel;
+            ending = ballot(live && rel == 0u);
+            rel = (live && rel == 0u) ? 0xFFFFFFFFu : rel;
         }
-        // ---- next event: the earliest group end ----
-        const uint32_t dt = uniform(wave_min(rel));
-        if (dt == 0xFFFFFFFFu) {  // nothing running yet the front block does not fit
-            flag_status(a.status, kStatusGroupOverflow);
-            return -1;
-        }
-        t += dt;
-        rel = live ? rel - dt : rel;
-        uint64_t ending = ballot(live && rel == 0u);
-        rel = (live && rel == 0u) ? 0xFFFFFFFFu : rel;
         while (ending) {
             const uint32_t g = (uint32_t)__builtin_ctzll(ending);
             ending &= ending - 1ull;
             const uint32_t kg = uniform(read_lane(gk, g));
+            if constexpr (CONT)
+                used -= uniform(read_lane(gsh, g));
             const uint32_t u_reg = kr[kg].u_reg, u_lds = kr[kg].u_lds, u_wave = kr[kg].u_wave;
             const uint32_t packed = ring[g * kWave + lane];
 #pragma unroll

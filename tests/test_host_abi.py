@@ -157,6 +157,26 @@ def test_simulate_rejects_bad_arguments_before_device_work():
     assert "duration" in ko.ko_last_error()
 
 
+def test_memory_contention_parameter_checks():
+    """mem_blocks (Section 4's shared memory throughput) is 0 or 1 .. 2^24;
+    Algorithm 1 does not read it, the round-synchronous model refuses it."""
+    gpu = synth.MI355X_MODEL.as_dict()
+    ks = synth.draw_set(0, 0)
+    good = [0, len(ks)]
+    assert _call_simulate(dict(gpu, mem_blocks=-1), ks, good, ko.OrderSpec.all()) == ko.KO_EINVAL
+    assert _call_simulate(dict(gpu, mem_blocks=(1 << 24) + 1), ks, good, ko.OrderSpec.all()) == ko.KO_EINVAL
+    assert "mem_blocks" in ko.ko_last_error()
+    for b in (1, 77, 1 << 24):
+        assert ko.ko_heuristic_order(dict(gpu, mem_blocks=b), ks, with_rounds=True) == \
+            ko.ko_heuristic_order(gpu, ks, with_rounds=True)
+    lib = ko.library_handle()
+    g = ko.gpu_model(dict(gpu, mem_blocks=4))
+    k = ko.kernel_array(ks)
+    dummy = ctypes.c_void_p(0x1000)
+    rc = lib.ko_simulate_rounds(ctypes.byref(g), k.ctypes.data, len(k), None, 0, 10, dummy, None)
+    assert rc == ko.KO_EINVAL and "mem_blocks" in ko.ko_last_error()
+
+
 def test_rank_percentile_and_heuristic_reject_bad_arguments():
     gpu = synth.SMALL_MODEL.as_dict()
     ks = synth.draw_set(0, 0)
