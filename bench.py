@@ -12,10 +12,15 @@ workload (10 kernels, 256-CU MI355X-shaped model, 3,628,800 launch orders):
      histogram (device).
 
 Inputs are synthetic and seeded (SeedSequence([20151123, 1, 0])) and resident
-in HBM before timing starts.  After the timed steps, the metric's second part
-is measured on the n=12 workload (key "surrogate": exact simulations to the
-first order in the exact top 1%, learned scorer against uniform sampling;
---no-surrogate skips it), then the CPU oracle.  Prints one JSON line.
+in HBM before timing starts.  After the timed steps, untimed legs add objects
+to the same line: the round-synchronous model ("rounds") and memory contention
+("contended") on the same set, all 720 orders of the n=6 set on the 16-CU model
+("small"), all orders of the 4096-set batch in one captured graph ("batch";
+--no-legs skips these two), the metric's second part on the n=12 workload
+("surrogate": exact simulations to the first order in the exact top 1%, learned
+scorer against uniform sampling, two training recipes; --no-surrogate skips
+it), then the CPU oracle at every core and at one thread ("cpu_baseline").
+Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -26,6 +31,8 @@ import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -67,37 +74,56 @@ def parse():
     p.add_argument("--no-surrogate", action="store_true",
                    help="skip the surrogate leg (n=12: train, then exact simulations to a top-1%% order)")
     p.add_argument("--surrogate-heldout", type=int, default=8)
+    p.add_argument("--no-legs", action="store_true",
+                   help="skip the n=6 (16-CU) and 4096-set batch legs")
     p.add_argument("--copy-mb", type=int, default=0,
                    help="after timing, copy this many MiB device-to-device once (untimed): a "
                         "plain copy of known size that calibrates HBM byte counters in a profile")
     return p.parse_args()
 
 
-def cpu_baseline(model, ks, seconds: float) -> dict:
-    """The CPU oracle, as it stands, on a bounded prefix of the same orders."""
+def cpu_model_name() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(model, ks, seconds: float, threads: int, lo: int):
+    """Orders/s of the oracle on lexicographic ranks from `lo`, about `seconds` long."""
     import oracle
-    threads = oracle.default_threads()
     pilot = 200 * threads
     t0 = time.perf_counter()
-    oracle.makespans_range(model.as_dict(), ks, 0, pilot, threads)
+    oracle.makespans_range(model.as_dict(), ks, lo, pilot, threads)
     dt = time.perf_counter() - t0
     count = max(pilot, int(pilot * max(seconds - dt, 0.0) / max(dt, 1e-9)))
     t0 = time.perf_counter()
-    oracle.makespans_range(model.as_dict(), ks, pilot, count, threads)
+    oracle.makespans_range(model.as_dict(), ks, lo + pilot, count, threads)
     dt = time.perf_counter() - t0
-    return {"value": count / dt, "unit": "orders/s", "cores": threads, "kind": "oracle",
-            "sample": f"lexicographic ranks {pilot}..{pilot + count - 1} of the same set "
+    return count / dt, lo + pilot, count, dt
+
+
+def cpu_baseline(model, ks, seconds: float) -> dict:
+    """The CPU oracle, as it stands, on bounded samples of the same orders: with
+    every core this process may use, then with one thread."""
+    import oracle
+    threads = oracle.default_threads()
+    rate, lo, count, dt = _oracle_rate(model, ks, 0.6 * seconds, threads, 0)
+    rate1, lo1, count1, dt1 = _oracle_rate(model, ks, 0.4 * seconds, 1, lo + count)
+    return {"value": rate, "unit": "orders/s", "cores": threads, "kind": "oracle",
+            "sample": f"lexicographic ranks {lo}..{lo + count - 1} of the same set "
                       f"({count} orders, {dt:.1f} s, plain C event-driven oracle, -O2, "
-                      f"{threads} threads)"}
+                      f"{threads} threads)",
+            "single_thread": {"value": rate1, "unit": "orders/s", "cores": 1,
+                              "sample": f"ranks {lo1}..{lo1 + count1 - 1} ({count1} orders, {dt1:.1f} s)"},
+            "cpu_model": cpu_model_name()}
 
 
-def surrogate_leg(heldout: int) -> dict:
-    """The metric's second part on the n=12 workload (not in `value`): train the
-    scorer on 2^22 exact samples (8192 sets x 512, rank-quantile targets,
-    65,536 Adam steps), then per held-out set score 10^8 sampled orders,
-    re-simulate the best 10^4 exactly and count exact simulations to the first
-    order in the exact top 1% (full enumeration), against uniform sampling's
-    exact expectation N / hits."""
+def _surrogate_recipe(heldout: int, train_sets: int, per_set: int, quantiles: dict, exact_rate: float) -> dict:
     import json as _json
 
     from paper_1511_07983_amd import surrogate
@@ -106,20 +132,161 @@ def surrogate_leg(heldout: int) -> dict:
     def keep(text, flush=True):
         rec = _json.loads(text)
         lines.append(rec)
-        print(f"[bench] surrogate {rec.get('phase')} done", file=sys.stderr, flush=True)
+        print(f"[bench] surrogate {train_sets}x{per_set} {rec.get('phase')} done", file=sys.stderr, flush=True)
 
     try:
-        surrogate.report(heldout=heldout, out=keep)
+        surrogate.report(heldout=heldout, train_sets=train_sets, per_set=per_set, quantiles=quantiles, out=keep)
     except Exception as exc:  # keep the throughput line even if this leg fails
         return {"error": f"{type(exc).__name__}: {exc}"}
     train = next(l for l in lines if l.get("phase") == "train")
     summary = next(l for l in lines if l.get("phase") == "summary")
     rows = [l for l in lines if l.get("phase") == "heldout"]
-    return {"workload": "surrogate-heldout-n12-mi355x", "heldout_sets": heldout,
+    score_s = float(sum(r["score_rerank_s"] for r in rows) / max(1, len(rows)))
+    random_sims = float(np.mean([r["random_sims_expected"] for r in rows]))
+    return {"train_sets": train["sets"], "samples_per_set": per_set, "train_samples": train["samples"],
             "speedup_geomean": summary["speedup_geomean"], "per_set": [round(r["speedup"], 3) for r in rows],
             "recall_at_1pct_mean": summary["recall_at_1pct_mean"], "mae_cycles_mean": summary["mae_cycles_mean"],
-            "train_s": train["train_s"], "train_samples": train["samples"], "train_sets": train["sets"],
-            "score_rerank_s_per_set": round(float(sum(r["score_rerank_s"] for r in rows) / max(1, len(rows))), 3)}
+            "train_s": train["train_s"], "score_rerank_s_per_set": round(score_s, 3),
+            # what the saved simulations would cost: uniform sampling's expected
+            # exact simulations at the exact simulator's rate on these sets
+            "random_sims_mean": round(random_sims, 1),
+            "random_sims_exact_s": random_sims / exact_rate if exact_rate > 0 else None}
+
+
+def surrogate_leg(heldout: int) -> dict:
+    """The metric's second part on the n=12 workload (not in `value`): train the
+    scorer on 2^22 exact samples, then per held-out set score 10^8 sampled
+    orders, re-simulate the best 10^4 exactly and count exact simulations to the
+    first order in the exact top 1% (full enumeration), against uniform
+    sampling's exact expectation N / hits.  Two training recipes: 512 sets x
+    8192 orders (the workload as specified) and 8192 sets x 512 orders."""
+    import torch
+
+    import paper_1511_07983_amd as ko
+    import synth
+    w = synth.WORKLOADS[13]
+    quantiles = {}
+    # the exact simulator's rate on n=12 orders (sampled, all held-out sets' model)
+    ks = synth.draw_set(13, 0)
+    ms = torch.empty(1 << 22, dtype=torch.int64, device="cuda:0")
+    spec = ko.OrderSpec.sampled([1 << 22], seed=7)
+    ko.ko_simulate_batch(w.model, ks, [0, len(ks)], spec, makespans=ms)
+    ko.ko_sync()
+    t0 = time.perf_counter()
+    ko.ko_simulate_batch(w.model, ks, [0, len(ks)], spec, makespans=ms)
+    ko.ko_sync()
+    exact_rate = (1 << 22) / (time.perf_counter() - t0)
+    del ms
+    out = {"workload": w.name, "heldout_sets": heldout, "exact_orders_per_s_n12": exact_rate,
+           "as_specified_512x8192": _surrogate_recipe(heldout, 512, 8192, quantiles, exact_rate),
+           "wide_8192x512": _surrogate_recipe(heldout, 8192, 512, quantiles, exact_rate)}
+    return out
+
+
+def _event_time(fn, stream, reps: int) -> float:
+    """Median seconds of fn() enqueued on `stream`, HIP events around each call."""
+    import torch
+    fn()
+    stream.synchronize()
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        times.append(a.elapsed_time(b) / 1e3)
+    return float(np.median(times))
+
+
+def small_leg() -> dict:
+    """All 720 orders of the n=6 set on the 16-CU model: one ko_simulate_batch
+    call (host preparation, upload, simulate, per-set statistics) and one
+    replay of a captured graph of a prepared plan, HIP events around each."""
+    import torch
+
+    import paper_1511_07983_amd as ko
+    import synth
+    w = synth.WORKLOADS[0]
+    ks = synth.draw_set(0, 0)
+    N = math.factorial(len(ks))
+    ms = torch.empty(N, dtype=torch.int64, device="cuda:0")
+    st = torch.empty(8, dtype=torch.int64, device="cuda:0")
+    kern = ko.kernel_array(ks)
+    off = [0, len(ks)]
+    spec = ko.OrderSpec.all()
+    stream = torch.cuda.Stream()
+    t_call = _event_time(lambda: ko.ko_simulate_batch(w.model, kern, off, spec, makespans=ms, stats=st,
+                                                      stream=stream), stream, 50)
+    ko.ko_sync(stream)
+    plan = ko.Plan(w.model, kern, off, spec)
+    graph = plan.capture(stream=stream, makespans=ms, stats=st)
+    t_graph = _event_time(lambda: graph.launch(stream), stream, 50)
+    plan.status(stream)
+    graph.close()
+    plan.close()
+    ops = OPS_PER_BLOCK * int(ks["n_tblk"].sum()) * N
+    print("[bench] small done", file=sys.stderr, flush=True)
+    return {"workload": w.name, "orders": N, "ms_per_call": 1e3 * t_call, "ms_per_graph_replay": 1e3 * t_graph,
+            "orders_per_s": N / t_graph, "achieved": ops / t_graph / 1e12,
+            "frac": ops / t_graph / 1e12 / ALU_PEAK_TOPS,
+            "note": "latency-bound: 720 orders, one wavefront each, on a 1,024-SIMD chip"}
+
+
+def batch_leg() -> dict:
+    """All orders of all 4096 sets of the batch workload (n = 4..9) in one
+    captured graph of a planned launch, autotuned (engine, orders per work
+    item, workgroups per CU) on 128 of the sets."""
+    import json as _json
+
+    import synth
+    from paper_1511_07983_amd import batch
+    recs = []
+    try:
+        batch.report(workload=2, sets=4096, tune_sets=128, reps=5, tune=True,
+                     out=lambda t, **kw: recs.append(_json.loads(t)))
+    except Exception as exc:
+        return {"error": f"{type(exc).__name__}: {exc}"}
+    rec = recs[-1]
+    ops = 0
+    for s in range(4096):
+        ks = synth.draw_set(2, s)
+        ops += OPS_PER_BLOCK * int(ks["n_tblk"].sum()) * math.factorial(len(ks))
+    t = rec["graph_replay_s"]
+    print("[bench] batch done", file=sys.stderr, flush=True)
+    return {"workload": rec["workload"], "sets": rec["sets"], "orders": rec["orders"], "graph_replay_s": t,
+            "orders_per_s": rec["orders_per_s"], "achieved": ops / t / 1e12, "frac": ops / t / 1e12 / ALU_PEAK_TOPS,
+            "engine": rec["engine"], "config": rec["config"], "work_items": rec["work_items"]}
+
+
+def contended_leg(model, kernels, off, N, ops_per_order, mem_blocks: int = 256) -> dict:
+    """All orders of the same set when resident blocks share the chip's memory
+    throughput (mem_blocks = one memory-bound block per CU at full speed):
+    the wave engine's contended mode, HIP events around the simulate kernel."""
+    import torch
+
+    import paper_1511_07983_amd as ko
+    gpu = dict(model.as_dict(), mem_blocks=mem_blocks)
+    ms = torch.empty(N, dtype=torch.int64, device="cuda:0")
+    st = torch.empty(8, dtype=torch.int64, device="cuda:0")
+    spec = ko.OrderSpec.all()
+    ko.ko_simulate_batch(gpu, kernels, off, spec, makespans=ms, stats=st)
+    ko.ko_sync()
+    ko.ko_set_kernel_timing(True)
+    t = []
+    for _ in range(3):
+        ko.ko_simulate_batch(gpu, kernels, off, spec, makespans=ms, stats=st)
+        t.append(ko.ko_last_kernel_ms() / 1e3)
+    ko.ko_set_kernel_timing(False)
+    ko.ko_sync()
+    rec = ko.stats_records(st)[0]
+    k = float(np.median(t))
+    print("[bench] contended done", file=sys.stderr, flush=True)
+    return {"kernel": "ko::simulate_kernel<4, true>", "mem_blocks": mem_blocks, "orders": N,
+            "kernel_ms": 1e3 * k, "orders_per_s": N / k, "achieved": ops_per_order * N / k / 1e12,
+            "frac": ops_per_order * N / k / 1e12 / ALU_PEAK_TOPS,
+            "min_makespan": int(rec["min_makespan"]), "max_makespan": int(rec["max_makespan"])}
 
 
 def rounds_leg(ops_per_order: int):
@@ -147,7 +314,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1511_07983_amd as ko
@@ -250,6 +416,10 @@ def main():
                       "min_makespan": int(rec["min_makespan"]), "max_makespan": int(rec["max_makespan"])},
     }
     out["rounds"] = rounds_leg(ops_per_order)
+    out["contended"] = contended_leg(w.model, kernels, off, N, ops_per_order)
+    if not args.no_legs:
+        out["small"] = small_leg()
+        out["batch"] = batch_leg()
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(args.surrogate_heldout)
     if args.cpu_seconds > 0:

@@ -423,6 +423,22 @@ int ko_kth_smallest_i64(const int64_t *v_dev, uint64_t count, uint64_t k, int64_
 int ko_sort_i64(const int64_t *v_dev, uint64_t count, int64_t *sorted_out_dev, uint64_t *index_out_dev,
                 void *hip_stream);
 
+/* ko_stats_i64 — statistics of an int64 array already in device memory (the
+ * makespans another call left there, e.g. ko_simulate_rounds): Table 3's
+ * optimal and worst with their smallest indices, and the counts behind a
+ * percentile rank, into one ko_set_stats: min/max makespan, argmin/argmax
+ * (index in v; ties to the smallest), n_less/n_equal/n_greater against
+ * *ref_dev (0 when ref_dev is NULL), n_orders = count.  An empty array gives
+ * min INT64_MAX, max INT64_MIN, argmin = argmax = 0.
+ *   v_dev      device int64[count]; count <= 2^40
+ *   ref_dev    device int64[1] or NULL
+ *   stats_dev  device ko_set_stats[1]
+ * Asynchronous on hip_stream (a reduction on the device; the partials live in
+ * the library's workspace).  Errors: KO_EINVAL (NULL stats_dev, NULL v_dev
+ * with count > 0), KO_ERANGE (count), KO_ENOMEM, KO_EHIP. */
+int ko_stats_i64(const int64_t *v_dev, uint64_t count, const int64_t *ref_dev, ko_set_stats *stats_dev,
+                 void *hip_stream);
+
 /* ------------------------------------------------------------------ hardware
  * Validation of the model on the GPU itself (not part of the model): each
  * kernel of a set becomes a synthetic HIP kernel with its grid (n_tblk

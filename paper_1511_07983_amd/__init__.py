@@ -43,7 +43,8 @@ EXPORTED = ("ko_heuristic_order", "ko_count_orders", "ko_simulate_batch", "ko_si
             "ko_sync", "ko_shutdown", "ko_plan_create", "ko_plan_info", "ko_plan_launch", "ko_plan_status",
             "ko_plan_engine",
             "ko_plan_destroy", "ko_graph_capture", "ko_graph_launch", "ko_graph_destroy",
-            "ko_sample_orders", "ko_topk_f32", "ko_kth_smallest_i64", "ko_sort_i64", "ko_simulate_rounds",
+            "ko_sample_orders", "ko_topk_f32", "ko_kth_smallest_i64", "ko_sort_i64", "ko_stats_i64",
+            "ko_simulate_rounds",
             "ko_set_kernel_timing", "ko_last_kernel_ms", "ko_hw_vgprs", "ko_hw_time_orders",
             "ko_hw_last_error", "ko_last_error")
 
@@ -170,6 +171,9 @@ def _L():
         lib.ko_sort_i64.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p]
         lib.ko_sort_i64.restype = ctypes.c_int
+        lib.ko_stats_i64.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+        lib.ko_stats_i64.restype = ctypes.c_int
         lib.ko_hw_vgprs.argtypes = [ctypes.c_int32, _i32p]
         lib.ko_hw_vgprs.restype = ctypes.c_int
         lib.ko_hw_time_orders.argtypes = [ctypes.c_void_p, ctypes.c_int32, _i32p, ctypes.c_int32, ctypes.c_int32,
@@ -559,6 +563,21 @@ def ko_sort_i64(v, *, sorted_out=None, index_out=None, want_index: bool = True, 
     _check(_L().ko_sort_i64(_dev_ptr(v, torch.int64, n, "v"), n, _dev_ptr(sorted_out, torch.int64, n, "sorted_out"),
                             _dev_ptr(index_out, torch.int64, n, "index_out"), _stream_handle(stream)))
     return sorted_out, index_out
+
+
+def ko_stats_i64(v, *, ref=None, stats=None, stream=None):
+    """Device statistics of the int64 device tensor v (asynchronous): min/max
+    with smallest indices and the counts against ref (an int64[1] device tensor
+    or None), into stats (int64[8] device tensor, created if None; read it
+    with stats_records).  Returns stats."""
+    import torch
+    n = v.numel()
+    if stats is None:
+        stats = torch.empty(8, dtype=torch.int64, device=v.device)
+    _check(_L().ko_stats_i64(_dev_ptr(v, torch.int64, n, "v") if n else None, n,
+                             _dev_ptr(ref, torch.int64, 1, "ref"), _dev_ptr(stats, torch.int64, 8, "stats"),
+                             _stream_handle(stream)))
+    return stats
 
 
 def ranking_curve(makespans, stream=None):

@@ -2,11 +2,13 @@
 
 A batch of thousands of kernel sets of uneven size (n = 4..9, so 24 to 362,880
 orders each) runs as one persistent launch fed by a device work queue of
-(set, chunk of ranks) items (ko_plan_*).  The launch configuration (orders per
-work item, persistent workgroups per CU) is picked by `autotune`, which times
-each candidate with HIP events on the caller's stream, checks that every
-candidate produces identical makespans, and caches its choice in a JSON file
-keyed by the device, the model and the batch's shape.
+(set, chunk of ranks) items (ko_plan_*).  The launch configuration (the
+engine, i.e. how CU state is laid out: one wavefront per order with lanes
+owning CUs, or one lane per order with CU states as runs; orders per work
+item; persistent workgroups per CU) is picked by `autotune`, which times each
+candidate with HIP events on the caller's stream, checks that every candidate
+produces identical makespans, and caches its choice in a JSON file keyed by
+the device, the model and the batch's shape.
 
 `percentiles` is the batch form of Table 3's "percentile rank": Algorithm 1's
 order of every set (host), its exact makespan (one EXPLICIT plan launch for
@@ -24,10 +26,14 @@ import time
 
 import numpy as np
 
-from . import OrderSpec, Plan, gpu_model, kernel_array, ko_heuristic_order, stats_records
+from . import (ENGINE_LANES, ENGINE_WAVE, KO_EINVAL, KoError, OrderSpec, Plan, gpu_model, kernel_array,
+               ko_heuristic_order, stats_records)
 
-CHUNKS = (5, 6, 8, 10)      # orders per work item: 32, 64, 256, 1024 (lane engine: 64-256)
-WG_PER_CU = (4, 8, 16)
+# candidate orders per work item (log2) and persistent workgroups per CU, per engine
+SWEEP = {ENGINE_WAVE: ((5, 6, 8, 10), (4, 8, 16)),   # 32 .. 1024 orders, one wavefront each
+         ENGINE_LANES: ((6, 7, 8), (4, 8, 16))}      # 1 .. 4 orders per lane
+CHUNKS = SWEEP[ENGINE_WAVE][0]
+WG_PER_CU = SWEEP[ENGINE_WAVE][1]
 
 
 def _cache_path():
@@ -43,7 +49,8 @@ def batch_key(gpu, kernels, set_offsets, spec: OrderSpec) -> str:
     sizes = np.diff(np.asarray(set_offsets, dtype=np.int64))
     hist = np.bincount(sizes, minlength=21)
     text = json.dumps({"device": torch.cuda.get_device_name(), "model": [g.n_cu, g.wave_size, g.wave_cu, g.blk_cu,
-                                                                          g.reg_cu, g.lds_cu, g.rb_milli],
+                                                                          g.reg_cu, g.lds_cu, g.rb_milli,
+                                                                          g.mem_blocks],
                        "mode": spec.mode, "sizes": hist.tolist()}, sort_keys=True)
     return hashlib.sha256(text.encode()).hexdigest()[:24]
 
@@ -65,10 +72,22 @@ def _time_plan(plan: Plan, reps: int, out) -> float:
     return float(np.median(times))
 
 
+def _candidates(engines, chunks, wgs):
+    for e in engines:
+        c_list = chunks if chunks is not None else SWEEP[e][0]
+        w_list = wgs if wgs is not None else SWEEP[e][1]
+        for c in c_list:
+            for w in w_list:
+                yield e, c, w
+
+
 def autotune(gpu, kernels, set_offsets, spec: OrderSpec, *, reps: int = 3, use_cache: bool = True,
-             chunks=CHUNKS, wgs=WG_PER_CU, log=None):
-    """Best (chunk_log2, wg_per_cu) for this batch; every candidate must give
-    the same makespans bit for bit.  Returns (config dict, sweep rows)."""
+             engines=(ENGINE_WAVE, ENGINE_LANES), chunks=None, wgs=None, log=None):
+    """Best (engine, chunk_log2, wg_per_cu) for this batch; every candidate must
+    give the same makespans bit for bit.  An engine that does not apply to the
+    batch (the lane engine past 16 kernels or under memory contention) is left
+    out.  `chunks`/`wgs` override the per-engine candidate lists.  Returns
+    (config dict, sweep rows)."""
     import torch
     key = batch_key(gpu, kernels, set_offsets, spec)
     path = _cache_path()
@@ -81,23 +100,27 @@ def autotune(gpu, kernels, set_offsets, spec: OrderSpec, *, reps: int = 3, use_c
     ref = None
     rows = []
     total = None
-    for c in chunks:
-        for w in wgs:
-            plan = Plan(gpu, kernels, set_offsets, spec, chunk_log2=c, wg_per_cu=w)
-            total = plan.total_orders
-            out = torch.empty(max(total, 1), dtype=torch.int64, device="cuda:0")
-            ms = _time_plan(plan, reps, out)
-            if ref is None:
-                ref = out.clone()
-            elif not torch.equal(out, ref):
-                raise RuntimeError(f"configuration chunk=2^{c} wg={w} changed the makespans")
-            rows.append({"chunk_log2": c, "wg_per_cu": w, "ms": ms, "work_items": plan.work_items})
-            if log:
-                log(rows[-1])
-            plan.close()
+    for e, c, w in _candidates(engines, chunks, wgs):
+        try:
+            plan = Plan(gpu, kernels, set_offsets, spec, chunk_log2=c, wg_per_cu=w, engine=e)
+        except KoError as exc:
+            if exc.code == KO_EINVAL and e == ENGINE_LANES:
+                continue  # the lane engine does not take this batch
+            raise
+        total = plan.total_orders
+        out = torch.empty(max(total, 1), dtype=torch.int64, device="cuda:0")
+        ms = _time_plan(plan, reps, out)
+        if ref is None:
+            ref = out.clone()
+        elif not torch.equal(out, ref):
+            raise RuntimeError(f"configuration engine={e} chunk=2^{c} wg={w} changed the makespans")
+        rows.append({"engine": e, "chunk_log2": c, "wg_per_cu": w, "ms": ms, "work_items": plan.work_items})
+        if log:
+            log(rows[-1])
+        plan.close()
     best = min(rows, key=lambda r: r["ms"])
-    cfg = {"chunk_log2": best["chunk_log2"], "wg_per_cu": best["wg_per_cu"], "ms": best["ms"],
-           "orders": int(total), "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
+    cfg = {"engine": best["engine"], "chunk_log2": best["chunk_log2"], "wg_per_cu": best["wg_per_cu"],
+           "ms": best["ms"], "orders": int(total), "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
     if use_cache:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         cache[key] = cfg
@@ -129,7 +152,7 @@ def percentiles(gpu, sets, *, config=None, n_bins: int = 0, want_makespans: bool
     p1.launch(makespans=ref)
     p1.status()
     p2 = Plan(gpu, kernels, offsets, OrderSpec.all(), chunk_log2=cfg.get("chunk_log2", 0),
-              wg_per_cu=cfg.get("wg_per_cu", 0))
+              wg_per_cu=cfg.get("wg_per_cu", 0), engine=cfg.get("engine", 0))
     st = torch.empty(8 * S, dtype=torch.int64, device=dev)
     ms = torch.empty(max(p2.total_orders, 1), dtype=torch.int64, device=dev) if (want_makespans or n_bins) else None
     hist = torch.empty(S * n_bins, dtype=torch.int64, device=dev) if n_bins else None
@@ -166,10 +189,10 @@ def report(*, workload: int = 2, sets: int = 4096, tune_sets: int = 512, reps: i
         k_t, o_t = concat_sets(all_sets[:tune_sets])
         cfg, rows = autotune(w.model, k_t, o_t, OrderSpec.all(), reps=2, use_cache=False)
     else:
-        cfg, rows = {"chunk_log2": 0, "wg_per_cu": 0}, []
+        cfg, rows = {"engine": 0, "chunk_log2": 0, "wg_per_cu": 0}, []
     kernels, offsets = concat_sets(all_sets)
     plan = Plan(w.model, kernels, offsets, OrderSpec.all(), chunk_log2=cfg["chunk_log2"],
-                wg_per_cu=cfg["wg_per_cu"])
+                wg_per_cu=cfg["wg_per_cu"], engine=cfg.get("engine", 0))
     st = torch.empty(8 * sets, dtype=torch.int64, device="cuda:0")
     ms = torch.empty(plan.total_orders, dtype=torch.int64, device="cuda:0")
     stream = torch.cuda.Stream()
@@ -192,7 +215,8 @@ def report(*, workload: int = 2, sets: int = 4096, tune_sets: int = 512, reps: i
     out(json.dumps({"workload": w.name, "sets": sets, "orders": int(plan.total_orders),
                     "engine": {"engine": engine, "lane_entries": entries, "spilled_orders": spilled,
                                "items_re_run": handed},
-                    "config": {"chunk_log2": cfg["chunk_log2"], "wg_per_cu": cfg["wg_per_cu"]},
+                    "config": {"engine": cfg.get("engine", 0), "chunk_log2": cfg["chunk_log2"],
+                               "wg_per_cu": cfg["wg_per_cu"]},
                     "tuning": rows, "graph_replay_s": t, "orders_per_s": plan.total_orders / t,
                     "work_items": int(plan.work_items)}), flush=True)
     graph.close()

@@ -417,6 +417,9 @@ struct Workspace {
     // radix sort: two (key, index) buffers and the digit counts
     void *sort_buf = nullptr;
     size_t sort_cap = 0;
+    // ko_stats_i64: one Partial per workgroup
+    ko::Partial *stat_parts = nullptr;
+    size_t stat_parts_cap = 0;
     // optional timing of the simulate kernel (ko_set_kernel_timing)
     hipEvent_t sim_begin = nullptr, sim_end = nullptr;
     bool timing = false;
@@ -514,6 +517,7 @@ void release_workspace(Workspace &w)
     (void)hipFree(w.sel_bins);
     (void)hipFree(w.sel_cand);
     (void)hipFree(w.sort_buf);
+    (void)hipFree(w.stat_parts);
     (void)hipHostFree(w.sel_host);
     (void)hipEventDestroy(w.sim_begin);
     (void)hipEventDestroy(w.sim_end);
@@ -742,9 +746,12 @@ int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *
         chunk = pow2_at_least(std::max<uint64_t>(1, plan->total / (waves * 4)));
         chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, 64), 256);
     } else if (chunk == 0) {
+        // about 8 items per persistent wave; a batch smaller than that gets one
+        // order per item, so that every order has a wave of its own (one order
+        // is a long serial chain on one wave: tens of microseconds)
         const uint64_t waves = (uint64_t)plan->grid * 4;
         chunk = pow2_at_least(std::max<uint64_t>(1, plan->total / (waves * 8)));
-        chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, 16), 8192);
+        chunk = std::min<uint64_t>(chunk, 8192);
     }
     if (plan->total / chunk > max_items)
         chunk = pow2_at_least((plan->total + max_items - 1) / max_items);
@@ -1804,6 +1811,38 @@ int ko_sort_i64(const int64_t *v_dev, uint64_t count, int64_t *sorted_out_dev, u
     KO_HIP(hipEventRecord(w->done, stream), "hipEventRecord");
     KO_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
     return KO_OK;
+}
+
+int ko_stats_i64(const int64_t *v_dev, uint64_t count, const int64_t *ref_dev, ko_set_stats *stats_dev,
+                 void *hip_stream)
+{
+    try {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        if (!stats_dev)
+            return fail(KO_EINVAL, "stats_dev must not be NULL");
+        if (count && !v_dev)
+            return fail(KO_EINVAL, "v_dev must not be NULL when count > 0");
+        if (count > (uint64_t(1) << 40))
+            return fail(KO_ERANGE, "count above 2^40");
+        Workspace *w = nullptr;
+        int rc = get_workspace(&w);
+        if (rc)
+            return rc;
+        // four workgroups per CU, never more than one per 256 values
+        const uint32_t parts =
+            (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((count + 255) / 256, (uint64_t)w->cu_count * 4));
+        if ((rc = grow_device(w->done, (void **)&w->stat_parts, &w->stat_parts_cap, parts * sizeof(ko::Partial))))
+            return rc;
+        hipStream_t stream = (hipStream_t)hip_stream;
+        KO_HIP(hipStreamWaitEvent(stream, w->done, 0), "hipStreamWaitEvent");
+        const int e = ko::launch_stats_i64(v_dev, count, ref_dev, w->stat_parts, parts, stats_dev, stream);
+        if (e)
+            return hip_fail((hipError_t)e, "statistics launch");
+        KO_HIP(hipEventRecord(w->done, stream), "hipEventRecord");
+        return KO_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(KO_ENOMEM, "host allocation failed");
+    }
 }
 
 int ko_set_kernel_timing(int32_t enable)

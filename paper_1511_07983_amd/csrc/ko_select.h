@@ -4,6 +4,8 @@
 
 #include <stdint.h>
 
+#include "ko_device.h"
+
 namespace ko {
 
 int launch_sample_orders(uint32_t n, uint32_t set, uint64_t seed, uint64_t first,
@@ -26,5 +28,10 @@ int launch_sort_i64(const int64_t *v, uint64_t count, int64_t vmin, uint32_t pas
                     uint32_t *idx_a, uint64_t *keys_b, uint32_t *idx_b, uint32_t *counts, int64_t *sorted,
                     uint64_t *index, void *stream);
 int launch_unpack_topk(const uint64_t *keys, uint32_t k, int64_t *idx, float *val, void *stream);
+// Statistics of v[0, count) (min/max with the smallest index on ties, counts
+// against *ref if ref is not null) into `stats` (one ko_set_stats): n_parts
+// workgroups write Partials to `parts`, one more workgroup combines them.
+int launch_stats_i64(const int64_t *v, uint64_t count, const int64_t *ref, Partial *parts, uint32_t n_parts,
+                     void *stats, void *stream);
 
 }  // namespace ko

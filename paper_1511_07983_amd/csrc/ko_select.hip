@@ -196,6 +196,102 @@ __global__ __launch_bounds__(256) void minmax_i64_kernel(const int64_t *v, uint6
     }
 }
 
+// ------------------------------------------------------------------ statistics
+
+// Combine (min, argmin, max, argmax, counts) of two parts; ties go to the
+// smaller index.
+__device__ __forceinline__ void stats_merge(Partial &a, const Partial &b)
+{
+    if (b.min_ms < a.min_ms || (b.min_ms == a.min_ms && b.argmin < a.argmin)) {
+        a.min_ms = b.min_ms;
+        a.argmin = b.argmin;
+    }
+    if (b.max_ms > a.max_ms || (b.max_ms == a.max_ms && b.argmax < a.argmax)) {
+        a.max_ms = b.max_ms;
+        a.argmax = b.argmax;
+    }
+    a.n_less += b.n_less;
+    a.n_equal += b.n_equal;
+    a.n_greater += b.n_greater;
+    a.count += b.count;
+}
+
+__device__ __forceinline__ Partial stats_empty()
+{
+    Partial p;
+    p.min_ms = INT64_MAX;
+    p.max_ms = INT64_MIN;
+    p.argmin = ~0ull;
+    p.argmax = ~0ull;
+    p.n_less = p.n_equal = p.n_greater = p.count = 0;
+    return p;
+}
+
+// Tree over the workgroup's 256 parts in LDS; thread 0 ends with the total.
+__device__ __forceinline__ Partial stats_block(Partial mine)
+{
+    __shared__ Partial part[256];
+    part[threadIdx.x] = mine;
+    __syncthreads();
+    for (uint32_t h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            Partial a = part[threadIdx.x];
+            stats_merge(a, part[threadIdx.x + h]);
+            part[threadIdx.x] = a;
+        }
+        __syncthreads();
+    }
+    return part[0];
+}
+
+// One Partial per workgroup over a grid-stride share of v[0, count), counts
+// against *ref when ref is not null.
+__global__ __launch_bounds__(256) void stats_partial_kernel(const int64_t *v, uint64_t count, const int64_t *ref,
+                                                            Partial *parts)
+{
+    Partial p = stats_empty();
+    const bool has_ref = ref != nullptr;
+    const int64_t r = has_ref ? *ref : 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const int64_t m = v[i];
+        // indices only grow along a thread's share: strict comparisons keep the first
+        if (m < p.min_ms) {
+            p.min_ms = m;
+            p.argmin = i;
+        }
+        if (m > p.max_ms) {
+            p.max_ms = m;
+            p.argmax = i;
+        }
+        if (has_ref) {
+            p.n_less += (m < r) ? 1u : 0u;
+            p.n_equal += (m == r) ? 1u : 0u;
+            p.n_greater += (m > r) ? 1u : 0u;
+        }
+        p.count++;
+    }
+    const Partial t = stats_block(p);
+    if (threadIdx.x == 0)
+        parts[blockIdx.x] = t;
+}
+
+// One workgroup: the total of n_parts Partials, written as ko_set_stats
+// (the same 64-byte layout; an empty array gives min INT64_MAX, max
+// INT64_MIN, indices 0).
+__global__ __launch_bounds__(256) void stats_final_kernel(const Partial *parts, uint32_t n_parts, Partial *out)
+{
+    Partial p = stats_empty();
+    for (uint32_t i = threadIdx.x; i < n_parts; i += blockDim.x)
+        stats_merge(p, parts[i]);
+    Partial t = stats_block(p);
+    if (threadIdx.x == 0) {
+        if (t.count == 0)
+            t.argmin = t.argmax = 0;
+        *out = t;
+    }
+}
+
 // counts[d * n_tiles + t] = elements of tile t whose digit is d
 __global__ __launch_bounds__(256) void sort_count_kernel(const uint64_t *keys, uint64_t count, uint32_t shift,
                                                          uint32_t n_tiles, uint32_t *counts)
@@ -378,6 +474,16 @@ int launch_minmax_i64(const int64_t *v, uint64_t count, unsigned long long *mm, 
 {
     hipLaunchKernelGGL(minmax_i64_kernel, dim3(blocks_for(count, (uint64_t)grid_cap)), dim3(256), 0,
                        (hipStream_t)stream, v, count, mm);
+    return (int)hipGetLastError();
+}
+
+int launch_stats_i64(const int64_t *v, uint64_t count, const int64_t *ref, Partial *parts, uint32_t n_parts,
+                     void *stats, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(stats_partial_kernel, dim3(n_parts), dim3(256), 0, st, v, count, ref, parts);
+    hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(256), 0, st, parts, n_parts,
+                       reinterpret_cast<Partial *>(stats));
     return (int)hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ def report(out=print):
     import numpy as np
     import torch
 
-    from . import batch, ko_simulate_rounds
+    from . import batch, ko_simulate_rounds, ko_stats_i64, stats_records
     names = list(paper_sets.EXPERIMENTS)
     sets = [paper_sets.EXPERIMENTS[k] for k in names]
     res = batch.percentiles(paper_sets.MODEL, sets)
@@ -56,12 +56,14 @@ def report(out=print):
         # the same orders under the round-synchronous reading of the execution rounds
         n = len(sets[i])
         perms = np.array(list(itertools.permutations(range(n))), dtype=np.uint8)
-        rms = ko_simulate_rounds(paper_sets.MODEL.as_dict(), sets[i], torch.from_numpy(perms).cuda()).cpu().numpy()
+        rms = ko_simulate_rounds(paper_sets.MODEL.as_dict(), sets[i], torch.from_numpy(perms).cuda())
         h = torch.tensor([row["algorithm_order"]], dtype=torch.uint8).cuda()
-        h_ms = int(ko_simulate_rounds(paper_sets.MODEL.as_dict(), sets[i], h).cpu()[0])
-        row["rounds"] = {"best_cycles": int(rms.min()), "worst_cycles": int(rms.max()),
-                         "algorithm_cycles": h_ms,
-                         "percentile_inclusive": round(100.0 * float((rms >= h_ms).mean()), 2)}
+        h_ms = ko_simulate_rounds(paper_sets.MODEL.as_dict(), sets[i], h)
+        st = stats_records(ko_stats_i64(rms, ref=h_ms))[0]
+        row["rounds"] = {"best_cycles": int(st["min_makespan"]), "worst_cycles": int(st["max_makespan"]),
+                         "algorithm_cycles": int(h_ms.cpu()[0]),
+                         "percentile_inclusive": round(100.0 * float(st["n_equal"] + st["n_greater"])
+                                                       / len(perms), 2)}
         rows.append(row)
         out(json.dumps(row), flush=True)
     return rows

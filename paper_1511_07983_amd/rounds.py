@@ -4,8 +4,10 @@ Times ko_simulate_rounds on the n=10 set of the all-orders workload (MI355X-shap
 model), over the same seeded sampled orders that ko_simulate_batch evaluates in
 sampled mode or (--all) over all 10! orders unranked on the device, and reports
 Algorithm 1's order under this model: its makespan and its percentile among the
-evaluated orders (the share of them with a makespan at least as long).  The makespans come from the GPU; the percentile
-and the summary are host arithmetic on the copied-back values.
+evaluated orders (the share of them with a makespan at least as long).  The
+makespans, the best and worst order and the counts behind the percentile are
+computed on the device (ko_simulate_rounds, then ko_stats_i64); only the
+64-byte statistics record comes back.
 
     python -m paper_1511_07983_amd.rounds [--orders N | --all] [--reps R]
 """
@@ -26,7 +28,7 @@ def report(n_orders: int = 1 << 22, reps: int = 5, all_orders: bool = False, out
 
     import synth
 
-    from . import ko_heuristic_order, ko_sample_orders, ko_simulate_rounds
+    from . import ko_heuristic_order, ko_sample_orders, ko_simulate_rounds, ko_stats_i64, stats_records
 
     wl = synth.WORKLOADS[1]
     ks = synth.draw_set(1, 0)
@@ -51,12 +53,13 @@ def report(n_orders: int = 1 << 22, reps: int = 5, all_orders: bool = False, out
     stop.record()
     torch.cuda.synchronize()
     ms_per_launch = start.elapsed_time(stop) / reps
-    sampled = ms.cpu().numpy()
-    if (sampled < 0).any():
-        raise RuntimeError("negative round makespan from the device")
     heur = ko_heuristic_order(gpu, ks)
     h = torch.tensor([heur], dtype=torch.uint8, device=dev)
-    h_ms = int(ko_simulate_rounds(gpu, ks, h).cpu()[0])
+    h_ms = ko_simulate_rounds(gpu, ks, h)
+    st = stats_records(ko_stats_i64(ms, ref=h_ms))[0]
+    if st["min_makespan"] < 0:
+        raise RuntimeError("negative round makespan from the device")
+    h_ms = int(h_ms.cpu()[0])
     rec = {
         "model": "round-synchronous execution rounds",
         "workload": wl.name,
@@ -65,11 +68,11 @@ def report(n_orders: int = 1 << 22, reps: int = 5, all_orders: bool = False, out
         "orders_kind": "all, by lexicographic rank" if all_orders else "sampled",
         "ms_per_launch": round(ms_per_launch, 3),
         "orders_per_s": round(n_orders / (ms_per_launch / 1e3)),
-        "best": int(sampled.min()),
-        "worst": int(sampled.max()),
+        "best": int(st["min_makespan"]),
+        "worst": int(st["max_makespan"]),
         "heuristic_order": heur,
         "heuristic_makespan": h_ms,
-        "heuristic_percentile": round(100.0 * float((sampled >= h_ms).mean()), 2),
+        "heuristic_percentile": round(100.0 * float(st["n_equal"] + st["n_greater"]) / n_orders, 2),
     }
     out(json.dumps(rec))
     return rec

@@ -371,10 +371,12 @@ def _init_params(seed: int) -> np.ndarray:
 def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: int = 8192,
            per_set: int = 512, heldout: int = 8, n_score: int = 100_000_000, top_k: int = 10_000,
            steps: int = 65536, batch: int = 4096, lr: float = 1e-3, seed: int = 2015, target: str = "quantile",
-           out=print):
+           quantiles: dict | None = None, out=print):
     """Train on exact samples, then per held-out set: exact top-1% threshold by
     full enumeration, scoring of `n_score` sampled orders, exact re-simulation
-    of the `top_k` best.  Prints one JSON line per held-out set and a summary."""
+    of the `top_k` best.  Prints one JSON line per held-out set and a summary.
+    `quantiles` (held-out set index -> Quantile), when given, keeps the
+    thresholds of earlier calls on the same held-out sets and is filled in."""
     import json
     import time
 
@@ -403,7 +405,12 @@ def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: i
     rows = []
     for s, ks in enumerate(held):
         t0 = time.perf_counter()
-        q = top_quantile(model, ks, 0.01)
+        if quantiles is not None and s in quantiles:
+            q = quantiles[s]
+        else:
+            q = top_quantile(model, ks, 0.01)
+            if quantiles is not None:
+                quantiles[s] = q
         torch.cuda.synchronize()
         t_enum = time.perf_counter() - t0
         t0 = time.perf_counter()

@@ -156,11 +156,19 @@ def test_autotuner_configs_agree_and_cache(tmp_path, monkeypatch):
     monkeypatch.setenv("KO_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     sets = batch_sets(256, 1000)
     kernels, offsets = kb.concat_sets(sets)
-    cfg, rows = kb.autotune(MODEL, kernels, offsets, ko.OrderSpec.all(), reps=2, chunks=(5, 9), wgs=(4, 8),
+    cfg, rows = kb.autotune(MODEL, kernels, offsets, ko.OrderSpec.all(), reps=2, chunks=(6, 8), wgs=(4, 8),
                             log=lambda r: say("tune", r))
-    assert len(rows) == 4 and cfg["chunk_log2"] in (5, 9) and cfg["wg_per_cu"] in (4, 8)
+    # both engines (the CU-state layouts) are swept, and every candidate agreed
+    assert len(rows) == 8 and {r["engine"] for r in rows} == {ko.ENGINE_WAVE, ko.ENGINE_LANES}
+    assert cfg["chunk_log2"] in (6, 8) and cfg["wg_per_cu"] in (4, 8)
+    assert cfg["engine"] in (ko.ENGINE_WAVE, ko.ENGINE_LANES)
     again, rows2 = kb.autotune(MODEL, kernels, offsets, ko.OrderSpec.all())
     assert again == cfg and rows2 == []
+    # under memory contention only the wave engine applies
+    cont = dict(MODEL.as_dict(), mem_blocks=64)
+    monkeypatch.setenv("KO_AUTOTUNE_CACHE", str(tmp_path / "tune2.json"))
+    cfg2, rows2 = kb.autotune(cont, kernels, offsets, ko.OrderSpec.all(), reps=1, chunks=(8,), wgs=(8,))
+    assert [r["engine"] for r in rows2] == [ko.ENGINE_WAVE] and cfg2["engine"] == ko.ENGINE_WAVE
 
 
 def test_percentiles_of_the_4096_set_workload():

@@ -8,7 +8,11 @@ a BF16 rounding boundary, by one BF16 ulp (2^-8 relative) of that element.  Its
 effect on y is bounded by 2^-8 * |a| * |w4| per flipped element; with weights of
 scale 0.08 and a handful of flips that stays far below 1e-3 (1 + |y|), the
 bound used for y.  Gradients pass through the same flips (dZ1..dZ3 are also
-rounded), so they are compared per tensor in relative L2 norm (<= 1e-2).
+rounded), so on random data they are compared per tensor in relative L2 norm
+(<= 1e-2).  On a case built so that no rounding happens at all (dyadic
+weights and inputs with few significant bits), outputs, loss and every
+gradient element must equal the oracle exactly, and one Adam step must land
+within one float32 ulp of it, element by element.
 """
 
 import sys
@@ -93,6 +97,86 @@ def test_gradients(B, n):
         a, b = g[name].ravel(), go[name].ravel()
         rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
         assert rel <= 1e-2, (name, rel)
+
+
+def make_dyadic_case(seed, B, n):
+    """A case on which the device's float32 arithmetic is exact: features are
+    0 or 1, weights are sparse multiples of 1/4, 1/2 (at most 3, 2 and 1
+    nonzeros per row of W1, W2, W3), biases small multiples of a power of two.
+    Then every value at a BF16 rounding point (S, A2, A3, dZ1..dZ3) has at most
+    8 significant bits and every float32 sum stays below 2^24 units of its
+    grid, so the device's outputs and gradients must equal the oracle's float64
+    values exactly, whatever the summation order.  B is a power of two and the
+    targets differ from the exact outputs by +-1/4 or +-1/2, so dy is exact."""
+    rng = np.random.default_rng(seed)
+    used = mlp.N_FEAT + mlp.N_POS
+    W1 = np.zeros((mlp.D_HID, mlp.D_IN))
+    for r in range(mlp.D_HID):
+        cols = rng.choice(used, size=3, replace=False)
+        W1[r, cols] = rng.choice([-0.25, 0.25], size=3)
+    W2 = np.zeros((mlp.D_HID, mlp.D_HID))
+    W3 = np.zeros((mlp.D_HID, mlp.D_HID))
+    for r in range(mlp.D_HID):
+        cols = rng.choice(mlp.D_HID, size=2, replace=False)
+        W2[r, cols] = rng.choice([-0.5, 0.5], size=2)
+        W3[r, rng.integers(0, mlp.D_HID)] = rng.choice([-0.5, 0.5])
+    params = {"W1": W1, "b1": rng.choice([-0.25, 0.0, 0.25], size=mlp.D_HID),
+              "W2": W2, "b2": rng.choice([-0.125, 0.0, 0.125], size=mlp.D_HID),
+              "W3": W3, "b3": rng.choice([-0.0625, 0.0, 0.0625], size=mlp.D_HID),
+              "w4": rng.choice([-0.5, 0.0, 0.5], size=mlp.D_HID), "b4": np.array([0.03125])}
+    flat = mlp.flatten(params).astype(np.float32)
+    assert np.array_equal(flat.astype(np.float64), mlp.flatten(params))
+    feat = rng.integers(0, 2, size=(1, n, mlp.N_FEAT)).astype(np.float32)
+    pos = np.stack([rng.permutation(n) for _ in range(B)]).astype(np.uint8)
+    pos[1, : n // 2] = mlp.UNPLACED  # a partial order
+    X = np.zeros((B, n, mlp.D_IN))
+    X[:, :, :mlp.N_FEAT] = feat[0][None].astype(np.float64)
+    for b in range(B):
+        X[b, np.arange(n), mlp.N_FEAT + pos[b]] = 1.0
+    y, c = mlp.forward(params, X)
+    # the rounding points really are exact on this case (so the comparison is exact)
+    for key in ("Sb", "A2b", "A3b"):
+        assert np.array_equal(mlp.bf16(c[key]), c[key]), key
+    t = (y + rng.choice([-0.5, -0.25, 0.25, 0.5], size=B)).astype(np.float32)
+    assert np.array_equal(t.astype(np.float64) - y, t - y)
+    return params, flat, feat, pos, X, y, t
+
+
+@pytest.mark.parametrize("B,n", [(64, 10), (128, 16), (32, 3)])
+def test_gradients_exact_element_by_element(B, n):
+    params, flat, feat, pos, X, y_or, t = make_dyadic_case(60 + n, B, n)
+    say(f"exact backward B={B} n={n}")
+    model = nn.Surrogate(flat)
+    x = device_tokens(model, feat, pos)
+    assert np.array_equal(bf16_values(x), X)
+    y = model.forward(x).cpu().numpy().astype(np.float64)
+    assert np.array_equal(y, y_or)
+    loss = model.backward(x, torch.from_numpy(t).to("cuda:0"))
+    lo, _, go = mlp.loss_and_grads(params, X, t.astype(np.float64))
+    # the oracle's own rounding points are identities here as well
+    _, _, go_plain = mlp.loss_and_grads(params, X, t.astype(np.float64), bf16_points=False)
+    assert float(loss.cpu()[0]) == lo
+    g = mlp.unflatten(model.read("grads").astype(np.float64))
+    for name, _ in mlp.SHAPES:
+        assert np.array_equal(go[name], go_plain[name]), name
+        bad = np.flatnonzero(g[name].ravel() != go[name].ravel())
+        assert bad.size == 0, (name, bad[:5], g[name].ravel()[bad[:5]], go[name].ravel()[bad[:5]])
+    assert sum(np.count_nonzero(go[k]) for k, _ in mlp.SHAPES) > 2000  # the case is not trivial
+    # one Adam step from the same float32 weights and exact gradients, element
+    # by element: the device evaluates the update (moments, bias corrections,
+    # square root, epsilon, quotient, learning rate: about ten float32
+    # roundings of relative size 2^-24 each) and rounds the new weight, so it
+    # lies within one float32 ulp of the new weight plus 10 * 2^-24 * lr of
+    # the oracle's float64 step; components with a zero gradient do not move
+    lr = 1e-3
+    model.adam(1, lr)
+    w_dev = model.read("weights").astype(np.float64)
+    gflat = mlp.flatten(go)
+    w0 = flat.astype(np.float64)
+    w_or, _, _ = mlp.adam_step(w0, gflat, np.zeros_like(gflat), np.zeros_like(gflat), 1, lr)
+    ulp = np.spacing(np.abs(w_or).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(w_dev - w_or) <= ulp + 10 * 2.0 ** -24 * lr), np.abs(w_dev - w_or).max()
+    assert np.array_equal(w_dev[gflat == 0], w0[gflat == 0])
 
 
 def test_adam_step():

@@ -2,6 +2,7 @@
 against the oracle's block-by-block simulation, element by element."""
 
 import itertools
+import math
 import sys
 
 import numpy as np
@@ -180,3 +181,19 @@ def test_rounds_one_block_per_cu():
     ks = synth.random_tiny_set(rng, 6, model, tblk_hi=150, inst_hi=4000)
     orders = np.array(list(itertools.permutations(range(6))), dtype=np.int32)
     _check(model.as_dict(), ks, orders, "blk_cu=1")
+
+
+def test_rounds_report_statistics_on_device():
+    # the report's best, worst and percentile (device statistics over the
+    # device's makespans) against the oracle on the same sampled orders
+    from oracle.sampling import sampled_rank
+    from paper_1511_07983_amd import rounds
+    rec = rounds.report(n_orders=20000, reps=1, out=lambda *a, **k: None)
+    ks = synth.draw_set(1, 0)
+    gpu = synth.MI355X_MODEL.as_dict()
+    orders = np.array([oracle.unrank(10, sampled_rank(rounds.SEED, 0, i, math.factorial(10)))
+                       for i in range(20000)], dtype=np.int32)
+    want = oracle.rounds_makespans(gpu, ks, orders)
+    h = int(oracle.rounds_makespans(gpu, ks, [rec["heuristic_order"]])[0])
+    assert (rec["best"], rec["worst"], rec["heuristic_makespan"]) == (int(want.min()), int(want.max()), h)
+    assert rec["heuristic_percentile"] == round(100.0 * float((want >= h).sum()) / 20000, 2)

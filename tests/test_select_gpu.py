@@ -167,3 +167,31 @@ def test_median_gain_on_device_matches_oracle():
         t_alg = int(rng.integers(900, 1100))
         got = ko.median_gain(torch.from_numpy(m).to(DEV), t_alg)
         assert got == ostats.median_gain(m, t_alg), n
+
+
+@pytest.mark.parametrize("count", [0, 1, 255, 256, 257, 70_001, 3_628_800])
+def test_stats_i64_matches_oracle(count):
+    """Device statistics of an int64 array against the oracle's set_stats:
+    extremes with the smallest index on ties, counts against a reference,
+    on ragged sizes, heavy ties and negative values."""
+    rng = np.random.default_rng(count + 11)
+    v = rng.integers(-50, 400, size=count, dtype=np.int64)
+    if count > 10:
+        v[rng.integers(0, count, count // 3)] = 7   # ties at a middle value
+        v[count - 1] = v.min()                      # a tie of the minimum at the end
+    t = torch.from_numpy(v).to(DEV)
+    ref = torch.tensor([7], dtype=torch.int64, device=DEV)
+    say(f"stats count={count}")
+    rec = ko.stats_records(ko.ko_stats_i64(t, ref=ref))[0]
+    assert rec["n_orders"] == count
+    if count == 0:
+        assert rec["min_makespan"] == np.iinfo(np.int64).max and rec["max_makespan"] == np.iinfo(np.int64).min
+        assert rec["argmin"] == 0 and rec["argmax"] == 0
+        return
+    want = ostats.set_stats(v, ref=7)
+    assert (rec["min_makespan"], rec["max_makespan"]) == (want["min"], want["max"])
+    assert (rec["argmin"], rec["argmax"]) == (want["argmin"], want["argmax"])
+    assert (rec["n_less"], rec["n_equal"], rec["n_greater"]) == (want["n_less"], want["n_equal"], want["n_greater"])
+    # without a reference the counts are zero
+    rec = ko.stats_records(ko.ko_stats_i64(t))[0]
+    assert (rec["n_less"], rec["n_equal"], rec["n_greater"]) == (0, 0, 0)
