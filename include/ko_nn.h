@@ -131,6 +131,18 @@ size_t ko_nn_score_work_bytes(int32_t B);
 int ko_nn_forward_positions(const void *state_dev, const float *table_dev, const uint8_t *pos_dev,
                             int32_t B, int32_t n, float *y_dev, void *work_dev, void *hip_stream);
 
+/* ko_nn_score — y[B] (float32, device) for B orders of one set given as
+ * positions pos[B][n] (uint8, device: position of kernel i, 0..15, 16 =
+ * unplaced; larger values count as 16), from the set's features feat[n][8]
+ * (float32, device).  The same values as ko_nn_layer1_table followed by
+ * ko_nn_forward_positions, bit for bit, in one kernel that keeps each tile of
+ * 64 orders on chip (layer-1 pooling from the features and position weights,
+ * both 256x256 BF16 MFMA layers, the output layer): no table, no workspace,
+ * no intermediate in memory.  1 <= n <= 16, B >= 1.  Asynchronous on
+ * hip_stream.  Errors: KO_EINVAL. */
+int ko_nn_score(const void *state_dev, const float *feat_dev, const uint8_t *pos_dev, int32_t B, int32_t n,
+                float *y_dev, void *hip_stream);
+
 const char *ko_nn_last_error(void);
 
 #ifdef __cplusplus

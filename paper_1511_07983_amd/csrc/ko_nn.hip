@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ko_nn.h"
@@ -20,6 +21,8 @@
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kHid = KO_NN_HID;
@@ -60,6 +63,16 @@ __host__ __device__ inline uint16_t to_bf16(float f)
     __builtin_memcpy(&u, &f, 4);
     u += 0x7FFFu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
+}
+
+// Two floats to BF16 (round to nearest even, as to_bf16 for every finite
+// value) in one conversion instruction; lo in bits 0..15.
+__device__ inline uint32_t pack_bf16x2(float lo, float hi)
+{
+    const bf16x2 h = __builtin_convertvector(f32x2{lo, hi}, bf16x2);
+    uint32_t u;
+    __builtin_memcpy(&u, &h, 4);
+    return u;
 }
 
 __device__ inline float from_bf16(uint16_t h)
@@ -518,11 +531,29 @@ __global__ __launch_bounds__(1024) void within_set_rank_kernel(const int64_t *va
         ranks[s * per + (int64_t)(key[p] & 8191u)] = p;
 }
 
+// The feature part of layer 1 plus its bias, for kernel i and hidden unit j:
+// g(i, j) = (sum_{k<8} W1[j][k] f_i[k]) + b1[j], summed in k order in
+// float32 over the BF16 operands the token path multiplies.  w1r holds the 8
+// BF16 weights W1[j][0..7].
+__device__ __forceinline__ float layer1_base(const uint4 w1r, const float *fi, float b1)
+{
+    const uint32_t w[4] = {w1r.x, w1r.y, w1r.z, w1r.w};
+    float z = 0.f;
+#pragma unroll
+    for (int k = 0; k < KO_NN_FEAT; k++) {
+        const uint16_t h = (uint16_t)(w[k >> 1] >> (16 * (k & 1)));
+        z += from_bf16(h) * from_bf16(to_bf16(fi[k]));
+    }
+    return z + b1;
+}
+
 // Layer 1 for one set, tabulated over launch positions: a token is its
 // kernel's features plus a one-hot position, so its first-layer output is
-//   T[i][p][j] = relu(sum_{k<8} W1[j][k] f_i[k] + W1[j][8+p] + b1[j])
-// for kernel i at position p (17 positions: 16 launch slots and "unplaced").
-// Operands are the BF16 values the token path multiplies; sums are float32.
+//   T[i][p][j] = relu(g(i, j) + W1[j][8+p])
+// for kernel i at position p (17 positions: 16 launch slots and "unplaced"),
+// with g as in layer1_base.  Operands are the BF16 values the token path
+// multiplies; sums are float32 (the token path adds the bias last, an
+// association that differs only in float32 rounding).
 __global__ void table_kernel(const uint16_t *wb, const float *master, const float *feat, int32_t n,
                              float *T)
 {
@@ -532,12 +563,9 @@ __global__ void table_kernel(const uint16_t *wb, const float *master, const floa
     const int j = (int)(idx % kHid);
     const int p = (int)((idx / kHid) % KO_NN_POS);
     const int64_t i = idx / ((int64_t)kHid * KO_NN_POS);
-    float z = 0.f;
-    for (int k = 0; k < KO_NN_FEAT; k++)
-        z += from_bf16(wb[kW1 + (size_t)j * kIn + k]) * from_bf16(to_bf16(feat[i * KO_NN_FEAT + k]));
-    z += from_bf16(wb[kW1 + (size_t)j * kIn + KO_NN_FEAT + p]);
-    z += master[kB1 + j];
-    T[idx] = fmaxf(z, 0.f);
+    const uint4 w1r = *reinterpret_cast<const uint4 *>(wb + kW1 + (size_t)j * kIn);
+    const float g = layer1_base(w1r, feat + i * KO_NN_FEAT, master[kB1 + j]);
+    T[idx] = fmaxf(g + from_bf16(wb[kW1 + (size_t)j * kIn + KO_NN_FEAT + p]), 0.f);
 }
 
 // Sum pooling from the table: S[b][j] = sum_i T[i][pos[b][i]][j] (kernel order,
@@ -554,6 +582,151 @@ __global__ __launch_bounds__(256) void gather_pool_kernel(const float *T, const 
         s += T[((int64_t)i * KO_NN_POS + p) * kHid + j];
     }
     Sb[b * kHid + j] = to_bf16(s);
+}
+
+// Scoring in one kernel, for a tile of 64 orders of one set per workgroup:
+// the same values as table_kernel + gather_pool_kernel + the two hidden
+// layers (gemm_nt_kernel) + out_forward_kernel, bit for bit, with nothing
+// written to memory but y.
+//   1. layer 1 and pooling: a token's first-layer output is
+//      relu(g(i, j) + W1[j][8 + p]) (table_kernel); each thread keeps g for
+//      its two columns and every kernel in registers and reads the position
+//      weights from LDS, so the table (n x 17 x 256 floats) is never built.
+//      A row's positions come in one 16-byte LDS read; S is summed in kernel
+//      order and rounded to BF16 into an LDS tile [64][256];
+//   2. layers 2 and 3: wave w computes columns [64w, 64w + 64) of
+//      relu(A W^T + b) for the 64 rows as 4 x 4 MFMA 16x16x32 tiles, A from
+//      the LDS tile, W's 16-byte fragments straight from memory (the same
+//      fragments and k order as gemm_nt_kernel), and writes the BF16 result
+//      back over the tile once every wave has read it;
+//   3. the output layer: one wave per row, the same sum as out_forward_kernel.
+constexpr int kScTile = 64;                // orders per workgroup
+constexpr int kScPitch = kHid + 8;         // LDS row pitch (elements): 132 dwords, 4 mod 32 banks
+
+template <int N>
+__global__ __launch_bounds__(256) void score_kernel(const uint16_t *wb, const float *master, const float *feat,
+                                                    const uint8_t *pos, int32_t B, float *y)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t At[kScTile][kScPitch];
+    __shared__ __attribute__((aligned(16))) float w1p[KO_NN_POS][kHid];
+    // per row and kernel: the byte offset of the position's row of w1p
+    __shared__ __attribute__((aligned(16))) uint16_t ps[kScTile][16];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    // the wave index is uniform across the wave (see out_forward_kernel)
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t b0 = (int64_t)blockIdx.x * kScTile;
+    const int rows = (int)min((int64_t)kScTile, (int64_t)B - b0);
+
+    for (int idx = tid; idx < KO_NN_POS * kHid; idx += 256) {
+        const int q = idx / kHid, j = idx % kHid;
+        w1p[q][j] = from_bf16(wb[kW1 + (size_t)j * kIn + KO_NN_FEAT + q]);
+    }
+    for (int idx = tid; idx < kScTile * 16; idx += 256) {
+        const int r = idx >> 4, i = idx & 15;
+        const int p = (r < rows && i < N) ? min((int)pos[(b0 + r) * N + i], KO_NN_UNPLACED) : KO_NN_UNPLACED;
+        ps[r][i] = (uint16_t)(p * kHid * (int)sizeof(float));
+    }
+    // thread t: columns c0 = 2 (t % 128) and c0 + 1, rows [32 (t / 128), +32)
+    const int c0 = 2 * (tid & 127);
+    const int r0 = (tid >> 7) * (kScTile / 2);
+    const uint4 w1a = *reinterpret_cast<const uint4 *>(wb + kW1 + (size_t)c0 * kIn);
+    const uint4 w1b = *reinterpret_cast<const uint4 *>(wb + kW1 + (size_t)(c0 + 1) * kIn);
+    const float bias0 = master[kB1 + c0], bias1 = master[kB1 + c0 + 1];
+    float g0[N], g1[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        g0[i] = layer1_base(w1a, feat + i * KO_NN_FEAT, bias0);
+        g1[i] = layer1_base(w1b, feat + i * KO_NN_FEAT, bias1);
+    }
+    __syncthreads();
+    const char *wcol = reinterpret_cast<const char *>(&w1p[0][c0]);
+    for (int r = r0; r < r0 + kScTile / 2; r++) {
+        uint32_t pw[8];
+        const uint4 q0 = *reinterpret_cast<const uint4 *>(&ps[r][0]);
+        pw[0] = q0.x, pw[1] = q0.y, pw[2] = q0.z, pw[3] = q0.w;
+        if (N > 8) {
+            const uint4 q1 = *reinterpret_cast<const uint4 *>(&ps[r][8]);
+            pw[4] = q1.x, pw[5] = q1.y, pw[6] = q1.z, pw[7] = q1.w;
+        }
+        float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+        for (int i = 0; i < N; i++) {
+            const uint32_t off = (i & 1) ? (pw[i >> 1] >> 16) : (pw[i >> 1] & 0xFFFFu);
+            const float2 w = *reinterpret_cast<const float2 *>(wcol + off);
+            s0 += fmaxf(g0[i] + w.x, 0.f);
+            s1 += fmaxf(g1[i] + w.y, 0.f);
+        }
+        *reinterpret_cast<uint32_t *>(&At[r][c0]) = pack_bf16x2(s0, s1);
+    }
+    __syncthreads();
+
+    const int kk = (lane >> 4) * 8;
+#pragma unroll
+    for (int layer = 0; layer < 2; layer++) {
+        const uint16_t *W = wb + (layer == 0 ? kW2 : kW3);
+        const float *bias = master + (layer == 0 ? kB2 : kB3);
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k0 = 0; k0 < kHid; k0 += kKStep) {
+            bf16x8 af[4], bfr[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(W + (size_t)(wave * 64 + j * 16 + (lane & 15)) * kHid +
+                                                           k0 + kk);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                af[i] = *reinterpret_cast<const bf16x8 *>(&At[i * 16 + (lane & 15)][k0 + kk]);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();  // every wave has read the tile
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int col = wave * 64 + j * 16 + (lane & 15);
+            const float bc = bias[col];
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int e = 0; e < 4; e += 2) {
+                    const int row = i * 16 + (lane >> 4) * 4 + e;
+                    const uint32_t h = pack_bf16x2(fmaxf(acc[i][j][e] + bc, 0.f), fmaxf(acc[i][j][e + 1] + bc, 0.f));
+                    At[row][col] = (uint16_t)h;
+                    At[row + 1][col] = (uint16_t)(h >> 16);
+                }
+        }
+        __syncthreads();
+    }
+    for (int r = wave; r < rows; r += 4) {
+        float s = 0.f;
+        for (int c = lane; c < kHid; c += 64)
+            s += from_bf16(At[r][c]) * from_bf16(wb[kW4 + c]);
+        s = wave_sum(s);
+        if (lane == 0)
+            y[b0 + r] = s + master[kB4];
+    }
+}
+
+template <int N>
+void launch_score_n(unsigned grid, hipStream_t st, const uint16_t *wb, const float *master, const float *feat,
+                    const uint8_t *pos, int32_t B, float *y)
+{
+    hipLaunchKernelGGL(score_kernel<N>, dim3(grid), dim3(256), 0, st, wb, master, feat, pos, B, y);
+}
+
+template <int... Ns>
+bool launch_score(int n, unsigned grid, hipStream_t st, const uint16_t *wb, const float *master, const float *feat,
+                  const uint8_t *pos, int32_t B, float *y, std::integer_sequence<int, Ns...>)
+{
+    return ((n == Ns + 1 ? (launch_score_n<Ns + 1>(grid, st, wb, master, feat, pos, B, y), true) : false) || ...);
 }
 
 // ------------------------------------------------------------------ host side
@@ -1088,6 +1261,22 @@ int ko_nn_forward_positions(const void *state_dev, const float *table_dev, const
     return forward_positions_impl(state_of(const_cast<void *>(state_dev)), table_dev, pos_dev, B, n,
                                   y_dev, (uint16_t *)c, (uint16_t *)(c + part),
                                   (uint16_t *)(c + 2 * part), (hipStream_t)hip_stream);
+}
+
+int ko_nn_score(const void *state_dev, const float *feat_dev, const uint8_t *pos_dev, int32_t B, int32_t n,
+                float *y_dev, void *hip_stream)
+{
+    if (!state_dev || !feat_dev || !pos_dev || !y_dev)
+        return fail(KO_EINVAL, "state, features, positions and y must not be NULL");
+    if (B < 1 || n < 1 || n > KO_NN_MAX_TOKENS)
+        return fail(KO_EINVAL, "B must be >= 1 and n in 1..%d", KO_NN_MAX_TOKENS);
+    const State s = state_of(const_cast<void *>(state_dev));
+    const unsigned grid = (unsigned)(((int64_t)B + kScTile - 1) / kScTile);
+    // one instantiation per set size: the kernel loop is unrolled over the tokens
+    launch_score(n, grid, (hipStream_t)hip_stream, s.wb, s.master, feat_dev, pos_dev, B, y_dev,
+                 std::make_integer_sequence<int, KO_NN_MAX_TOKENS>{});
+    NN_LAUNCHED();
+    return KO_OK;
 }
 
 const char *ko_nn_last_error(void) { return g_err.c_str(); }

@@ -36,7 +36,7 @@ EXPORTED = ("ko_nn_num_params", "ko_nn_state_bytes", "ko_nn_work_bytes", "ko_nn_
             "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens", "ko_nn_targets", "ko_nn_within_set_ranks",
             "ko_nn_forward",
             "ko_nn_backward", "ko_nn_adam", "ko_nn_layer1_table", "ko_nn_score_work_bytes",
-            "ko_nn_forward_positions", "ko_nn_last_error")
+            "ko_nn_forward_positions", "ko_nn_score", "ko_nn_last_error")
 
 _vp = ctypes.c_void_p
 _lib.ko_nn_num_params.restype = ctypes.c_size_t
@@ -58,10 +58,11 @@ _lib.ko_nn_within_set_ranks.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp
 _lib.ko_nn_score_work_bytes.argtypes = [ctypes.c_int32]
 _lib.ko_nn_score_work_bytes.restype = ctypes.c_size_t
 _lib.ko_nn_forward_positions.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
+_lib.ko_nn_score.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
 _lib.ko_nn_last_error.restype = ctypes.c_char_p
 for _f in ("ko_nn_load", "ko_nn_read", "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens", "ko_nn_targets",
            "ko_nn_forward", "ko_nn_backward", "ko_nn_adam", "ko_nn_layer1_table", "ko_nn_within_set_ranks",
-           "ko_nn_forward_positions"):
+           "ko_nn_forward_positions", "ko_nn_score"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -194,6 +195,17 @@ class Surrogate:
         _check(_lib.ko_nn_forward_positions(self.state.data_ptr(), table.data_ptr(), pos.data_ptr(), B, n,
                                             y.data_ptr(), self._score_work.data_ptr(),
                                             _stream_handle(stream)))
+        return y
+
+    def score(self, feat, pos, y=None, stream=None):
+        """feat: device float32 [n, 8] of one set; pos: device uint8 [B, n]
+        (position of each kernel) -> y [B], in one fused kernel (ko_nn_score)."""
+        torch = self.torch
+        B, n = pos.shape
+        if y is None:
+            y = torch.empty(B, dtype=torch.float32, device=self.device)
+        _check(_lib.ko_nn_score(self.state.data_ptr(), feat.data_ptr(), pos.data_ptr(), B, n, y.data_ptr(),
+                                _stream_handle(stream)))
         return y
 
     def adam(self, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

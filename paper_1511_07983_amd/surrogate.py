@@ -186,8 +186,7 @@ def predict(sur: "nn.Surrogate", table: SetTable, set_index: int, pos):
     host: lower is better.  With rank-quantile training a score estimates the
     order's quantile among the set's orders; with "lb" training it is cycles
     above the set's best over its lower bound."""
-    tab = sur.layer1_table(table.feat[set_index])
-    return sur.forward_positions(tab, pos).cpu().numpy().astype(np.float64)
+    return sur.score(table.feat[set_index], pos).cpu().numpy().astype(np.float64)
 
 
 def mae_cycles(res: "SearchResult", q: Quantile, target: str, lb: float) -> float:
@@ -264,13 +263,13 @@ def score_and_rerank(sur: "nn.Surrogate", table: SetTable, set_index: int, *, n_
     """Score `n_score` sampled orders, keep the `top_k` best predicted, re-simulate them exactly."""
     torch = _torch()
     n = table.n
-    tab = sur.layer1_table(table.feat[set_index])
+    feat = table.feat[set_index]
     scores = torch.empty(n_score, dtype=torch.float32, device=device)
     pos = torch.empty(min(batch, n_score) * n, dtype=torch.uint8, device=device)
     for b0 in range(0, n_score, batch):
         c = min(batch, n_score - b0)
         ko_sample_orders(n, set_index, seed, c, first=b0, positions=pos[:c * n])
-        sur.forward_positions(tab, pos[:c * n].view(c, n), y=scores[b0:b0 + c])
+        sur.score(feat, pos[:c * n].view(c, n), y=scores[b0:b0 + c])
     idx, val = ko_topk_f32(scores, top_k)
     orders = torch.empty(top_k * n, dtype=torch.uint8, device=device)
     ko_sample_orders(n, set_index, seed, top_k, indices=idx, orders=orders)
@@ -307,7 +306,7 @@ def beam_search(sur: "nn.Surrogate", table: SetTable, set_index: int, *, width: 
     onto the descendants of a few prefixes)."""
     torch = _torch()
     n = table.n
-    tab = sur.layer1_table(table.feat[set_index])
+    feat = table.feat[set_index]
     beams = np.zeros((1, 0), dtype=np.int64)  # prefixes of kernel indices
     n_scored = 0
     val = None
@@ -320,7 +319,7 @@ def beam_search(sur: "nn.Surrogate", table: SetTable, set_index: int, *, width: 
         pos = np.full((len(cand), n), nn.UNPLACED, dtype=np.uint8)
         np.put_along_axis(pos, cand, np.arange(depth + 1, dtype=np.uint8)[None, :].repeat(len(cand), 0),
                           axis=1)
-        scores = sur.forward_positions(tab, torch.from_numpy(pos).to(device))
+        scores = sur.score(feat, torch.from_numpy(pos).to(device))
         n_scored += len(cand)
         keep = min(width, len(cand))
         if max_children > 0:

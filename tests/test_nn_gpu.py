@@ -251,3 +251,32 @@ def test_forward_positions_matches_oracle_and_token_path(B, n):
     assert np.abs(y - yo).max() <= 1e-3 * (1.0 + np.abs(yo).max())
     y_tok = model.forward(device_tokens(model, feat, pos)).cpu().numpy().astype(np.float64)
     assert np.abs(y - y_tok).max() <= 1e-3 * (1.0 + np.abs(y_tok).max())
+
+
+@pytest.mark.parametrize("B,n", [(1, 1), (63, 5), (64, 16), (65, 12), (1000, 12), (4097, 9), (300, 16)])
+def test_fused_score_equals_table_path_bit_for_bit(B, n):
+    """ko_nn_score (one kernel: layer-1 pooling from features and position
+    weights, both MFMA layers, output layer) against the table path (layer-1
+    table, gather-sum, two GEMM launches, output kernel): every y identical,
+    on ragged tiles, partial orders and out-of-range positions; and within
+    the oracle's tolerance."""
+    rng, flat, feat, pos, X = make_case(70 + B + n, B, n)
+    if B > 3:
+        pos[2, :] = 200  # positions above 16 count as unplaced
+        X[2, :, mlp.N_FEAT:] = 0.0
+        X[2, :, mlp.N_FEAT + mlp.UNPLACED] = 1.0
+    say(f"fused score B={B} n={n}")
+    model = nn.Surrogate(flat)
+    f = torch.from_numpy(feat[0]).to("cuda:0")
+    p = torch.from_numpy(pos).to("cuda:0")
+    y_fused = model.score(f, p).cpu().numpy()
+    y_table = model.forward_positions(model.layer1_table(f), p).cpu().numpy()
+    bad = np.flatnonzero(y_fused.view(np.uint32) != y_table.view(np.uint32))
+    assert bad.size == 0, (bad[:5], y_fused[bad[:5]], y_table[bad[:5]])
+    # against the oracle with the tolerance of the module docstring, which
+    # allows a handful of BF16 rounding flips per row: it holds for a few
+    # hundred rows; over thousands, some row collects more flips (the table
+    # path, identical above, does the same)
+    m = min(B, 256)
+    yo, _ = mlp.forward(mlp.unflatten(flat.astype(np.float64)), X[:m])
+    assert np.abs(y_fused[:m] - yo).max() <= 1e-3 * (1.0 + np.abs(yo).max())
