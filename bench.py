@@ -18,8 +18,10 @@ to the same line: the round-synchronous model ("rounds") and memory contention
 ("small"), all orders of the 4096-set batch in one captured graph ("batch";
 --no-legs skips these two), the metric's second part on the n=12 workload
 ("surrogate": exact simulations to the first order in the exact top 1%, learned
-scorer against uniform sampling, two training recipes; --no-surrogate skips
-it), then the CPU oracle at every core and at one thread ("cpu_baseline").
+scorer against uniform sampling, two training recipes) and on the n=16 sets
+("search_n16": beam search and sample-then-score at an equal exact budget;
+--no-surrogate skips both), then the CPU oracle at every core and at one
+thread ("cpu_baseline").
 Prints one JSON line.
 """
 
@@ -181,6 +183,28 @@ def surrogate_leg(heldout: int) -> dict:
            "as_specified_512x8192": _surrogate_recipe(heldout, 512, 8192, quantiles, exact_rate),
            "wide_8192x512": _surrogate_recipe(heldout, 8192, 512, quantiles, exact_rate)}
     return out
+
+
+def search_n16_leg() -> dict:
+    """Surrogate-guided search on the 1024 n=16 sets (N_tblk 256..8192) at an
+    equal budget of 256 exact simulations per set against uniform sampling:
+    beam search (width 256, at most 2 children per prefix), sample-then-score
+    (2^20 scored orders, the best 256 simulated) and both ranked together."""
+    import json as _json
+
+    from paper_1511_07983_amd import surrogate
+    recs = []
+    try:
+        surrogate.report_beam(eval_sets=1024, out=lambda t, **kw: recs.append(_json.loads(t)))
+    except Exception as exc:  # keep the throughput line even if this leg fails
+        return {"error": f"{type(exc).__name__}: {exc}"}
+    print("[bench] search n=16 done", file=sys.stderr, flush=True)
+    train = next(r for r in recs if r.get("phase") == "train")
+    res = next(r for r in recs if r.get("phase") == "search_vs_random")
+    res["train_s"] = train["train_s"]
+    res["train_samples"] = train["samples"]
+    res.pop("phase", None)
+    return res
 
 
 def _event_time(fn, stream, reps: int) -> float:
@@ -422,6 +446,7 @@ def main():
         out["batch"] = batch_leg()
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(args.surrogate_heldout)
+        out["search_n16"] = search_n16_leg()
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(w.model, ks, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -143,6 +143,35 @@ int ko_nn_forward_positions(const void *state_dev, const float *table_dev, const
 int ko_nn_score(const void *state_dev, const float *feat_dev, const uint8_t *pos_dev, int32_t B, int32_t n,
                 float *y_dev, void *hip_stream);
 
+/* Beam search over launch orders of one set, one position per step, on the
+ * device (the scores come from ko_nn_score on the candidates' positions; the
+ * selection of the best candidates is libko's ko_topk_f32).
+ *
+ * ko_nn_beam_expand — the candidates of one step: prefix w (prefix[W][d],
+ * uint8, device: the kernels at positions 0..d-1; NULL when d = 0 and W = 1)
+ * grows by each of its n - d unused kernels in increasing index order.
+ * Candidate c = w (n - d) + t gets pos[c][n] (uint8, device: position of
+ * every kernel, d for the new one, 16 = unplaced) and cand[c] (int32,
+ * device) = w << 8 | new kernel.  1 <= n <= 16, 0 <= d < n, W >= 1. */
+int ko_nn_beam_expand(const uint8_t *prefix_dev, int32_t W, int32_t d, int32_t n, uint8_t *pos_dev,
+                      int32_t *cand_dev, void *hip_stream);
+
+/* ko_nn_beam_cap — diversity rules on a step's scores (score[W][m], float32,
+ * device, in place; m = n - d children per prefix): with temperature > 0 each
+ * score first gets temperature * G added, G a standard Gumbel variate from
+ * SplitMix64 (Steele, Lea & Flood 2014) at counter (seed, candidate index),
+ * i.e. -log(-log(u)) with u = (top 24 bits + 0.5) / 2^24; then with cap > 0
+ * only the cap lowest scores among each prefix's children are kept (ties by
+ * candidate order) and the others become +inf.  Errors: KO_EINVAL. */
+int ko_nn_beam_cap(float *score_dev, int32_t W, int32_t m, int32_t cap, float temperature, uint64_t seed,
+                   void *hip_stream);
+
+/* ko_nn_beam_gather — the next step's prefixes: out[r][d+1] (uint8, device)
+ * = the prefix of candidate idx[r] (int64, device) followed by its new
+ * kernel, r < keep.  Errors: KO_EINVAL. */
+int ko_nn_beam_gather(const uint8_t *prefix_dev, int32_t d, const int32_t *cand_dev, const int64_t *idx_dev,
+                      int32_t keep, uint8_t *out_dev, void *hip_stream);
+
 const char *ko_nn_last_error(void);
 
 #ifdef __cplusplus

@@ -21,6 +21,10 @@ Parts:
   * ``stats``        per-set statistics, rank counts, percentiles, histogram,
                       and the Table 3 report formulas.
   * ``sampling``     counter-based sampled ranks (SplitMix64 + multiply-shift).
+  * ``features``, ``mlp``  the surrogate's per-kernel features, area lower
+                      bound and network in float64.
+  * ``beam``         the bookkeeping of one beam-search step (expansion,
+                      diversity rules, gather).
 """
 
 from __future__ import annotations

@@ -729,6 +729,98 @@ bool launch_score(int n, unsigned grid, hipStream_t st, const uint16_t *wb, cons
     return ((n == Ns + 1 ? (launch_score_n<Ns + 1>(grid, st, wb, master, feat, pos, B, y), true) : false) || ...);
 }
 
+// ------------------------------------------------------------------ beam search
+
+// Candidates of one beam step: prefix w (kernel indices of positions 0..d-1)
+// grows by each of its m = n - d unused kernels, in increasing kernel order.
+// Candidate c = w * m + t: pos[c][i] = position of kernel i (the prefix's, d
+// for the new kernel, 16 = unplaced for the rest); cand[c] = w << 8 | kernel.
+__global__ void beam_expand_kernel(const uint8_t *prefix, int32_t W, int32_t d, int32_t n, uint8_t *pos,
+                                   int32_t *cand)
+{
+    const int m = n - d;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (int64_t)W * m)
+        return;
+    const int64_t w = c / m;
+    const int t = (int)(c % m);
+    uint32_t used = 0;
+    uint8_t p[KO_NN_MAX_TOKENS];
+    for (int i = 0; i < n; i++)
+        p[i] = KO_NN_UNPLACED;
+    for (int j = 0; j < d; j++) {
+        const int k = prefix[w * d + j];
+        used |= 1u << k;
+        p[k] = (uint8_t)j;
+    }
+    // the t-th unused kernel
+    int k = 0, seen = 0;
+    for (int i = 0; i < n; i++) {
+        if (!((used >> i) & 1u)) {
+            if (seen == t)
+                k = i;
+            seen++;
+        }
+    }
+    p[k] = (uint8_t)d;
+    for (int i = 0; i < n; i++)
+        pos[c * n + i] = p[i];
+    cand[c] = (int32_t)((w << 8) | k);
+}
+
+// Diversity rules on the scores of one step, in place (m candidates per
+// prefix, W prefixes): with temperature > 0 every score first gets
+// temperature * G added, G a standard Gumbel variate from the counter-based
+// generator (seed, candidate index); then, with cap > 0, only the cap best
+// scores of each prefix's children stay (ties by candidate order) and the
+// others become +inf.  One thread per prefix.
+__global__ void beam_cap_kernel(float *score, int32_t W, int32_t m, int32_t cap, float temperature, uint64_t seed)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= W)
+        return;
+    float v[KO_NN_MAX_TOKENS];
+    for (int t = 0; t < m; t++) {
+        float x = score[w * m + t];
+        if (temperature > 0.f) {
+            // SplitMix64 (Steele, Lea & Flood 2014) of seed + (c + 1) * golden gamma
+            uint64_t z = seed + (uint64_t)(w * m + t + 1) * 0x9E3779B97F4A7C15ull;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            const float u = ((float)(z >> 40) + 0.5f) * (1.0f / 16777216.0f);  // (0, 1)
+            x += temperature * -logf(-logf(u));
+        }
+        v[t] = x;
+    }
+    if (cap > 0 && cap < m) {
+        for (int t = 0; t < m; t++) {
+            int better = 0;
+            for (int u = 0; u < m; u++)
+                better += (v[u] < v[t] || (v[u] == v[t] && u < t)) ? 1 : 0;
+            if (better >= cap)
+                v[t] = INFINITY;
+        }
+    }
+    for (int t = 0; t < m; t++)
+        score[w * m + t] = v[t];
+}
+
+// New prefixes: out[r] = prefix[parent] followed by the candidate's kernel,
+// for the chosen candidates idx[0..keep).
+__global__ void beam_gather_kernel(const uint8_t *prefix, int32_t d, const int32_t *cand, const int64_t *idx,
+                                   int32_t keep, uint8_t *out)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= keep)
+        return;
+    const int32_t cw = cand[idx[r]];
+    const int64_t w = cw >> 8;
+    for (int j = 0; j < d; j++)
+        out[r * (d + 1) + j] = prefix[w * d + j];
+    out[r * (d + 1) + d] = (uint8_t)(cw & 0xFF);
+}
+
 // ------------------------------------------------------------------ host side
 
 thread_local std::string g_err = "no error";
@@ -1275,6 +1367,42 @@ int ko_nn_score(const void *state_dev, const float *feat_dev, const uint8_t *pos
     // one instantiation per set size: the kernel loop is unrolled over the tokens
     launch_score(n, grid, (hipStream_t)hip_stream, s.wb, s.master, feat_dev, pos_dev, B, y_dev,
                  std::make_integer_sequence<int, KO_NN_MAX_TOKENS>{});
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+int ko_nn_beam_expand(const uint8_t *prefix_dev, int32_t W, int32_t d, int32_t n, uint8_t *pos_dev,
+                      int32_t *cand_dev, void *hip_stream)
+{
+    if (n < 1 || n > KO_NN_MAX_TOKENS || d < 0 || d >= n || W < 1 || (int64_t)W * (n - d) > INT32_MAX)
+        return fail(KO_EINVAL, "need 1 <= n <= %d, 0 <= d < n, W >= 1 and W * (n - d) < 2^31", KO_NN_MAX_TOKENS);
+    if ((d > 0 && !prefix_dev) || !pos_dev || !cand_dev)
+        return fail(KO_EINVAL, "prefixes (when d > 0), positions and candidates must not be NULL");
+    const int64_t count = (int64_t)W * (n - d);
+    hipLaunchKernelGGL(beam_expand_kernel, dim3(grid1(count)), dim3(256), 0, (hipStream_t)hip_stream, prefix_dev,
+                       W, d, n, pos_dev, cand_dev);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+int ko_nn_beam_cap(float *score_dev, int32_t W, int32_t m, int32_t cap, float temperature, uint64_t seed,
+                   void *hip_stream)
+{
+    if (!score_dev || W < 1 || m < 1 || m > KO_NN_MAX_TOKENS || cap < 0 || !(temperature >= 0.f))
+        return fail(KO_EINVAL, "need scores, W >= 1, 1 <= m <= %d, cap >= 0, temperature >= 0", KO_NN_MAX_TOKENS);
+    hipLaunchKernelGGL(beam_cap_kernel, dim3(grid1(W)), dim3(256), 0, (hipStream_t)hip_stream, score_dev, W, m,
+                       cap, temperature, seed);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+int ko_nn_beam_gather(const uint8_t *prefix_dev, int32_t d, const int32_t *cand_dev, const int64_t *idx_dev,
+                      int32_t keep, uint8_t *out_dev, void *hip_stream)
+{
+    if (d < 0 || d >= KO_NN_MAX_TOKENS || keep < 1 || (d > 0 && !prefix_dev) || !cand_dev || !idx_dev || !out_dev)
+        return fail(KO_EINVAL, "need 0 <= d < %d, keep >= 1 and non-NULL buffers", KO_NN_MAX_TOKENS);
+    hipLaunchKernelGGL(beam_gather_kernel, dim3(grid1(keep)), dim3(256), 0, (hipStream_t)hip_stream, prefix_dev, d,
+                       cand_dev, idx_dev, keep, out_dev);
     NN_LAUNCHED();
     return KO_OK;
 }

@@ -36,7 +36,8 @@ EXPORTED = ("ko_nn_num_params", "ko_nn_state_bytes", "ko_nn_work_bytes", "ko_nn_
             "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens", "ko_nn_targets", "ko_nn_within_set_ranks",
             "ko_nn_forward",
             "ko_nn_backward", "ko_nn_adam", "ko_nn_layer1_table", "ko_nn_score_work_bytes",
-            "ko_nn_forward_positions", "ko_nn_score", "ko_nn_last_error")
+            "ko_nn_forward_positions", "ko_nn_score", "ko_nn_beam_expand", "ko_nn_beam_cap", "ko_nn_beam_gather",
+            "ko_nn_last_error")
 
 _vp = ctypes.c_void_p
 _lib.ko_nn_num_params.restype = ctypes.c_size_t
@@ -59,16 +60,49 @@ _lib.ko_nn_score_work_bytes.argtypes = [ctypes.c_int32]
 _lib.ko_nn_score_work_bytes.restype = ctypes.c_size_t
 _lib.ko_nn_forward_positions.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
 _lib.ko_nn_score.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
+_lib.ko_nn_beam_expand.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
+_lib.ko_nn_beam_cap.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64,
+                                _vp]
+_lib.ko_nn_beam_gather.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp, _vp]
 _lib.ko_nn_last_error.restype = ctypes.c_char_p
 for _f in ("ko_nn_load", "ko_nn_read", "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens", "ko_nn_targets",
            "ko_nn_forward", "ko_nn_backward", "ko_nn_adam", "ko_nn_layer1_table", "ko_nn_within_set_ranks",
-           "ko_nn_forward_positions", "ko_nn_score"):
+           "ko_nn_forward_positions", "ko_nn_score", "ko_nn_beam_expand", "ko_nn_beam_cap", "ko_nn_beam_gather"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
 def _check(rc):
     if rc != 0:
         raise KoError(rc, _lib.ko_nn_last_error().decode())
+
+
+def beam_expand(prefix, n: int, stream=None):
+    """Candidates of one beam step: prefix (device uint8 [W, d]) -> (positions
+    [W (n - d), n] uint8, candidates [W (n - d)] int32 = parent << 8 | kernel)."""
+    W, d = prefix.shape
+    C = W * (n - d)
+    pos = torch.empty((C, n), dtype=torch.uint8, device=prefix.device)
+    cand = torch.empty(C, dtype=torch.int32, device=prefix.device)
+    _check(_lib.ko_nn_beam_expand(prefix.data_ptr() if d else None, W, d, n, pos.data_ptr(), cand.data_ptr(),
+                                  _stream_handle(stream)))
+    return pos, cand
+
+
+def beam_cap(scores, W: int, m: int, cap: int = 0, temperature: float = 0.0, seed: int = 0, stream=None):
+    """Diversity rules on a step's scores (device float32 [W * m], in place)."""
+    _check(_lib.ko_nn_beam_cap(scores.data_ptr(), W, m, int(cap), float(temperature),
+                               int(seed) & ((1 << 64) - 1), _stream_handle(stream)))
+    return scores
+
+
+def beam_gather(prefix, cand, idx, stream=None):
+    """Next prefixes: device uint8 [keep, d + 1] from the chosen candidates idx (device int64)."""
+    W, d = prefix.shape
+    keep = idx.numel()
+    out = torch.empty((keep, d + 1), dtype=torch.uint8, device=cand.device)
+    _check(_lib.ko_nn_beam_gather(prefix.data_ptr() if d else None, d, cand.data_ptr(), idx.data_ptr(), keep,
+                                  out.data_ptr(), _stream_handle(stream)))
+    return out
 
 
 def num_params() -> int:

@@ -283,62 +283,41 @@ def score_and_rerank(sur: "nn.Surrogate", table: SetTable, set_index: int, *, n_
                         exact=ms.cpu().numpy(), n_scored=n_score)
 
 
-def _capped_best(scores: np.ndarray, parent: np.ndarray, keep: int, max_children: int) -> np.ndarray:
-    """Indices of the `keep` best (lowest) scores, ties by index, taking at most
-    `max_children` candidates that share a parent."""
-    order = np.lexsort((np.arange(len(scores)), scores))
-    ps = parent[order]
-    by_parent = np.argsort(ps, kind="stable")
-    sorted_ps = ps[by_parent]
-    starts = np.r_[0, np.flatnonzero(np.diff(sorted_ps)) + 1]
-    run_start = np.repeat(starts, np.diff(np.r_[starts, len(sorted_ps)]))
-    rank = np.empty(len(order), dtype=np.int64)
-    rank[by_parent] = np.arange(len(sorted_ps)) - run_start
-    return order[rank < max_children][:keep]
-
-
 def beam_search(sur: "nn.Surrogate", table: SetTable, set_index: int, *, width: int = 256,
-                max_children: int = 0, device="cuda:0") -> SearchResult:
-    """Grow orders position by position, keeping the `width` best-scored
-    prefixes (kernels not yet placed are "unplaced"); re-simulate the final
-    complete orders exactly.  With max_children > 0, at most that many children
-    of one prefix survive a step (a diversity rule: the beam cannot collapse
-    onto the descendants of a few prefixes)."""
+                max_children: int = 0, temperature: float = 0.0, seed: int = 0, device="cuda:0") -> SearchResult:
+    """Grow orders position by position on the device, keeping the `width`
+    best-scored prefixes (kernels not yet placed are "unplaced").  Each step
+    expands every kept prefix by each unused kernel (ko_nn_beam_expand),
+    scores the partial orders (ko_nn_score), applies the diversity rules
+    (ko_nn_beam_cap: at most `max_children` children of one prefix survive,
+    and with temperature > 0 Gumbel noise perturbs the scores, seeded per
+    step), keeps the best (ko_topk_f32) and gathers their prefixes
+    (ko_nn_beam_gather).  The last step scores the complete orders without
+    noise; they are ranked by that score and re-simulated exactly."""
     torch = _torch()
     n = table.n
     feat = table.feat[set_index]
-    beams = np.zeros((1, 0), dtype=np.int64)  # prefixes of kernel indices
+    prefix = torch.empty((1, 0), dtype=torch.uint8, device=device)
     n_scored = 0
     val = None
-    for depth in range(n):
-        used = np.zeros((len(beams), n), dtype=bool)
-        if depth:
-            np.put_along_axis(used, beams, True, axis=1)
-        parent, nxt = np.nonzero(~used)
-        cand = np.concatenate([beams[parent], nxt[:, None]], axis=1)
-        pos = np.full((len(cand), n), nn.UNPLACED, dtype=np.uint8)
-        np.put_along_axis(pos, cand, np.arange(depth + 1, dtype=np.uint8)[None, :].repeat(len(cand), 0),
-                          axis=1)
-        scores = sur.score(feat, torch.from_numpy(pos).to(device))
-        n_scored += len(cand)
-        keep = min(width, len(cand))
-        if max_children > 0:
-            sc = scores.cpu().numpy()
-            sel = _capped_best(sc, parent, keep, max_children)
-            beams = cand[sel]
-            val = torch.from_numpy(sc[sel])
-        else:
-            idx, v = ko_topk_f32(scores, keep)
-            beams = cand[idx.cpu().numpy()]
-            val = v
-    K = len(beams)
-    orders = torch.from_numpy(beams.astype(np.uint8).ravel().copy()).to(device)
+    for d in range(n):
+        W, m = prefix.shape[0], n - d
+        pos, cand = nn.beam_expand(prefix, n)
+        scores = sur.score(feat, pos)
+        n_scored += W * m
+        last = d == n - 1
+        if not last and (max_children > 0 or temperature > 0):
+            nn.beam_cap(scores, W, m, max_children, temperature, seed + d)
+        finite = W * (min(max_children, m) if max_children > 0 and not last else m)
+        idx, val = ko_topk_f32(scores, min(width, finite))
+        prefix = nn.beam_gather(prefix, cand, idx)
+    K = prefix.shape[0]
+    orders = prefix.reshape(-1).contiguous()
     ms = torch.empty(K, dtype=torch.int64, device=device)
     ko_simulate_batch(table.model, table.sets[set_index], [0, n], OrderSpec.explicit(orders, [K]),
                       makespans=ms)
     ko_sync()
-    lb = float(table.lb_host[set_index])
-    return SearchResult(sample_index=np.full(K, -1), orders=beams.astype(np.uint8),
+    return SearchResult(sample_index=np.full(K, -1), orders=prefix.cpu().numpy(),
                         predicted=val.cpu().numpy().astype(np.float64), exact=ms.cpu().numpy(),
                         n_scored=n_scored)
 
@@ -436,32 +415,47 @@ def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: i
     return rows
 
 
-def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets: int = 512, per_set: int = 8192,
-                 eval_sets: int = 1024, width: int = 256, q_samples: int = 4096, steps: int = 8192,
-                 batch: int = 4096, lr: float = 1e-3, mask_frac: float = 0.25, seed: int = 2016,
-                 max_children: int = 2, out=print):
-    """Beam search (width `width`) against uniform sampling at the same exact
-    budget (`width` exact simulations per set).  The top-1% threshold of each
-    set is the ceil(q_samples/100)-th smallest of `q_samples` exact random
-    orders (n! is out of reach at n=16).  Prints one JSON summary line."""
+def _search_row(exact_ranked: np.ndarray, exact: np.ndarray, threshold, random_expected):
+    """(best makespan, top-1% hits, exact simulations to the first hit)."""
+    return (int(exact.min()), int((exact <= threshold).sum()),
+            sims_to_first_hit(exact_ranked, int(threshold), float(random_expected)))
+
+
+def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets: int = 8192, per_set: int = 512,
+                eval_sets: int = 1024, width: int = 256, q_samples: int = 4096, steps: int = 32768,
+                batch: int = 4096, lr: float = 1e-3, mask_frac: float = 0.25, seed: int = 2016,
+                max_children: int = 2, temperature: float = 0.0, n_score: int = 1 << 20, sur=None,
+                out=print):
+    """Surrogate-guided search on n=16 sets against uniform sampling at the
+    same exact budget (`width` exact simulations per set): beam search (width
+    `width`, at most `max_children` children per prefix per step, optional
+    Gumbel noise) and sample-then-score (score `n_score` uniformly sampled
+    orders, re-simulate the best `width`).  The top-1% threshold of each set is
+    the ceil(q_samples/100)-th smallest of `q_samples` exact random orders (n!
+    is out of reach at n=16); uniform sampling needs q_samples / (samples at or
+    below it) simulations on average to reach it.  A search needs the 1-based
+    position of its first hit in its predicted order (its budget plus uniform
+    sampling's expectation if it has none).  `sur`, when given, is a trained
+    scorer used as is (no training).  Prints one JSON summary line."""
     import json
     import time
 
     import synth
 
     torch = _torch()
-    t0 = time.perf_counter()
-    tr = [synth.draw_set(train_workload, s) for s in range(train_sets)]
-    table = SetTable.build(synth.WORKLOADS[train_workload].model, tr)
-    data = mask_suffixes(exact_samples(table, per_set, seed=seed, target="quantile"), mask_frac, seed + 1)
-    sur = nn.Surrogate(_init_params(seed + 2))
-    log = train(sur, table, data, steps=steps, batch=batch, lr=lr, warmup=min(200, steps // 10), seed=seed + 3,
-                log_every=max(1, steps // 8))
-    torch.cuda.synchronize()
-    out(json.dumps({"phase": "train", "sets": train_sets, "n": table.n, "samples": data.count,
-                    "mask_frac": mask_frac, "train_s": round(time.perf_counter() - t0, 2), "loss": log}),
-        flush=True)
-    del data
+    if sur is None:
+        t0 = time.perf_counter()
+        tr = [synth.draw_set(train_workload, s) for s in range(train_sets)]
+        table = SetTable.build(synth.WORKLOADS[train_workload].model, tr)
+        data = mask_suffixes(exact_samples(table, per_set, seed=seed, target="quantile"), mask_frac, seed + 1)
+        sur = nn.Surrogate(_init_params(seed + 2))
+        log = train(sur, table, data, steps=steps, batch=batch, lr=lr, warmup=min(200, steps // 10),
+                    seed=seed + 3, log_every=max(1, steps // 8))
+        torch.cuda.synchronize()
+        out(json.dumps({"phase": "train", "sets": train_sets, "n": table.n, "samples": data.count,
+                        "mask_frac": mask_frac, "train_s": round(time.perf_counter() - t0, 2), "loss": log}),
+            flush=True)
+        del data
     model = synth.WORKLOADS[eval_workload].model
     ev = [synth.draw_set(eval_workload, s) for s in range(eval_sets)]
     etab = SetTable.build(model, ev)
@@ -477,31 +471,60 @@ def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets:
                       makespans=rms)
     ko_sync()
     k = max(1, math.ceil(q_samples / 100))
-    thr = np.array([ko_kth_smallest_i64(qms[s * q_samples:(s + 1) * q_samples], k) for s in range(S)])
+    thr, rexp = np.zeros(S, dtype=np.int64), np.zeros(S)
+    for s in range(S):
+        thr[s], hits = ko_kth_smallest_i64(qms[s * q_samples:(s + 1) * q_samples], k, with_count=True)
+        rexp[s] = q_samples / hits
     rnd = rms.cpu().numpy().reshape(S, width)
     t_exact = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    rows = []
+    rows = {"beam": [], "sample_then_score": [], "merged": []}
+    times = {}
+    found = {"beam": [], "sample_then_score": []}
+    for name in ("beam", "sample_then_score"):
+        t0 = time.perf_counter()
+        for s in range(S):
+            if name == "beam":
+                res = beam_search(sur, etab, s, width=width, max_children=max_children, temperature=temperature,
+                                  seed=seed + 20 + s)
+            else:
+                res = score_and_rerank(sur, etab, s, n_score=n_score, top_k=width, seed=seed + 30)
+            found[name].append(res)
+            rows[name].append(_search_row(res.exact, res.exact, thr[s], rexp[s]))
+        times[name] = round(time.perf_counter() - t0, 2)
+    # both searches' complete orders ranked together by the same scorer; the
+    # best `width` distinct ones are the merged search's exact budget
     for s in range(S):
-        res = beam_search(sur, etab, s, width=width, max_children=max_children)
-        hit_b = np.flatnonzero(res.exact <= thr[s])
-        hit_r = np.flatnonzero(rnd[s] <= thr[s])
-        rows.append((int(res.exact.min()), int(rnd[s].min()), len(hit_b), len(hit_r),
-                     int(hit_b[0]) + 1 if len(hit_b) else 0, int(hit_r[0]) + 1 if len(hit_r) else 0))
-    t_beam = time.perf_counter() - t0
-    a = np.array(rows, dtype=np.float64)
-    better = float(np.mean(a[:, 0] < a[:, 1]))
-    tie = float(np.mean(a[:, 0] == a[:, 1]))
-    out(json.dumps({"phase": "beam_vs_random", "eval_sets": S, "n": etab.n, "width": width,
-                    "max_children": max_children,
-                    "exact_budget_per_set": width, "q_samples": q_samples,
-                    "best_ratio_beam_over_random_mean": float(np.mean(a[:, 0] / a[:, 1])),
-                    "beam_better_frac": better, "tie_frac": tie,
-                    "beam_hits_top1pct_mean": float(a[:, 2].mean()), "random_hits_top1pct_mean": float(a[:, 3].mean()),
-                    "sets_beam_found_top1pct": float(np.mean(a[:, 2] > 0)),
-                    "sets_random_found_top1pct": float(np.mean(a[:, 3] > 0)),
-                    "exact_sampling_s": round(t_exact, 2), "beam_s": round(t_beam, 2)}), flush=True)
-    return rows
+        b, r = found["beam"][s], found["sample_then_score"][s]
+        orders = np.concatenate([b.orders, r.orders])
+        pred = np.concatenate([b.predicted, r.predicted])
+        exact = np.concatenate([b.exact, r.exact])
+        _, first = np.unique(orders, axis=0, return_index=True)
+        keep = first[np.lexsort((first, pred[first]))][:width]
+        rows["merged"].append(_search_row(exact[keep], exact[keep], thr[s], rexp[s]))
+    times["merged"] = times["beam"] + times["sample_then_score"]
+    rnd_best = rnd.min(axis=1)
+    rnd_hits = (rnd <= thr[:, None]).sum(axis=1)
+    summary = {"phase": "search_vs_random", "eval_sets": S, "n": etab.n, "exact_budget_per_set": width,
+               "q_samples": q_samples, "random_sims_expected_mean": float(rexp.mean()),
+               "sets_random_found_top1pct": float(np.mean(rnd_hits > 0)),
+               "random_hits_top1pct_mean": float(rnd_hits.mean()), "exact_sampling_s": round(t_exact, 2)}
+    for name, r in rows.items():
+        a = np.array(r, dtype=np.float64)
+        speed = rexp / a[:, 2]
+        summary[name] = {"sets_found_top1pct": float(np.mean(a[:, 1] > 0)),
+                         "hits_top1pct_mean": float(a[:, 1].mean()),
+                         "best_better_than_random_frac": float(np.mean(a[:, 0] < rnd_best)),
+                         "best_ratio_over_random_mean": float(np.mean(a[:, 0] / rnd_best)),
+                         "sims_to_top1pct_mean": float(a[:, 2].mean()),
+                         "speedup_geomean": float(np.exp(np.mean(np.log(speed)))),
+                         "speedup_median": float(np.median(speed)),
+                         "sets_at_least_10x": float(np.mean(speed >= 10.0)),
+                         "search_s": times[name]}
+    summary["beam"].update({"width": width, "max_children": max_children, "temperature": temperature})
+    summary["sample_then_score"].update({"n_score": n_score})
+    summary["merged"].update({"of": "beam and sample_then_score, ranked together by score"})
+    out(json.dumps(summary), flush=True)
+    return summary
 
 
 if __name__ == "__main__":
@@ -527,12 +550,16 @@ if __name__ == "__main__":
     ap.add_argument("--width", type=int, default=256)
     ap.add_argument("--max-children", type=int, default=2,
                     help="beam: at most this many children of one prefix per step (0 = no cap)")
+    ap.add_argument("--temperature", type=float, default=0.0, help="beam: Gumbel noise on each step's scores")
+    ap.add_argument("--beam-n-score", type=int, default=1 << 20,
+                    help="--beam: orders scored per set by sample-then-score")
     a = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     if a.beam:
         report_beam(train_sets=a.train_sets, per_set=a.per_set, eval_sets=a.eval_sets, width=a.width,
-                    steps=a.steps, batch=a.batch, lr=a.lr, max_children=a.max_children)
+                    steps=a.steps, batch=a.batch, lr=a.lr, max_children=a.max_children,
+                    temperature=a.temperature, n_score=a.beam_n_score)
         raise SystemExit(0)
     report(train_workload=a.train_workload, heldout_workload=a.heldout_workload, train_sets=a.train_sets,
            per_set=a.per_set, heldout=a.heldout, n_score=a.n_score, top_k=a.top_k, steps=a.steps,

@@ -332,3 +332,39 @@ def test_median_gain_is_the_half_probability_threshold(seed):
     assert 2 * int((m >= thr).sum()) >= n
     for v in range(thr + 1, 21):
         assert 2 * int((m >= v).sum()) < n
+
+
+def test_beam_step_oracle_hand_example():
+    """One beam step on n = 4, by hand.  Prefixes [2, 0] and [1, 3] (d = 2):
+    their unused kernels are {1, 3} and {0, 2}, so the candidates are
+    [2,0,1], [2,0,3], [1,3,0], [1,3,2] in that order, with positions (per
+    kernel 0..3): [1,2,0,16], [1,16,0,2], [2,0,16,1], [16,0,2,1].  With
+    scores [5, 3, 3, 4] and at most one child per prefix, the survivors are
+    candidate 1 (3 < 5) and candidate 2 (3 < 4); the others become +inf."""
+    from oracle import beam
+    pos, parent, kernel = beam.expand(np.array([[2, 0], [1, 3]]), 4)
+    assert pos.tolist() == [[1, 2, 0, 16], [1, 16, 0, 2], [2, 0, 16, 1], [16, 0, 2, 1]]
+    assert parent.tolist() == [0, 0, 1, 1] and kernel.tolist() == [1, 3, 0, 2]
+    ruled = beam.cap(np.array([5, 3, 3, 4], dtype=np.float32), 2, 1)
+    assert ruled.tolist() == [math.inf, 3.0, 3.0, math.inf]
+    # ties go to the first candidate of a prefix
+    assert beam.cap(np.array([2, 2, 7, 7], dtype=np.float32), 2, 1).tolist() == [2.0, math.inf, 7.0, math.inf]
+    assert beam.gather(np.array([[2, 0], [1, 3]]), parent, kernel, [2, 1]).tolist() == [[1, 3, 0], [2, 0, 3]]
+    # the empty prefix expands to every kernel at position 0
+    pos0, parent0, kernel0 = beam.expand(np.zeros((1, 0), dtype=np.int64), 3)
+    assert pos0.tolist() == [[0, 16, 16], [16, 0, 16], [16, 16, 0]] and kernel0.tolist() == [0, 1, 2]
+
+
+def test_beam_gumbel_noise_is_a_gumbel_variate():
+    """The noise maps SplitMix64's top 24 bits u to -log(-log u): pinned by the
+    published first SplitMix64 output for seed 1234567 (u = its top 24 bits
+    over 2^24) and by the Gumbel law's mean (the Euler-Mascheroni constant)
+    and variance (pi^2 / 6) over many counters."""
+    from oracle import beam
+    x = 6457827717110365317
+    u = ((x >> 40) + 0.5) / 2 ** 24
+    # float32 steps: within a few float32 ulps of the float64 value
+    assert beam.gumbel(1234567, 0) == pytest.approx(-math.log(-math.log(u)), rel=1e-5)
+    g = np.array([beam.gumbel(99, c) for c in range(20000)])
+    assert abs(g.mean() - 0.5772156649) < 0.03
+    assert abs(g.var() - math.pi ** 2 / 6) < 0.08

@@ -171,7 +171,43 @@ def test_scoring_reaches_top1pct_with_fewer_simulations_than_random(trained):
             f"recall@1% {np.mean(res.exact <= q.makespan):.3f}")
     gmean = float(np.exp(np.mean(np.log(ratios))))
     say(f"speedup to first top-1% order: geometric mean {gmean:.2f}x, per set {np.round(ratios, 2)}")
-    assert gmean > 1.0
+    print(f"[surrogate-gpu] speedup to first top-1% order: geometric mean {gmean:.2f}x, "
+          f"per set {np.round(ratios, 2)}", flush=True)
+    # this small fixture (128 training sets, 1500 steps, fixed seeds) is far
+    # below the reported recipes; it must still beat uniform sampling clearly
+    # and on most sets
+    assert gmean > 2.0
+    assert sum(r > 1.0 for r in ratios) >= 6
+
+
+def test_beam_step_kernels_match_oracle(trained):
+    """Each device step of the beam search against oracle/beam.py: the
+    candidates' positions and (parent, kernel) pairs, the per-prefix cap with
+    and without Gumbel noise, and the gathered prefixes."""
+    from oracle import beam as obeam
+    sur, _, _ = trained
+    rng = np.random.default_rng(5)
+    for n in (1, 5, 12, 16):
+        for d in sorted({0, n // 2, n - 1}):
+            W = 1 if d == 0 else 37
+            pre = np.array([rng.permutation(n)[:d] for _ in range(W)], dtype=np.uint8).reshape(W, d)
+            pos, cand = nn.beam_expand(torch.from_numpy(pre).to(DEV), n)
+            wpos, wpar, wker = obeam.expand(pre.astype(np.int64), n)
+            assert np.array_equal(pos.cpu().numpy(), wpos), (n, d)
+            c = cand.cpu().numpy()
+            assert np.array_equal(c >> 8, wpar) and np.array_equal(c & 255, wker), (n, d)
+            m = n - d
+            sc = rng.integers(0, 9, W * m).astype(np.float32)      # ties
+            for cap in (0, 1, 2, 5):
+                got = nn.beam_cap(torch.from_numpy(sc).to(DEV), W, m, cap).cpu().numpy()
+                assert np.array_equal(got, obeam.cap(sc, m, cap)), (n, d, cap)
+            scn = rng.normal(size=W * m).astype(np.float32)
+            got = nn.beam_cap(torch.from_numpy(scn).to(DEV), W, m, 0, 0.5, 77).cpu().numpy()
+            want = obeam.cap(scn, m, 0, 0.5, 77)
+            assert np.allclose(got, want, rtol=0, atol=1e-5), (n, d)
+            idx = rng.choice(W * m, size=min(W * m, 20), replace=False)
+            out = nn.beam_gather(torch.from_numpy(pre).to(DEV), cand, torch.from_numpy(idx).to(DEV))
+            assert np.array_equal(out.cpu().numpy(), obeam.gather(pre, wpar, wker, idx)), (n, d)
 
 
 def test_beam_search_finds_complete_orders(trained):
@@ -179,10 +215,11 @@ def test_beam_search_finds_complete_orders(trained):
     held = set_list(15, 0, 4)
     table = sg.SetTable.build(MODEL, held)
     for s, ks in enumerate(held):
-        res = sg.beam_search(sur, table, s, width=32)
+        res = sg.beam_search(sur, table, s, width=32, max_children=2, temperature=0.2 * s, seed=s)
         assert res.orders.shape == (32, 8)
         assert all(sorted(o.tolist()) == list(range(8)) for o in res.orders)
         assert len({o.tobytes() for o in res.orders}) == 32
+        assert np.all(np.diff(res.predicted) >= 0)  # ranked by the final (noise-free) score
         want = oracle.makespans_orders(MODEL.as_dict(), ks, res.orders.astype(np.int32))
         assert np.array_equal(res.exact, want)
         q = sg.top_quantile(MODEL, ks, 0.01)
