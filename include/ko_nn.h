@@ -56,8 +56,8 @@ size_t ko_nn_work_bytes(int32_t B, int32_t n);
  * zero gradients and Adam moments, refresh the BF16 copies.  Synchronous. */
 int ko_nn_load(void *state_dev, const float *params_host, void *hip_stream);
 
-/* ko_nn_read — copy master weights (which = 0) or gradients (which = 1) to host
- * float out[ko_nn_num_params()].  Synchronous. */
+/* ko_nn_read — copy master weights (which = 0), gradients (1) or Adam's first
+ * (2) or second (3) moments to host float out[ko_nn_num_params()].  Synchronous. */
 int ko_nn_read(const void *state_dev, int32_t which, float *out_host, void *hip_stream);
 
 /* ko_nn_features — the 8 per-kernel features (host).  out[n][8]:
@@ -106,9 +106,67 @@ int ko_nn_forward(const void *state_dev, const uint16_t *x_dev, int32_t B, int32
 int ko_nn_backward(void *state_dev, const uint16_t *x_dev, const float *t_dev, int32_t B, int32_t n,
                    float *loss_dev, void *work_dev, void *hip_stream);
 
-/* ko_nn_adam — one Adam step (bias-corrected, step >= 1) on the stored gradients. */
+/* ko_nn_adam — one Adam step (bias-corrected, step >= 1) on the stored gradients.
+ * The bias corrections 1 - beta^step are evaluated on the device, as in
+ * ko_nn_train_step, so the two give the same weights for the same step and rate. */
 int ko_nn_adam(void *state_dev, int32_t step, float lr, float beta1, float beta2, float eps,
                void *hip_stream);
+
+/* Adam's hyper-parameters and rate schedule, kept in device memory so that a
+ * training step reads them without the host and a captured step can be
+ * replayed.  The rate of step s is lr s / warmup while s <= warmup, then
+ * lr (lr_final + (1 - lr_final) (1 + cos(pi p)) / 2) with
+ * p = (s - warmup) / max(1, total - warmup). */
+typedef struct ko_nn_sched {
+    int32_t step;      /* Adam steps taken so far; a training step takes step + 1 and stores it */
+    int32_t warmup;    /* steps of linear warm-up (0 = none) */
+    int32_t total;     /* the step at which the cosine reaches lr * lr_final */
+    int32_t per_epoch; /* minibatches per pass over the sample rows (ko_nn_batch), >= 1 */
+    float lr;          /* peak rate */
+    float lr_final;    /* final rate as a fraction of lr (1 = constant rate after warm-up) */
+    float beta1, beta2, eps;
+    int32_t reserved[3];
+} ko_nn_sched;
+
+/* ko_nn_train_step — one training step on the device: forward, loss (loss_dev,
+ * float32[1], nullable), gradients (kept in the state block, equal bit for
+ * bit to ko_nn_backward's) and Adam on them with step sched->step + 1 and the
+ * schedule's rate, after which sched->step holds that step.  13 launches on
+ * hip_stream: no host synchronisation, no allocation and no memset, so a
+ * stream capture of it replays as a training step (see ko_nn_step_capture).
+ * sched_dev: device ko_nn_sched.  Errors: KO_EINVAL. */
+int ko_nn_train_step(void *state_dev, const uint16_t *x_dev, const float *t_dev, int32_t B, int32_t n,
+                     ko_nn_sched *sched_dev, float *loss_dev, void *work_dev, void *hip_stream);
+
+/* ko_nn_batch — a step's minibatch chosen on the device: sample b is row
+ * r = perm[(sched->step mod sched->per_epoch) B + b] (perm: int64, device, at
+ * least per_epoch B entries), with the tokens of ko_nn_tokens and the targets
+ * of ko_nn_targets for that row (x[B][n][32], t[B]).  Run before
+ * ko_nn_train_step, it takes the steps' minibatches in the order of perm. */
+int ko_nn_batch(const float *feat_dev, const int32_t *set_of_dev, const uint8_t *pos_dev,
+                const int64_t *makespans_dev, const int64_t *center_dev, const int64_t *scale_dev,
+                const int64_t *perm_dev, const ko_nn_sched *sched_dev, int32_t B, int32_t n, uint16_t *x_dev,
+                float *t_dev, void *hip_stream);
+
+/* An instantiated HIP graph of ko_nn_batch followed by ko_nn_train_step. */
+typedef struct ko_nn_graph ko_nn_graph;
+
+/* ko_nn_step_capture — capture ko_nn_batch + ko_nn_train_step with these
+ * arguments on hip_stream (a created stream, not the null stream).  Each
+ * replay is one training step on the next minibatch: the schedule's step
+ * advances on the device.  The graph holds every address given: they must
+ * outlive it; a caller that rewrites perm (a new pass) does so between
+ * replays, on the replay stream.  Errors: KO_EINVAL, KO_EHIP. */
+int ko_nn_step_capture(void *state_dev, const float *feat_dev, const int32_t *set_of_dev, const uint8_t *pos_dev,
+                       const int64_t *makespans_dev, const int64_t *center_dev, const int64_t *scale_dev,
+                       const int64_t *perm_dev, ko_nn_sched *sched_dev, int32_t B, int32_t n, uint16_t *x_dev,
+                       float *t_dev, float *loss_dev, void *work_dev, void *hip_stream, ko_nn_graph **out);
+
+/* ko_nn_graph_launch — replay a captured step on hip_stream. */
+int ko_nn_graph_launch(ko_nn_graph *graph, void *hip_stream);
+
+/* ko_nn_graph_destroy — wait for the device, free the graph (NULL is a no-op). */
+int ko_nn_graph_destroy(ko_nn_graph *graph);
 
 /* ko_nn_layer1_table — the first layer of one set, tabulated for scoring:
  * table[i][p][256] (float32, device, n*17*256 floats) = relu of the first

@@ -38,6 +38,7 @@ constexpr size_t kB3 = kW3 + (size_t)kHid * kHid;
 constexpr size_t kW4 = kB3 + kHid;
 constexpr size_t kB4 = kW4 + kHid;
 constexpr size_t kNP = kB4 + 1;                  // 140289
+static_assert(kB4 == kW4 + kHid, "db4 follows dw4");
 constexpr size_t kNPad = (kNP + 63) / 64 * 64;   // 140352
 
 struct State {
@@ -264,34 +265,155 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs a)
             }
 }
 
-// C[r][c] = sum_z P[z][r][c], z ascending
-__global__ void splitk_reduce_kernel(const float *P, int64_t splits, int32_t M, int32_t N, float *C,
-                                     int64_t ldc)
+// The products of a training step, whose reductions are short: the whole K
+// range of a workgroup (at most 256, a split-K chunk or a layer's width) is
+// staged into LDS in one load phase, with every global load of the panel in
+// flight at once, and then consumed by the MFMAs without further global
+// round trips.  64 x 64 output tiles of 4 waves (each 32 x 32, 2 x 2 MFMA
+// 16x16x32 tiles), so a 4096 x 256 product runs on 256 workgroups.
+//
+// An operand is k-contiguous (KC: element (r, k) at P[r * sr + k], 16-byte
+// loads along k stored as they are) or r-contiguous (element (r, k) at
+// P[k * sk + r]: 16-byte loads of 8 rows at one k, written transposed into
+// the LDS tile, where the 64 lanes of a wave take 64 consecutive k so that
+// their 2-byte writes fall into distinct dwords).  Either way every element
+// of the 64 x 256 tile is written, zero outside the operand and past kw, so
+// the MFMAs of a partial last k step add zeros.  The MFMA operands, the
+// k order of the accumulation and the epilogue are those of gemm_bf16_kernel,
+// so every output equals that kernel's bit for bit.
+constexpr int kPanelK = 256;
+constexpr int kPanelPitch = kPanelK + 8;   // elements; 132 dwords per row
+
+template <bool KC>
+__device__ __forceinline__ void load_panel(const uint16_t *P, int64_t sr, int64_t sk, int64_t r0, int32_t R,
+                                           int64_t k0, int32_t kw, uint16_t (*S)[kPanelPitch])
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)M * N)
-        return;
-    float s = 0.f;
-#pragma unroll 8
-    for (int64_t z = 0; z < splits; z++)
-        s += P[z * M * N + idx];
-    C[(idx / N) * ldc + idx % N] = s;
+    const int tid = threadIdx.x;
+    uint4 v[8];
+    if (KC) {
+        // 64 rows x 32 chunks of 8 k: chunk c = tid + 256 i is row c / 32, k (c % 32) * 8
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int c = tid + 256 * i;
+            const int r = c >> 5, kc = (c & 31) * 8;
+            v[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (r0 + r < R && kc < kw)
+                v[i] = *reinterpret_cast<const uint4 *>(P + (r0 + r) * sr + k0 + kc);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int c = tid + 256 * i;
+            *reinterpret_cast<uint4 *>(&S[c >> 5][(c & 31) * 8]) = v[i];
+        }
+    } else {
+        // thread t takes k = t and the 8 chunks of 8 rows at that k
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            v[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (tid < kw && r0 + 8 * i < R)
+                v[i] = *reinterpret_cast<const uint4 *>(P + (k0 + tid) * sk + r0 + 8 * i);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const uint32_t w[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+#pragma unroll
+            for (int e = 0; e < 8; e++)
+                S[8 * i + e][tid] = (uint16_t)(w[e >> 1] >> (16 * (e & 1)));
+        }
+    }
+}
+
+template <bool AK, bool BK>
+__global__ __launch_bounds__(256) void panel_gemm_kernel(GemmArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[kTile][kPanelPitch];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kTile][kPanelPitch];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t m0 = (int64_t)blockIdx.x * kTile;
+    const int64_t n0 = (int64_t)blockIdx.y * kTile;
+    const int64_t kb = a.P ? (int64_t)blockIdx.z * a.kchunk : 0;
+    const int64_t ke = a.P ? min((int64_t)a.K, kb + a.kchunk) : (int64_t)a.K;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+            acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kk = (lane >> 4) * 8;
+    for (int64_t p0 = kb; p0 < ke; p0 += kPanelK) {
+        const int kw = (int)min((int64_t)kPanelK, ke - p0);
+        const int ksteps = (kw + kKStep - 1) / kKStep;
+        // A(m, k): k-contiguous rows of pitch sam, or m-contiguous rows of pitch sak
+        load_panel<AK>(a.A, a.sam, a.sak, m0, a.M, p0, kw, As);
+        load_panel<BK>(a.B, a.sbn, a.sbk, n0, a.N, p0, kw, Bs);
+        __syncthreads();
+        for (int ks = 0; ks < ksteps; ks++) {
+            bf16x8 af[2], bfr[2];
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+                af[i] = *reinterpret_cast<const bf16x8 *>(&As[wm * 32 + i * 16 + (lane & 15)][ks * kKStep + kk]);
+#pragma unroll
+            for (int j = 0; j < 2; j++)
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn * 32 + j * 16 + (lane & 15)][ks * kKStep + kk]);
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int64_t row = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + e;
+                const int64_t col = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (row >= a.M || col >= a.N)
+                    continue;
+                float v = acc[i][j][e];
+                if (a.P) {
+                    a.P[(int64_t)blockIdx.z * a.M * a.N + row * a.N + col] = v;
+                    continue;
+                }
+                if (a.epi == kEpiMask) {
+                    v = (a.zref[row * a.ldz + col] > 0.f) ? v : 0.f;
+                } else if (a.bias) {
+                    v += a.bias[col];
+                }
+                if (a.C)
+                    a.C[row * a.ldc + col] = v;
+                if (a.Cb)
+                    a.Cb[row * a.ldcb + col] = to_bf16(a.epi == kEpiRelu ? fmaxf(v, 0.f) : v);
+            }
 }
 
 // ------------------------------------------------------------------ small kernels
 
-// S[b][c] = sum_j relu(Z1[b*n+j][c]); also its BF16 copy.
-__global__ void pool_kernel(const float *Z1, int32_t B, int32_t n, float *S, uint16_t *Sb)
+// S[b][c] = sum_j relu(Z1[b*n+j][c]); also its BF16 copy, and the count of
+// the sample's tokens with Z1 > 0 in column c (the bias gradient db1 is the
+// column sum of dS times that count).
+__global__ void pool_kernel(const float *Z1, int32_t B, int32_t n, float *S, uint16_t *Sb, uint8_t *cnt)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)B * kHid)
         return;
     const int64_t b = idx / kHid, c = idx % kHid;
     float s = 0.f;
-    for (int j = 0; j < n; j++)
-        s += fmaxf(Z1[(b * n + j) * kHid + c], 0.f);
+    int k = 0;
+    for (int j = 0; j < n; j++) {
+        const float z = Z1[(b * n + j) * kHid + c];
+        s += fmaxf(z, 0.f);
+        k += z > 0.f;
+    }
     S[idx] = s;
     Sb[idx] = to_bf16(s);
+    cnt[idx] = (uint8_t)k;
 }
 
 __device__ inline float wave_sum(float v)
@@ -334,105 +456,243 @@ __global__ __launch_bounds__(256) void out_forward_kernel(const uint16_t *A3b, c
         y[b] = s + master[kB4];
 }
 
-// loss = mean (y - t)^2 ; dy = 2 (y - t) / B   (single workgroup)
-__global__ __launch_bounds__(256) void loss_kernel(const float *y, const float *t, int32_t B, float *dy,
-                                                   float *loss)
+// The output layer, forward and backward, one wave per sample: y = A3b . w4b
+// + b4 (the sum of out_forward_kernel), d = y - t, dy = 2 d / B, the squared
+// error d^2 (the loss is their column sum), and dZ3 = dy w4b [Z3 > 0] in
+// float32 and BF16.  With `sched` set, the first thread advances the step
+// counter: the step's later kernels (the Adam update) read the new value and
+// the step's earlier ones (minibatch selection) have read the old one.
+__global__ __launch_bounds__(256) void head_kernel(const uint16_t *A3b, const uint16_t *wb, const float *master,
+                                                   const float *Z3, const float *t, int32_t B, float *y,
+                                                   float *dy, float *sq, float *dZ3, uint16_t *dZ3b,
+                                                   ko_nn_sched *sched)
 {
-    __shared__ float red[4];
-    float s = 0.f;
-    for (int64_t b = threadIdx.x; b < B; b += blockDim.x) {
-        const float d = y[b] - t[b];
-        s += d * d;
-        dy[b] = 2.f * d / (float)B;
-    }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0 && loss)
-        *loss = s / (float)B;
-}
-
-// dZ3[b][c] = dy[b] * w4b[c] * [Z3 > 0]   (fp32 and bf16)
-__global__ void out_backward_kernel(const float *dy, const uint16_t *wb, const float *Z3, int32_t B,
-                                    float *dZ3, uint16_t *dZ3b)
-{
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)B * kHid)
+    if (sched && blockIdx.x == 0 && threadIdx.x == 0)
+        sched->step += 1;
+    // the wave index is uniform across the wave (see out_forward_kernel)
+    const int64_t b = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= B)
         return;
-    const int64_t b = idx / kHid, c = idx % kHid;
-    const float v = (Z3[idx] > 0.f) ? dy[b] * from_bf16(wb[kW4 + c]) : 0.f;
-    dZ3[idx] = v;
-    dZ3b[idx] = to_bf16(v);
+    float s = 0.f;
+    for (int c = lane; c < kHid; c += 64)
+        s += from_bf16(A3b[b * kHid + c]) * from_bf16(wb[kW4 + c]);
+    // the xor butterfly leaves the same sum, bit for bit, in every lane
+    s = wave_sum(s);
+    const float yb = s + master[kB4];
+    const float d = yb - t[b];
+    const float g = 2.f * d / (float)B;
+    if (lane == 0) {
+        y[b] = yb;
+        dy[b] = g;
+        sq[b] = d * d;
+    }
+    for (int c = lane; c < kHid; c += 64) {
+        const float v = (Z3[b * kHid + c] > 0.f) ? g * from_bf16(wb[kW4 + c]) : 0.f;
+        dZ3[b * kHid + c] = v;
+        dZ3b[b * kHid + c] = to_bf16(v);
+    }
 }
 
-// Column sums in two deterministic stages.  Stage 1: workgroup g covers rows
-// [g*chunk, (g+1)*chunk) and thread c adds w(r) * X(r, c) down column c
-// (coalesced across threads); thread `cols` adds w(r) alone when `with_w` is
-// set.  X(r, c) is float32 (Xf) or bf16 (Xb) with row pitch ld; w(r) is
-// wrow[r] or 1.  Stage 2 adds the partials of the chunks in order.
-__global__ __launch_bounds__(320) void colsum_partial_kernel(const float *Xf, const uint16_t *Xb,
-                                                             int64_t ld, int64_t rows, int32_t cols,
-                                                             const float *wrow, int32_t with_w,
-                                                             int64_t chunk, float *part)
+// dZ1[r][c] = dS[r / n][c] [Z1[r][c] > 0], stored as BF16 (the token rows'
+// only use): one wave per token row, four columns per lane.
+__global__ __launch_bounds__(256) void dz1_kernel(const float *dS, const float *Z1, int64_t T, int32_t n,
+                                                  uint16_t *dZ1b)
 {
+    // the row is uniform across the wave, so the bounds check is a scalar branch
+    const int64_t r = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (r >= T)
+        return;
+    const int c = (threadIdx.x & 63) * 4;
+    const float4 z = *reinterpret_cast<const float4 *>(Z1 + r * kHid + c);
+    const float4 d = *reinterpret_cast<const float4 *>(dS + (r / n) * kHid + c);
+    uint2 o;
+    o.x = (uint32_t)to_bf16(z.x > 0.f ? d.x : 0.f) | ((uint32_t)to_bf16(z.y > 0.f ? d.y : 0.f) << 16);
+    o.y = (uint32_t)to_bf16(z.z > 0.f ? d.z : 0.f) | ((uint32_t)to_bf16(z.w > 0.f ? d.w : 0.f) << 16);
+    *reinterpret_cast<uint2 *>(dZ1b + r * kHid + c) = o;
+}
+
+// Column sums of up to five row-major matrices in one launch, stage 1 of 2:
+// workgroup g of problem q covers rows [g chunk, (g + 1) chunk) and thread c
+// adds w(r) X(r, c) down column c in row order (w(r) = wrow[r] or 1; X float32
+// or BF16 with row pitch ld, times the count Xm(r, c) when Xm is set); with
+// `with_w` thread `cols` adds w(r) alone.  The partials go to
+// part[g][cols + with_w]; the finish kernel adds them.
+struct ColProblem {
+    const float *Xf;
+    const uint16_t *Xb;
+    const uint8_t *Xm;
+    const float *wrow;
+    float *part;
+    int64_t ld, rows, chunk;
+    int32_t cols, with_w, first;   // first: this problem's first workgroup
+    int32_t pad;
+};
+constexpr int kColProblems = 5;
+struct ColMulti {
+    ColProblem p[kColProblems];
+    int32_t count;
+};
+
+__global__ __launch_bounds__(320) void colsum_multi_kernel(ColMulti a)
+{
+    int q = 0;
+    for (int i = 1; i < a.count; i++)
+        q = ((int)blockIdx.x >= a.p[i].first) ? i : q;
+    const ColProblem &p = a.p[q];
     const int c = threadIdx.x;
-    const int width = cols + (with_w ? 1 : 0);
+    const int width = p.cols + p.with_w;
     if (c >= width)
         return;
-    const int64_t r0 = (int64_t)blockIdx.x * chunk;
-    const int64_t r1 = min(rows, r0 + chunk);
+    const int64_t g = (int64_t)blockIdx.x - p.first;
+    const int64_t r0 = g * p.chunk;
+    const int64_t r1 = min(p.rows, r0 + p.chunk);
     float s = 0.f;
+#pragma unroll 8
     for (int64_t r = r0; r < r1; r++) {
-        const float w = wrow ? wrow[r] : 1.f;
-        if (c < cols)
-            s += w * (Xf ? Xf[r * ld + c] : from_bf16(Xb[r * ld + c]));
-        else
+        const float w = p.wrow ? p.wrow[r] : 1.f;
+        if (c < p.cols) {
+            float x = p.Xf ? p.Xf[r * p.ld + c] : from_bf16(p.Xb[r * p.ld + c]);
+            if (p.Xm)
+                x *= (float)p.Xm[r * p.ld + c];
+            s += w * x;
+        } else {
             s += w;
+        }
     }
-    part[(int64_t)blockIdx.x * width + c] = s;
+    p.part[g * width + c] = s;
 }
 
-// Stage 2: one workgroup per column; thread t adds chunks t, t + 256, ... in
-// order, then a fixed tree combines the threads (deterministic).
-__global__ __launch_bounds__(256) void colsum_finish_kernel(const float *part, int64_t chunks, int32_t width,
-                                                            float *out, int32_t cols, int32_t out_extra)
+// Adam on one parameter: float32 master weight, moments and BF16 copy, with
+// the bias corrections c1 = 1 - beta1^s and c2 = 1 - beta2^s of step s.
+struct AdamArgs {
+    float *master, *m, *v;
+    uint16_t *wb;
+    float lr, b1, b2, eps, c1, c2;
+};
+
+__device__ inline void adam_update(int64_t i, float gi, const AdamArgs &a)
 {
-    __shared__ float red[4];
-    const int c = blockIdx.x;
-    float s = 0.f;
-#pragma unroll 4
-    for (int64_t g = threadIdx.x; g < chunks; g += 256)
-        s += part[g * width + c];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0)
-        out[c < cols ? c : out_extra] = s;
+    const float mi = a.b1 * a.m[i] + (1.f - a.b1) * gi;
+    const float vi = a.b2 * a.v[i] + (1.f - a.b2) * gi * gi;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    const float wi = a.master[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+    a.master[i] = wi;
+    a.wb[i] = to_bf16(wi);
 }
 
-// dZ1[r][c] = dS[r / n][c] * [Z1[r][c] > 0]   (fp32 and bf16)
-__global__ void dz1_kernel(const float *dS, const float *Z1, int32_t B, int32_t n, float *dZ1,
-                           uint16_t *dZ1b)
+// A float every lane holds, made explicitly wave-uniform.
+__device__ inline float uniform_f32(float v)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)B * n * kHid)
-        return;
-    const int64_t r = idx / kHid, c = idx % kHid;
-    const float v = (Z1[idx] > 0.f) ? dS[(r / n) * kHid + c] : 0.f;
-    dZ1[idx] = v;
-    dZ1b[idx] = to_bf16(v);
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-__global__ void adam_kernel(float *w, const float *g, float *m, float *v, int64_t count, float lr,
-                            float b1, float b2, float eps, float c1, float c2, uint16_t *wb)
+// The step-dependent values of an update, evaluated once per thread at kernel
+// entry while every lane is active (they are uniform: step and rate come from
+// the caller or the schedule).
+__device__ inline void adam_prepare(AdamArgs &a, int32_t step)
 {
+    a.c1 = uniform_f32(1.f - powf(a.b1, (float)step));
+    a.c2 = uniform_f32(1.f - powf(a.b2, (float)step));
+}
+
+// The rate of step s: linear warm-up over `warmup` steps to lr, then half a
+// cosine from lr down to lr * lr_final at step `total`.
+__device__ inline float sched_rate(const ko_nn_sched &h, int32_t s)
+{
+    if (s <= h.warmup)
+        return h.lr * (float)s / (float)max(1, h.warmup);
+    const float p = (float)(s - h.warmup) / (float)max(1, h.total - h.warmup);
+    return h.lr * (h.lr_final + (1.f - h.lr_final) * 0.5f * (1.f + cosf(3.14159265358979f * p)));
+}
+
+__global__ void adam_kernel(const float *g, int64_t count, AdamArgs a, int32_t step)
+{
+    adam_prepare(a, step);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count)
+    if (i < count)
+        adam_update(i, g[i], a);
+}
+
+// Stage 2 of every reduction of a step, in one launch: the weight gradients
+// from their split-K partials and the bias, output-layer and loss sums from
+// their column partials.  A reduction is a segment: `count` outputs, each the
+// sum of `rows` partials at stride `stride`.  A workgroup takes 32
+// consecutive outputs of one segment; its 8 thread groups add 8 consecutive
+// ranges of the partials, each in order, and the first group adds the 8
+// range sums in order (a fixed order: deterministic).  Writes the gradients
+// (and the loss, which is the sum over B); with `sched` set it then applies
+// Adam to each parameter with step sched->step and its rate.  A segment with
+// few partials (at most kFinShort) uses one group: 256 outputs per workgroup.
+struct Segment {
+    const float *P;
+    int64_t stride;
+    int32_t rows, count;
+    int32_t param;   // the gradient of output o is parameter param + o; -1: the loss
+    int32_t first;   // first workgroup
+    int32_t groups;  // 1 or kFinGroups
+    int32_t pad;
+};
+constexpr int kSegments = 8;
+constexpr int kFinGroups = 8, kFinShort = 32;
+struct FinishArgs {
+    Segment seg[kSegments];
+    int32_t count;
+    int32_t B;
+    float *grad, *loss_out;
+    const ko_nn_sched *sched;
+    AdamArgs adam;
+};
+
+__global__ __launch_bounds__(256) void finish_kernel(FinishArgs a)
+{
+    __shared__ float part[kFinGroups][256 / kFinGroups];
+    AdamArgs ad = a.adam;
+    if (a.sched) {
+        const ko_nn_sched h = *a.sched;
+        ad.lr = uniform_f32(sched_rate(h, h.step));
+        ad.b1 = h.beta1, ad.b2 = h.beta2, ad.eps = h.eps;
+        adam_prepare(ad, h.step);
+    }
+    int q = 0;
+    for (int i = 1; i < a.count; i++)
+        q = ((int)blockIdx.x >= a.seg[i].first) ? i : q;
+    const Segment &sg = a.seg[q];
+    // (shifts, not divisions: the group count is 1 or 8)
+    const bool wide = sg.groups > 1;
+    const int per = wide ? 256 / kFinGroups : 256;   // outputs per workgroup
+    const int ol = wide ? (int)threadIdx.x % per : (int)threadIdx.x;
+    const int grp = wide ? (int)threadIdx.x / per : 0;
+    const int32_t lo = wide ? (sg.rows * grp) / kFinGroups : 0;
+    const int32_t hi = wide ? (sg.rows * (grp + 1)) / kFinGroups : sg.rows;
+    const int64_t o = (int64_t)(blockIdx.x - sg.first) * per + ol;
+    float g = 0.f;
+    if (o < sg.count) {
+#pragma unroll 8
+        for (int32_t z = lo; z < hi; z++)
+            g += sg.P[z * sg.stride + o];
+    }
+    if (wide) {
+        part[grp][ol] = g;
+        __syncthreads();
+        if (grp != 0)
+            return;
+#pragma unroll
+        for (int i = 1; i < kFinGroups; i++)
+            g += part[i][ol];
+    }
+    if (o >= sg.count)
         return;
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-    w[i] = wi;
-    wb[i] = to_bf16(wi);
+    if (sg.param < 0) {
+        if (a.loss_out)
+            *a.loss_out = g / (float)a.B;
+        return;
+    }
+    const int64_t param = sg.param + o;
+    a.grad[param] = g;
+    if (a.sched)
+        adam_update(param, g, ad);
 }
 
 __global__ void refresh_kernel(const float *w, uint16_t *wb, int64_t count)
@@ -449,7 +709,27 @@ __global__ void zero_f32_kernel(float *p, int64_t count)
         p[i] = 0.f;
 }
 
-// x[b][i][0..7] = bf16(feat[set][i][.]); x[b][i][8 + pos] = 1; rest 0.
+// x[b][i][0..7] = bf16(feat[set][i][.]); x[b][i][8 + pos] = 1; rest 0: input
+// f of token i of sample row r.
+__device__ inline uint16_t token_value(const float *feat, const int32_t *set_of, const uint8_t *pos, int64_t r,
+                                       int64_t i, int f, int32_t n)
+{
+    const int64_t s = set_of ? set_of[r] : 0;
+    if (f < KO_NN_FEAT)
+        return to_bf16(feat[(s * n + i) * KO_NN_FEAT + f]);
+    if (f < KO_NN_FEAT + KO_NN_POS)
+        return (pos[r * n + i] == (uint8_t)(f - KO_NN_FEAT)) ? (uint16_t)0x3F80 : (uint16_t)0;
+    return 0;
+}
+
+// (makespan[r] - center[s]) / scale[s] for sample row r of set s = set_of[r]
+__device__ inline float target_value(const int64_t *makespans, const int32_t *set_of, const int64_t *center,
+                                     const int64_t *scale, int64_t r)
+{
+    const int64_t s = set_of ? set_of[r] : 0;
+    return (float)((double)(makespans[r] - center[s]) / (double)scale[s]);
+}
+
 __global__ void tokens_kernel(const float *feat, const int32_t *set_of, const uint8_t *pos,
                               const int64_t *rows, int32_t B, int32_t n, uint16_t *x)
 {
@@ -457,17 +737,8 @@ __global__ void tokens_kernel(const float *feat, const int32_t *set_of, const ui
     if (idx >= (int64_t)B * n * kIn)
         return;
     const int64_t t = idx / kIn;
-    const int f = (int)(idx % kIn);
-    const int64_t b = t / n, i = t % n;
-    const int64_t r = rows ? rows[b] : b;
-    const int64_t s = set_of ? set_of[r] : 0;
-    uint16_t v = 0;
-    if (f < KO_NN_FEAT) {
-        v = to_bf16(feat[(s * n + i) * KO_NN_FEAT + f]);
-    } else if (f < KO_NN_FEAT + KO_NN_POS) {
-        v = (pos[r * n + i] == (uint8_t)(f - KO_NN_FEAT)) ? (uint16_t)0x3F80 : (uint16_t)0;
-    }
-    x[idx] = v;
+    const int64_t b = t / n;
+    x[idx] = token_value(feat, set_of, pos, rows ? rows[b] : b, t % n, (int)(idx % kIn), n);
 }
 
 // t[b] = (makespan[r] - center[s]) / scale[s] with r = rows[b] (or b), s = set_of[r]
@@ -477,9 +748,27 @@ __global__ void targets_kernel(const int64_t *makespans, const int32_t *set_of, 
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B)
         return;
-    const int64_t r = rows ? rows[b] : b;
-    const int64_t s = set_of ? set_of[r] : 0;
-    t[b] = (float)((double)(makespans[r] - center[s]) / (double)scale[s]);
+    t[b] = target_value(makespans, set_of, center, scale, rows ? rows[b] : b);
+}
+
+// A training step's minibatch, chosen on the device: sample b is row
+// perm[(step mod per_epoch) B + b] with step = sched->step, the steps taken so
+// far; its tokens and target are those of tokens_kernel and targets_kernel.
+__global__ void batch_kernel(const float *feat, const int32_t *set_of, const uint8_t *pos, const int64_t *makespans,
+                             const int64_t *center, const int64_t *scale, const int64_t *perm,
+                             const ko_nn_sched *sched, int32_t B, int32_t n, uint16_t *x, float *t)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // a count below 1 is taken as 1 and the step as unsigned, so the slice
+    // always starts inside the first per_epoch B entries of perm
+    const uint32_t pe = (uint32_t)max(1, sched->per_epoch);
+    const int64_t *rows = perm + (int64_t)((uint32_t)sched->step % pe) * B;
+    if (idx < B)
+        t[idx] = target_value(makespans, set_of, center, scale, rows[idx]);
+    if (idx >= (int64_t)B * n * kIn)
+        return;
+    const int64_t tk = idx / kIn;
+    x[idx] = token_value(feat, set_of, pos, rows[tk / n], tk % n, (int)(idx % kIn), n);
 }
 
 // Within-set ranks: ranks[s * per + i] = position of sample i of set s when
@@ -852,10 +1141,22 @@ int fail(int code, const char *fmt, ...)
 
 unsigned grid1(int64_t count) { return (unsigned)((count + 255) / 256); }
 
+}  // namespace
+
+struct ko_nn_graph {
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
 struct Work {
-    float *P;  // split-K and column-sum partials
-    float *Z1, *S, *Z2, *Z3, *y, *dy, *dZ3, *dZ2, *dS, *dZ1;
+    float *P1, *P2, *P3;                    // split-K partials of dW1, dW2, dW3
+    float *Pb1, *Pout, *Pb3, *Pb2, *Ploss;  // column-sum partials
+    float *Z1, *S, *Z2, *Z3, *y, *dy, *sq, *dZ3, *dZ2, *dS;
     uint16_t *Sb, *A2b, *A3b, *dZ3b, *dZ2b, *dZ1b;
+    uint8_t *cnt;   // tokens of a sample with Z1 > 0, per column
 };
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -871,14 +1172,17 @@ int64_t split_count(int64_t K, int64_t cap)
 // the ordered reduction stays short; column sums use chunks of >= 16 rows
 constexpr int64_t kSplitCapW1 = 256, kSplitCapW = 32, kColChunks = 4096, kColRows = 16;
 
-size_t partial_floats(int64_t B, int64_t n)
+// rows per chunk and chunk count of a column sum over `rows` rows
+int64_t col_chunk(int64_t rows) { return std::max<int64_t>(kColRows, (rows + kColChunks - 1) / kColChunks); }
+int64_t col_chunks(int64_t rows) { return (rows + col_chunk(rows) - 1) / col_chunk(rows); }
+
+// K per split-K workgroup (a multiple of the MFMA k step) and the splits used
+int64_t split_chunk(int64_t K, int64_t cap)
 {
-    const int64_t T = B * n;
-    size_t need = (size_t)split_count(T, kSplitCapW1) * kHid * kIn;
-    need = std::max(need, (size_t)split_count(B, kSplitCapW) * kHid * kHid);
-    need = std::max(need, (size_t)kColChunks * (kHid + 1));
-    return need;
+    const int64_t splits = split_count(K, cap);
+    return ((K + splits - 1) / splits + kKStep - 1) / kKStep * kKStep;
 }
+int64_t splits_used(int64_t K, int64_t cap) { return (K + split_chunk(K, cap) - 1) / split_chunk(K, cap); }
 
 Work work_of(void *p, int64_t B, int64_t n, size_t *total)
 {
@@ -889,11 +1193,17 @@ Work work_of(void *p, int64_t B, int64_t n, size_t *total)
         off += align256(bytes);
         return r;
     };
-    const int64_t BH = B * kHid, TH = B * n * kHid;
+    const int64_t T = B * n, BH = B * kHid, TH = T * kHid;
     Work w;
-    w.P = (float *)take(partial_floats(B, n) * 4);
+    w.P1 = (float *)take((size_t)splits_used(T, kSplitCapW1) * kHid * kIn * 4);
+    w.P2 = (float *)take((size_t)splits_used(B, kSplitCapW) * kHid * kHid * 4);
+    w.P3 = (float *)take((size_t)splits_used(B, kSplitCapW) * kHid * kHid * 4);
+    w.Pb1 = (float *)take((size_t)col_chunks(B) * kHid * 4);
+    w.Pout = (float *)take((size_t)col_chunks(B) * (kHid + 1) * 4);
+    w.Pb3 = (float *)take((size_t)col_chunks(B) * kHid * 4);
+    w.Pb2 = (float *)take((size_t)col_chunks(B) * kHid * 4);
+    w.Ploss = (float *)take((size_t)col_chunks(B) * 4);
     w.Z1 = (float *)take(TH * 4);
-    w.dZ1 = (float *)take(TH * 4);
     w.dZ1b = (uint16_t *)take(TH * 2);
     w.S = (float *)take(BH * 4);
     w.Sb = (uint16_t *)take(BH * 2);
@@ -908,6 +1218,8 @@ Work work_of(void *p, int64_t B, int64_t n, size_t *total)
     w.dS = (float *)take(BH * 4);
     w.y = (float *)take(B * 4);
     w.dy = (float *)take(B * 4);
+    w.sq = (float *)take(B * 4);
+    w.cnt = (uint8_t *)take(BH);
     *total = off;
     return w;
 }
@@ -919,10 +1231,53 @@ bool nt_eligible(const GemmArgs &a)
            a.sbn % 8 == 0 && aligned(a.A) && aligned(a.B);
 }
 
+// The panel kernel takes each operand k-contiguous (K % 8 == 0) or
+// r-contiguous (rows M or N % 8 == 0), with 16-byte aligned bases and pitches.
+bool panel_operand_ok(const void *p, int64_t sr, int64_t sk, int32_t R, int32_t K)
+{
+    if (((uintptr_t)p & 15u) != 0)
+        return false;
+    if (sk == 1)
+        return sr % 8 == 0 && K % 8 == 0;
+    return sr == 1 && sk % 8 == 0 && R % 8 == 0;
+}
+
+bool panel_eligible(const GemmArgs &a)
+{
+    return panel_operand_ok(a.A, a.sam, a.sak, a.M, a.K) && panel_operand_ok(a.B, a.sbn, a.sbk, a.N, a.K);
+}
+
+void launch_panel(const GemmArgs &a, dim3 grid, hipStream_t st)
+{
+    const bool ak = a.sak == 1, bk = a.sbk == 1;
+    if (ak && bk)
+        hipLaunchKernelGGL((panel_gemm_kernel<true, true>), grid, dim3(256), 0, st, a);
+    else if (ak)
+        hipLaunchKernelGGL((panel_gemm_kernel<true, false>), grid, dim3(256), 0, st, a);
+    else if (bk)
+        hipLaunchKernelGGL((panel_gemm_kernel<false, true>), grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((panel_gemm_kernel<false, false>), grid, dim3(256), 0, st, a);
+}
+
+// Above this many 128 x 128 tiles the NT kernel's larger tiles read the
+// operands fewer times than 64 x 64 panels; below it they leave CUs idle.
+constexpr int64_t kNtMinTiles = 1024;
+
 int gemm(const GemmArgs &a, hipStream_t st)
 {
     if (a.M <= 0 || a.N <= 0 || a.K <= 0)
         return KO_OK;
+    const int64_t nt_tiles = (a.M + kNtTile - 1) / kNtTile * (a.N / kNtTile);
+    // (a product with K = 32 is one k step: the NT kernel's smaller LDS
+    // footprint keeps more workgroups resident for its output-bound work)
+    const bool nt_better = nt_eligible(a) && (nt_tiles >= kNtMinTiles || a.K <= kKStep);
+    if (panel_eligible(a) && !nt_better) {
+        dim3 g((unsigned)((a.M + kTile - 1) / kTile), (unsigned)((a.N + kTile - 1) / kTile));
+        launch_panel(a, g, st);
+        NN_LAUNCHED();
+        return KO_OK;
+    }
     if (nt_eligible(a)) {
         dim3 g((unsigned)((a.M + kNtTile - 1) / kNtTile), (unsigned)(a.N / kNtTile));
         hipLaunchKernelGGL(gemm_nt_kernel, g, dim3(256), 0, st, a);
@@ -935,43 +1290,23 @@ int gemm(const GemmArgs &a, hipStream_t st)
     return KO_OK;
 }
 
-// Weight gradient C[M][N] (fp32, row pitch ldc) = sum over K of A(m,k) B(k,n),
-// with K split across workgroups and the partials added in a fixed order.
-int gemm_splitk(GemmArgs a, float *P, int64_t cap, hipStream_t st)
+// Split-K partial products of a weight gradient: workgroup z of the grid
+// stores sum over its K chunk of A(m,k) B(k,n) to P + z M N; the finish
+// kernel adds the splits_used(K, cap) partials in order.
+int gemm_partials(GemmArgs a, float *P, int64_t cap, hipStream_t st)
 {
     if (a.M <= 0 || a.N <= 0 || a.K <= 0)
         return KO_OK;
-    const int64_t splits = split_count(a.K, cap);
-    a.kchunk = ((a.K + splits - 1) / splits + kKStep - 1) / kKStep * kKStep;
-    const int64_t used = (a.K + a.kchunk - 1) / a.kchunk;
-    float *C = a.C;
-    const int64_t ldc = a.ldc;
+    a.kchunk = split_chunk(a.K, cap);
     a.P = P;
     a.C = nullptr;
     a.Cb = nullptr;
     dim3 grid((unsigned)((a.M + kTile - 1) / kTile), (unsigned)((a.N + kTile - 1) / kTile),
-              (unsigned)used);
-    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, st, a);
-    NN_LAUNCHED();
-    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid1((int64_t)a.M * a.N)), dim3(256), 0, st, P, used,
-                       a.M, a.N, C, ldc);
-    NN_LAUNCHED();
-    return KO_OK;
-}
-
-// out[c] = sum_r w(r) X(r, c) for c < cols, and out[out_extra] = sum_r w(r)
-// when with_w is set.
-int colsum(const float *Xf, const uint16_t *Xb, int64_t ld, int64_t rows, int32_t cols, const float *wrow,
-           bool with_w, float *out, int32_t out_extra, float *P, hipStream_t st)
-{
-    const int64_t chunk = std::max<int64_t>(kColRows, (rows + kColChunks - 1) / kColChunks);
-    const int64_t used = (rows + chunk - 1) / chunk;
-    const int32_t width = cols + (with_w ? 1 : 0);
-    hipLaunchKernelGGL(colsum_partial_kernel, dim3((unsigned)used), dim3(320), 0, st, Xf, Xb, ld, rows, cols,
-                       wrow, with_w ? 1 : 0, chunk, P);
-    NN_LAUNCHED();
-    hipLaunchKernelGGL(colsum_finish_kernel, dim3((unsigned)width), dim3(256), 0, st, P, used, width, out, cols,
-                       out_extra);
+              (unsigned)splits_used(a.K, cap));
+    if (panel_eligible(a))
+        launch_panel(a, grid, st);
+    else
+        hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, st, a);
     NN_LAUNCHED();
     return KO_OK;
 }
@@ -1018,7 +1353,7 @@ int forward_impl(const State &s, const uint16_t *x, int32_t B, int32_t n, float 
     if ((rc = gemm(a, st)))
         return rc;
     hipLaunchKernelGGL(pool_kernel, dim3(grid1((int64_t)B * kHid)), dim3(256), 0, st, w.Z1, B, n, w.S,
-                       w.Sb);
+                       w.Sb, w.cnt);
     NN_LAUNCHED();
     // A2 = relu(S W2^T + b2)
     a = gemm_args(w.Sb, kHid, 1, s.wb + kW2, 1, kHid, B, kHid, kHid);
@@ -1040,6 +1375,8 @@ int forward_impl(const State &s, const uint16_t *x, int32_t B, int32_t n, float 
     a.ldcb = kHid;
     if ((rc = gemm(a, st)))
         return rc;
+    if (!y)
+        return KO_OK;   // the training step's head kernel computes y
     hipLaunchKernelGGL(out_forward_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, st, w.A3b,
                        s.wb, s.master, B, y);
     NN_LAUNCHED();
@@ -1070,6 +1407,95 @@ int forward_positions_impl(const State &s, const float *T, const uint8_t *pos, i
         return rc;
     hipLaunchKernelGGL(out_forward_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, st, A3b, s.wb,
                        s.master, B, y);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+// Forward, loss and every gradient of a minibatch (13 launches, no host
+// synchronisation, nothing allocated); with `sched` set the step counter
+// advances and the finish kernel applies Adam, which makes this one training
+// step that a HIP graph can capture.
+int backward_impl(const State &s, const uint16_t *x, const float *t, int32_t B, int32_t n, float *loss, Work &w,
+                  ko_nn_sched *sched, hipStream_t st)
+{
+    int rc;
+    const int64_t T = (int64_t)B * n;
+    if ((rc = forward_impl(s, x, B, n, nullptr, w, st)))
+        return rc;
+    hipLaunchKernelGGL(head_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, st, w.A3b, s.wb, s.master, w.Z3,
+                       t, B, w.y, w.dy, w.sq, w.dZ3, w.dZ3b, sched);
+    NN_LAUNCHED();
+    // layer 3: dZ2 = (dZ3b W3b) [Z2 > 0]; dW3 = dZ3b^T A2b (split-K partials)
+    GemmArgs a = gemm_args(w.dZ3b, kHid, 1, s.wb + kW3, kHid, 1, B, kHid, kHid);
+    a.epi = kEpiMask;
+    a.zref = w.Z2;
+    a.ldz = kHid;
+    a.C = w.dZ2;
+    a.ldc = kHid;
+    a.Cb = w.dZ2b;
+    a.ldcb = kHid;
+    if ((rc = gemm(a, st)))
+        return rc;
+    if ((rc = gemm_partials(gemm_args(w.dZ3b, 1, kHid, w.A2b, kHid, 1, kHid, kHid, B), w.P3, kSplitCapW, st)))
+        return rc;
+    // layer 2: dS = dZ2b W2b; dW2 = dZ2b^T Sb
+    a = gemm_args(w.dZ2b, kHid, 1, s.wb + kW2, kHid, 1, B, kHid, kHid);
+    a.C = w.dS;
+    a.ldc = kHid;
+    if ((rc = gemm(a, st)))
+        return rc;
+    if ((rc = gemm_partials(gemm_args(w.dZ2b, 1, kHid, w.Sb, kHid, 1, kHid, kHid, B), w.P2, kSplitCapW, st)))
+        return rc;
+    // layer 1: dZ1 = dS (per token) [Z1 > 0]; dW1 = dZ1b^T X
+    hipLaunchKernelGGL(dz1_kernel, dim3((unsigned)((T + 3) / 4)), dim3(256), 0, st, w.dS, w.Z1, T, n, w.dZ1b);
+    NN_LAUNCHED();
+    if ((rc = gemm_partials(gemm_args(w.dZ1b, 1, kHid, x, kIn, 1, kHid, kIn, (int32_t)T), w.P1, kSplitCapW1,
+                            st)))
+        return rc;
+    // column sums over the samples: dw4 = sum dy A3b and db4 = sum dy; db3; db2;
+    // db1 = sum dS cnt (dZ1 summed over a sample's tokens); the loss
+    ColMulti cm;
+    std::memset(&cm, 0, sizeof cm);
+    const int64_t chB = col_chunk(B), nB = col_chunks(B);
+    auto prob = [&](int q, const float *Xf, const uint16_t *Xb, int64_t ld, int32_t cols, const float *wrow,
+                    int32_t with_w, float *part, const uint8_t *Xm = nullptr) {
+        ColProblem &p = cm.p[q];
+        p.Xf = Xf, p.Xb = Xb, p.Xm = Xm, p.wrow = wrow, p.part = part;
+        p.ld = ld, p.rows = B, p.chunk = chB;
+        p.cols = cols, p.with_w = with_w, p.first = (int32_t)(q * nB);
+    };
+    prob(0, nullptr, w.A3b, kHid, kHid, w.dy, 1, w.Pout);
+    prob(1, w.dZ3, nullptr, kHid, kHid, nullptr, 0, w.Pb3);
+    prob(2, w.dZ2, nullptr, kHid, kHid, nullptr, 0, w.Pb2);
+    prob(3, w.sq, nullptr, 1, 1, nullptr, 0, w.Ploss);
+    prob(4, w.dS, nullptr, kHid, kHid, nullptr, 0, w.Pb1, w.cnt);
+    cm.count = kColProblems;
+    hipLaunchKernelGGL(colsum_multi_kernel, dim3((unsigned)(kColProblems * nB)), dim3(320), 0, st, cm);
+    NN_LAUNCHED();
+    FinishArgs f;
+    std::memset(&f, 0, sizeof f);
+    int32_t blocks = 0;
+    auto seg = [&](const float *P, int64_t stride, int64_t rows, int32_t count, int32_t param) {
+        Segment &g = f.seg[f.count++];
+        g.P = P, g.stride = stride, g.rows = (int32_t)rows, g.count = count, g.param = param, g.first = blocks;
+        g.groups = rows <= kFinShort ? 1 : kFinGroups;
+        const int32_t per = 256 / g.groups;
+        blocks += (count + per - 1) / per;
+    };
+    seg(w.P1, (int64_t)kHid * kIn, splits_used(T, kSplitCapW1), kHid * kIn, (int32_t)kW1);
+    seg(w.P2, (int64_t)kHid * kHid, splits_used(B, kSplitCapW), kHid * kHid, (int32_t)kW2);
+    seg(w.P3, (int64_t)kHid * kHid, splits_used(B, kSplitCapW), kHid * kHid, (int32_t)kW3);
+    seg(w.Pb1, kHid, nB, kHid, (int32_t)kB1);
+    seg(w.Pout, kHid + 1, nB, kHid + 1, (int32_t)kW4);   // dw4 then db4 (kB4 = kW4 + 256)
+    seg(w.Pb3, kHid, nB, kHid, (int32_t)kB3);
+    seg(w.Pb2, kHid, nB, kHid, (int32_t)kB2);
+    seg(w.Ploss, 1, nB, 1, -1);
+    f.B = B;
+    f.grad = s.grad;
+    f.loss_out = loss;
+    f.sched = sched;
+    f.adam = AdamArgs{s.master, s.m, s.v, s.wb, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // the rest comes from sched
+    hipLaunchKernelGGL(finish_kernel, dim3((unsigned)blocks), dim3(256), 0, st, f);
     NN_LAUNCHED();
     return KO_OK;
 }
@@ -1112,11 +1538,12 @@ int ko_nn_load(void *state_dev, const float *params_host, void *hip_stream)
 
 int ko_nn_read(const void *state_dev, int32_t which, float *out_host, void *hip_stream)
 {
-    if (!state_dev || !out_host || (which != 0 && which != 1))
+    if (!state_dev || !out_host || which < 0 || which > 3)
         return fail(KO_EINVAL, "bad arguments");
     hipStream_t st = (hipStream_t)hip_stream;
     State s = state_of(const_cast<void *>(state_dev));
-    NN_HIP(hipMemcpyAsync(out_host, which ? s.grad : s.master, kNP * 4, hipMemcpyDeviceToHost, st));
+    const float *src[4] = {s.master, s.grad, s.m, s.v};
+    NN_HIP(hipMemcpyAsync(out_host, src[which], kNP * 4, hipMemcpyDeviceToHost, st));
     NN_HIP(hipStreamSynchronize(st));
     return KO_OK;
 }
@@ -1245,64 +1672,110 @@ int ko_nn_backward(void *state_dev, const uint16_t *x_dev, const float *t_dev, i
         return rc;
     if (!t_dev)
         return fail(KO_EINVAL, "targets must not be NULL");
-    hipStream_t st = (hipStream_t)hip_stream;
     size_t total;
     Work w = work_of(work_dev, B, n, &total);
-    State s = state_of(state_dev);
-    if ((rc = forward_impl(s, x_dev, B, n, w.y, w, st)))
+    return backward_impl(state_of(state_dev), x_dev, t_dev, B, n, loss_dev, w, nullptr, (hipStream_t)hip_stream);
+}
+
+int ko_nn_train_step(void *state_dev, const uint16_t *x_dev, const float *t_dev, int32_t B, int32_t n,
+                     ko_nn_sched *sched_dev, float *loss_dev, void *work_dev, void *hip_stream)
+{
+    int rc = check_batch(state_dev, x_dev, B, n, work_dev);
+    if (rc)
         return rc;
-    const int32_t T = B * n;
-    hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, st, w.y, t_dev, B, w.dy, loss_dev);
+    if (!t_dev || !sched_dev)
+        return fail(KO_EINVAL, "targets and schedule must not be NULL");
+    size_t total;
+    Work w = work_of(work_dev, B, n, &total);
+    return backward_impl(state_of(state_dev), x_dev, t_dev, B, n, loss_dev, w, sched_dev, (hipStream_t)hip_stream);
+}
+
+int ko_nn_batch(const float *feat_dev, const int32_t *set_of_dev, const uint8_t *pos_dev,
+                const int64_t *makespans_dev, const int64_t *center_dev, const int64_t *scale_dev,
+                const int64_t *perm_dev, const ko_nn_sched *sched_dev, int32_t B, int32_t n, uint16_t *x_dev,
+                float *t_dev, void *hip_stream)
+{
+    if (!feat_dev || !pos_dev || !makespans_dev || !center_dev || !scale_dev || !perm_dev || !sched_dev || !x_dev ||
+        !t_dev)
+        return fail(KO_EINVAL, "only set_of may be NULL");
+    if (B < 1 || n < 1 || n > KO_NN_MAX_TOKENS)
+        return fail(KO_EINVAL, "B must be >= 1 and n in 1..%d", KO_NN_MAX_TOKENS);
+    hipLaunchKernelGGL(batch_kernel, dim3(grid1((int64_t)B * n * kIn)), dim3(256), 0, (hipStream_t)hip_stream,
+                       feat_dev, set_of_dev, pos_dev, makespans_dev, center_dev, scale_dev, perm_dev, sched_dev, B, n,
+                       x_dev, t_dev);
     NN_LAUNCHED();
-    // output layer: dw4[c] = sum_b dy[b] A3b[b][c], db4 = sum_b dy[b]
-    if ((rc = colsum(nullptr, w.A3b, kHid, B, kHid, w.dy, true, s.grad + kW4, (int32_t)(kB4 - kW4), w.P,
-                     st)))
+    return KO_OK;
+}
+
+int ko_nn_step_capture(void *state_dev, const float *feat_dev, const int32_t *set_of_dev, const uint8_t *pos_dev,
+                       const int64_t *makespans_dev, const int64_t *center_dev, const int64_t *scale_dev,
+                       const int64_t *perm_dev, ko_nn_sched *sched_dev, int32_t B, int32_t n, uint16_t *x_dev,
+                       float *t_dev, float *loss_dev, void *work_dev, void *hip_stream, ko_nn_graph **out)
+{
+    if (!out)
+        return fail(KO_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!hip_stream)
+        return fail(KO_EINVAL, "capture needs a created stream, not the null stream");
+    int rc = check_batch(state_dev, x_dev, B, n, work_dev);
+    if (rc)
         return rc;
-    hipLaunchKernelGGL(out_backward_kernel, dim3(grid1((int64_t)B * kHid)), dim3(256), 0, st, w.dy,
-                       s.wb, w.Z3, B, w.dZ3, w.dZ3b);
-    NN_LAUNCHED();
-    // layer 3: db3, dW3 = dZ3b^T A2b, dZ2 = (dZ3b W3b) * [Z2 > 0]
-    if ((rc = colsum(w.dZ3, nullptr, kHid, B, kHid, nullptr, false, s.grad + kB3, 0, w.P, st)))
-        return rc;
-    GemmArgs a = gemm_args(w.dZ3b, 1, kHid, w.A2b, kHid, 1, kHid, kHid, B);
-    a.C = s.grad + kW3;
-    a.ldc = kHid;
-    if ((rc = gemm_splitk(a, w.P, kSplitCapW, st)))
-        return rc;
-    a = gemm_args(w.dZ3b, kHid, 1, s.wb + kW3, kHid, 1, B, kHid, kHid);
-    a.epi = kEpiMask;
-    a.zref = w.Z2;
-    a.ldz = kHid;
-    a.C = w.dZ2;
-    a.ldc = kHid;
-    a.Cb = w.dZ2b;
-    a.ldcb = kHid;
-    if ((rc = gemm(a, st)))
-        return rc;
-    // layer 2: db2, dW2 = dZ2b^T Sb, dS = dZ2b W2b
-    if ((rc = colsum(w.dZ2, nullptr, kHid, B, kHid, nullptr, false, s.grad + kB2, 0, w.P, st)))
-        return rc;
-    a = gemm_args(w.dZ2b, 1, kHid, w.Sb, kHid, 1, kHid, kHid, B);
-    a.C = s.grad + kW2;
-    a.ldc = kHid;
-    if ((rc = gemm_splitk(a, w.P, kSplitCapW, st)))
-        return rc;
-    a = gemm_args(w.dZ2b, kHid, 1, s.wb + kW2, kHid, 1, B, kHid, kHid);
-    a.C = w.dS;
-    a.ldc = kHid;
-    if ((rc = gemm(a, st)))
-        return rc;
-    // layer 1: dZ1 = dS (per token) * [Z1 > 0]; db1; dW1 = dZ1b^T X
-    hipLaunchKernelGGL(dz1_kernel, dim3(grid1((int64_t)T * kHid)), dim3(256), 0, st, w.dS, w.Z1, B, n,
-                       w.dZ1, w.dZ1b);
-    NN_LAUNCHED();
-    if ((rc = colsum(w.dZ1, nullptr, kHid, T, kHid, nullptr, false, s.grad + kB1, 0, w.P, st)))
-        return rc;
-    a = gemm_args(w.dZ1b, 1, kHid, x_dev, kIn, 1, kHid, kIn, T);
-    a.C = s.grad + kW1;
-    a.ldc = kIn;
-    if ((rc = gemm_splitk(a, w.P, kSplitCapW1, st)))
-        return rc;
+    if (!feat_dev || !pos_dev || !makespans_dev || !center_dev || !scale_dev || !perm_dev || !sched_dev || !t_dev)
+        return fail(KO_EINVAL, "only set_of and loss may be NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    NN_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipLaunchKernelGGL(batch_kernel, dim3(grid1((int64_t)B * n * kIn)), dim3(256), 0, st, feat_dev, set_of_dev,
+                       pos_dev, makespans_dev, center_dev, scale_dev, perm_dev, sched_dev, B, n, x_dev, t_dev);
+    rc = KO_OK;
+    if (hipGetLastError() != hipSuccess)
+        rc = fail(KO_EHIP, "batch kernel launch failed during capture");
+    size_t total;
+    Work w = work_of(work_dev, B, n, &total);
+    if (!rc)
+        rc = backward_impl(state_of(state_dev), x_dev, t_dev, B, n, loss_dev, w, sched_dev, st);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc || e != hipSuccess) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return rc ? rc : fail(KO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(KO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+    }
+    int device = 0;
+    (void)hipGetDevice(&device);
+    ko_nn_graph *g = new ko_nn_graph();
+    g->device = device;
+    g->graph = graph;
+    g->exec = exec;
+    *out = g;
+    return KO_OK;
+}
+
+int ko_nn_graph_launch(ko_nn_graph *graph, void *hip_stream)
+{
+    if (!graph)
+        return fail(KO_EINVAL, "graph must not be NULL");
+    NN_HIP(hipGraphLaunch(graph->exec, (hipStream_t)hip_stream));
+    return KO_OK;
+}
+
+int ko_nn_graph_destroy(ko_nn_graph *graph)
+{
+    if (!graph)
+        return KO_OK;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(graph->device);
+    (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(graph->exec);
+    (void)hipGraphDestroy(graph->graph);
+    (void)hipSetDevice(prev);
+    delete graph;
     return KO_OK;
 }
 
@@ -1312,10 +1785,9 @@ int ko_nn_adam(void *state_dev, int32_t step, float lr, float beta1, float beta2
     if (!state_dev || step < 1)
         return fail(KO_EINVAL, "bad arguments");
     State s = state_of(state_dev);
-    const float c1 = 1.f - std::pow(beta1, (float)step);
-    const float c2 = 1.f - std::pow(beta2, (float)step);
-    hipLaunchKernelGGL(adam_kernel, dim3(grid1(kNP)), dim3(256), 0, (hipStream_t)hip_stream, s.master,
-                       s.grad, s.m, s.v, (int64_t)kNP, lr, beta1, beta2, eps, c1, c2, s.wb);
+    const AdamArgs a{s.master, s.m, s.v, s.wb, lr, beta1, beta2, eps, 0.f, 0.f};
+    hipLaunchKernelGGL(adam_kernel, dim3(grid1(kNP)), dim3(256), 0, (hipStream_t)hip_stream, s.grad,
+                       (int64_t)kNP, a, step);
     NN_LAUNCHED();
     return KO_OK;
 }

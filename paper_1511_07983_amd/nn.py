@@ -37,6 +37,7 @@ EXPORTED = ("ko_nn_num_params", "ko_nn_state_bytes", "ko_nn_work_bytes", "ko_nn_
             "ko_nn_forward",
             "ko_nn_backward", "ko_nn_adam", "ko_nn_layer1_table", "ko_nn_score_work_bytes",
             "ko_nn_forward_positions", "ko_nn_score", "ko_nn_beam_expand", "ko_nn_beam_cap", "ko_nn_beam_gather",
+            "ko_nn_train_step", "ko_nn_batch", "ko_nn_step_capture", "ko_nn_graph_launch", "ko_nn_graph_destroy",
             "ko_nn_last_error")
 
 _vp = ctypes.c_void_p
@@ -64,10 +65,17 @@ _lib.ko_nn_beam_expand.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c
 _lib.ko_nn_beam_cap.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64,
                                 _vp]
 _lib.ko_nn_beam_gather.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp, _vp]
+_lib.ko_nn_train_step.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp]
+_lib.ko_nn_batch.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
+_lib.ko_nn_step_capture.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+                                    _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
+_lib.ko_nn_graph_launch.argtypes = [_vp, _vp]
+_lib.ko_nn_graph_destroy.argtypes = [_vp]
 _lib.ko_nn_last_error.restype = ctypes.c_char_p
 for _f in ("ko_nn_load", "ko_nn_read", "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens", "ko_nn_targets",
            "ko_nn_forward", "ko_nn_backward", "ko_nn_adam", "ko_nn_layer1_table", "ko_nn_within_set_ranks",
-           "ko_nn_forward_positions", "ko_nn_score", "ko_nn_beam_expand", "ko_nn_beam_cap", "ko_nn_beam_gather"):
+           "ko_nn_forward_positions", "ko_nn_score", "ko_nn_beam_expand", "ko_nn_beam_cap", "ko_nn_beam_gather",
+           "ko_nn_train_step", "ko_nn_batch", "ko_nn_step_capture", "ko_nn_graph_launch", "ko_nn_graph_destroy"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -103,6 +111,53 @@ def beam_gather(prefix, cand, idx, stream=None):
     _check(_lib.ko_nn_beam_gather(prefix.data_ptr() if d else None, d, cand.data_ptr(), idx.data_ptr(), keep,
                                   out.data_ptr(), _stream_handle(stream)))
     return out
+
+
+# struct ko_nn_sched (include/ko_nn.h), 48 bytes
+SCHED_DTYPE = np.dtype([("step", "<i4"), ("warmup", "<i4"), ("total", "<i4"), ("per_epoch", "<i4"),
+                        ("lr", "<f4"), ("lr_final", "<f4"), ("beta1", "<f4"), ("beta2", "<f4"), ("eps", "<f4"),
+                        ("reserved", "<i4", (3,))])
+assert SCHED_DTYPE.itemsize == 48
+
+
+def sched(*, lr: float, warmup: int = 0, total: int = 1, lr_final: float = 1.0, per_epoch: int = 1, step: int = 0,
+          beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, device="cuda:0"):
+    """A device ko_nn_sched (uint8 tensor of 48 bytes): Adam's hyper-parameters
+    and rate schedule, read and advanced by train steps on the device."""
+    if per_epoch < 1 or total < 1 or warmup < 0 or step < 0:
+        raise ValueError("need per_epoch >= 1, total >= 1, warmup >= 0 and step >= 0")
+    h = np.zeros(1, dtype=SCHED_DTYPE)
+    h["step"], h["warmup"], h["total"], h["per_epoch"] = step, warmup, total, per_epoch
+    h["lr"], h["lr_final"], h["beta1"], h["beta2"], h["eps"] = lr, lr_final, beta1, beta2, eps
+    return torch.from_numpy(h.view(np.uint8).copy()).to(device)
+
+
+def sched_read(sched_dev) -> dict:
+    """The fields of a device ko_nn_sched (host copy; waits for the device)."""
+    h = sched_dev.cpu().numpy().view(SCHED_DTYPE)[0]
+    return {k: h[k].item() for k in SCHED_DTYPE.names if k != "reserved"}
+
+
+class StepGraph:
+    """An instantiated HIP graph of one training step (ko_nn_step_capture)."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep  # every buffer the graph reads or writes must outlive it
+
+    def launch(self, stream=None):
+        _check(_lib.ko_nn_graph_launch(self._h, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.ko_nn_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def num_params() -> int:
@@ -162,9 +217,10 @@ class Surrogate:
         _check(_lib.ko_nn_load(self.state.data_ptr(), p.ctypes.data, _stream_handle(stream)))
 
     def read(self, which: str = "weights", stream=None) -> np.ndarray:
+        """Host copy of the weights, "grads" or Adam's moments "m" and "v"."""
+        code = {"weights": 0, "grads": 1, "m": 2, "v": 3}[which]
         out = np.zeros(num_params(), dtype=np.float32)
-        _check(_lib.ko_nn_read(self.state.data_ptr(), 0 if which == "weights" else 1, out.ctypes.data,
-                               _stream_handle(stream)))
+        _check(_lib.ko_nn_read(self.state.data_ptr(), code, out.ctypes.data, _stream_handle(stream)))
         return out
 
     def tokens(self, feat, pos, set_of=None, rows=None, B=None, stream=None, out=None):
@@ -241,6 +297,56 @@ class Surrogate:
         _check(_lib.ko_nn_score(self.state.data_ptr(), feat.data_ptr(), pos.data_ptr(), B, n, y.data_ptr(),
                                 _stream_handle(stream)))
         return y
+
+    def train_step(self, x, t, sched_dev, loss=None, stream=None):
+        """Forward, loss, gradients and Adam (rate and step from the device
+        schedule, which advances) in one stream-ordered call; returns the loss."""
+        torch = self.torch
+        B, n, _ = x.shape
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(_lib.ko_nn_train_step(self.state.data_ptr(), x.data_ptr(), t.data_ptr(), B, n,
+                                     sched_dev.data_ptr(), loss.data_ptr(), self._workspace(B, n).data_ptr(),
+                                     _stream_handle(stream)))
+        return loss
+
+    def batch(self, feat, pos, set_of, makespans, center, scale, perm, sched_dev, B: int, x=None, t=None,
+              stream=None):
+        """The minibatch of the schedule's next step (ko_nn_batch): tokens x [B, n, 32]
+        and targets t [B] for rows perm[(step mod per_epoch) B + b]."""
+        torch = self.torch
+        n = pos.shape[1]
+        if perm.numel() < B * int(sched_read(sched_dev)["per_epoch"]):
+            raise ValueError("perm must hold per_epoch * B rows")
+        x = x if x is not None else torch.empty((B, n, D_IN), dtype=torch.int16, device=self.device)
+        t = t if t is not None else torch.empty(B, dtype=torch.float32, device=self.device)
+        _check(_lib.ko_nn_batch(feat.data_ptr(), set_of.data_ptr() if set_of is not None else None, pos.data_ptr(),
+                                makespans.data_ptr(), center.data_ptr(), scale.data_ptr(), perm.data_ptr(),
+                                sched_dev.data_ptr(), B, n, x.data_ptr(), t.data_ptr(), _stream_handle(stream)))
+        return x, t
+
+    def capture_step(self, feat, pos, set_of, makespans, center, scale, perm, sched_dev, B: int, *, stream,
+                     x=None, t=None, loss=None):
+        """A HIP graph of batch + train_step (ko_nn_step_capture); each replay is
+        the next training step.  stream: a created torch stream."""
+        torch = self.torch
+        n = pos.shape[1]
+        if perm.numel() < B * int(sched_read(sched_dev)["per_epoch"]):
+            raise ValueError("perm must hold per_epoch * B rows")
+        x = x if x is not None else torch.empty((B, n, D_IN), dtype=torch.int16, device=self.device)
+        t = t if t is not None else torch.empty(B, dtype=torch.float32, device=self.device)
+        loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=self.device)
+        work = self._workspace(B, n)
+        g = ctypes.c_void_p()
+        _check(_lib.ko_nn_step_capture(self.state.data_ptr(), feat.data_ptr(),
+                                       set_of.data_ptr() if set_of is not None else None, pos.data_ptr(),
+                                       makespans.data_ptr(), center.data_ptr(), scale.data_ptr(), perm.data_ptr(),
+                                       sched_dev.data_ptr(), B, n, x.data_ptr(), t.data_ptr(), loss.data_ptr(),
+                                       work.data_ptr(), _stream_handle(stream), ctypes.byref(g)))
+        graph = StepGraph(g, (self.state, feat, pos, set_of, makespans, center, scale, perm, sched_dev, x, t, loss,
+                              work))
+        graph.x, graph.t, graph.loss = x, t, loss
+        return graph
 
     def adam(self, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         _check(_lib.ko_nn_adam(self.state.data_ptr(), step, lr, beta1, beta2, eps,

@@ -150,7 +150,12 @@ def mask_suffixes(samples: Samples, frac: float, seed: int) -> Samples:
 def train(sur: "nn.Surrogate", table: SetTable, data: Samples, *, steps: int, batch: int = 4096,
           lr: float = 2e-3, warmup: int = 100, seed: int = 0, log_every: int = 100):
     """Adam on shuffled minibatches; returns [(step, loss)] at log points.
-    Learning rate: linear warm-up, then cosine decay to 5% of `lr`."""
+    Learning rate: linear warm-up, then cosine decay to 5% of `lr`.
+
+    A step is one replay of a captured HIP graph (ko_nn_step_capture): the
+    minibatch is picked from the pass's permutation, and forward, backward and
+    Adam run with the step counter and rate kept on the device; the host only
+    writes each pass's permutation between replays."""
     torch = _torch()
     dev = data.makespans.device
     R = data.count
@@ -158,26 +163,23 @@ def train(sur: "nn.Surrogate", table: SetTable, data: Samples, *, steps: int, ba
         batch = R
     rng = np.random.default_rng(seed)
     per_epoch = R // batch
-    x = torch.empty((batch, table.n, nn.D_IN), dtype=torch.int16, device=dev)
-    t = torch.empty(batch, dtype=torch.float32, device=dev)
-    perm = None
+    perm = torch.empty(per_epoch * batch, dtype=torch.int64, device=dev)
+    sch = nn.sched(lr=lr, warmup=warmup, total=steps, lr_final=0.05, per_epoch=per_epoch, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    stream.wait_stream(torch.cuda.current_stream(dev))
+    graph = sur.capture_step(table.feat, data.pos, data.set_of, data.t_values, data.t_center, data.t_scale, perm,
+                             sch, batch, stream=stream)
     log = []
-    for step in range(1, steps + 1):
-        j = (step - 1) % per_epoch
-        if j == 0:
-            perm = torch.from_numpy(rng.permutation(R).astype(np.int64)).to(dev)
-        rows = perm[j * batch:(j + 1) * batch]
-        sur.tokens(table.feat, data.pos, data.set_of, rows=rows, out=x)
-        sur.targets(data.t_values, data.t_center, data.t_scale, data.set_of, rows=rows, out=t)
-        loss = sur.backward(x, t)
-        if step <= warmup:
-            rate = lr * step / max(1, warmup)
-        else:
-            prog = (step - warmup) / max(1, steps - warmup)
-            rate = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * prog)))
-        sur.adam(step, rate)
-        if step == 1 or step % log_every == 0 or step == steps:
-            log.append((step, float(loss.cpu()[0])))
+    with torch.cuda.stream(stream):
+        for step in range(1, steps + 1):
+            if (step - 1) % per_epoch == 0:
+                perm.copy_(torch.from_numpy(rng.permutation(R)[:per_epoch * batch].astype(np.int64)))
+            graph.launch(stream)
+            if step == 1 or step % log_every == 0 or step == steps:
+                log.append((step, float(graph.loss.cpu()[0])))
+    torch.cuda.current_stream(dev).wait_stream(stream)
+    stream.synchronize()
+    graph.close()
     return log
 
 

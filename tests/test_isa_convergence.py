@@ -135,10 +135,9 @@ def test_sort_scatter_collectives_full_exec(select_report):
 
 
 
-@pytest.mark.parametrize("needle", ["out_forward_kernel", "loss_kernel", "out_backward_kernel",
-                                    "colsum_partial_kernel", "colsum_finish_kernel", "pool_kernel",
-                                    "gather_pool_kernel", "within_set_rank_kernel",
-                                    "gemm_bf16_kernel", "gemm_nt_kernel", "score_kernel"])
+@pytest.mark.parametrize("needle", ["out_forward_kernel", "head_kernel", "colsum_multi_kernel", "finish_kernel",
+                                    "dz1_kernel", "pool_kernel", "gather_pool_kernel", "within_set_rank_kernel",
+                                    "gemm_bf16_kernel", "gemm_nt_kernel", "panel_gemm_kernel", "score_kernel"])
 def test_surrogate_collectives_full_exec(nn_report, needle):
     for name in _pick(nn_report, needle):
         bad, _ = nn_report[name]
