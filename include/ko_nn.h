@@ -201,6 +201,46 @@ int ko_nn_forward_positions(const void *state_dev, const float *table_dev, const
 int ko_nn_score(const void *state_dev, const float *feat_dev, const uint8_t *pos_dev, int32_t B, int32_t n,
                 float *y_dev, void *hip_stream);
 
+/* Scoring with the pooling on the matrix cores.  S = sum over kernels of the
+ * layer-1 table row of (kernel, position) is the product of each order's
+ * one-hot row with the table.  An order of an n-kernel set puts each kernel
+ * at a position 0..n-1 or leaves it unplaced, so the table needs n + 1 slots
+ * per kernel (slot p for position p < n, slot n for "unplaced").  Carried as
+ * two BF16 matrices hi = bf16(T) and lo = bf16(T - hi) (16 significant bits
+ * of T), the pooling runs as BF16 MFMA products with float32 accumulation,
+ * like the two layers after it.  The result differs from ko_nn_score by that
+ * representation of T and the order of the float32 additions (S, like every
+ * path's, is then rounded to BF16).
+ *
+ * ko_nn_split_table_bytes — bytes of the split table of a set of n kernels:
+ * 2 x 256 x KP BF16 values, KP = n (n + 1) rounded up to a multiple of 32.
+ *
+ * ko_nn_split_table — the split table of one set (features feat[n][8],
+ * float32, device): split[q][j][k] (BF16, device, 16-byte aligned; q = 0
+ * high and 1 low part, hidden unit j, k = (n + 1) i + slot for kernel i,
+ * zero from n (n + 1) to KP), from the same first-layer values as
+ * ko_nn_layer1_table.  1 <= n <= 16.  Errors: KO_EINVAL. */
+size_t ko_nn_split_table_bytes(int32_t n);
+int ko_nn_split_table(const void *state_dev, const float *feat_dev, int32_t n, uint16_t *split_dev,
+                      void *hip_stream);
+
+/* ko_nn_score_split — y[B] (float32, device) for B orders of one set given as
+ * positions pos[B][n] (uint8, device: 0..n-1, or 16 and above = unplaced),
+ * from the set's split table (ko_nn_split_table, made with the current
+ * weights).  A position in n..15 is no launch position of an n-kernel order:
+ * that order's y is NaN.  One kernel per 128-order tile: the one-hot tile in
+ * LDS, the pooling product, both 256x256 layers and the output layer, nothing
+ * in memory but y.  1 <= n <= 16, B >= 1.  Errors: KO_EINVAL. */
+int ko_nn_score_split(const void *state_dev, const uint16_t *split_dev, const uint8_t *pos_dev, int32_t B,
+                      int32_t n, float *y_dev, void *hip_stream);
+
+/* ko_nn_score_split_acc — as ko_nn_score_split, but y[b] = scale * score
+ * (accumulate = 0) or y[b] + scale * score (accumulate != 0), in the same
+ * kernel: the mean score of an ensemble of networks is one call per member
+ * with scale = 1 / members, the first without accumulate. */
+int ko_nn_score_split_acc(const void *state_dev, const uint16_t *split_dev, const uint8_t *pos_dev, int32_t B,
+                          int32_t n, float scale, int32_t accumulate, float *y_dev, void *hip_stream);
+
 /* Beam search over launch orders of one set, one position per step, on the
  * device (the scores come from ko_nn_score on the candidates' positions; the
  * selection of the best candidates is libko's ko_topk_f32).

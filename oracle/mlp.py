@@ -75,14 +75,23 @@ def forward(params, X, bf16_points: bool = True):
     W1, W2, W3, w4 = (_r(p[k], bf16_points) for k in ("W1", "W2", "W3", "w4"))
     Z1 = X @ W1.T + p["b1"]
     S = np.maximum(Z1, 0.0).sum(axis=1)
+    y, cache = from_pooled(params, S, bf16_points)
+    cache.update(X=X, W1=W1, Z1=Z1)
+    return y, cache
+
+
+def from_pooled(params, S, bf16_points: bool = True):
+    """The layers after pooling, from S [B, 256] (the sum over tokens of
+    relu(Z1)).  Returns (y [B], cache)."""
+    p = params
+    W2, W3, w4 = (_r(p[k], bf16_points) for k in ("W2", "W3", "w4"))
     Sb = _r(S, bf16_points)
     Z2 = Sb @ W2.T + p["b2"]
     A2b = _r(np.maximum(Z2, 0.0), bf16_points)
     Z3 = A2b @ W3.T + p["b3"]
     A3b = _r(np.maximum(Z3, 0.0), bf16_points)
     y = A3b @ w4 + p["b4"][0]
-    cache = dict(X=X, W1=W1, W2=W2, W3=W3, w4=w4, Z1=Z1, Sb=Sb, Z2=Z2, A2b=A2b, Z3=Z3, A3b=A3b)
-    return y, cache
+    return y, dict(W2=W2, W3=W3, w4=w4, Sb=Sb, Z2=Z2, A2b=A2b, Z3=Z3, A3b=A3b)
 
 
 def loss_and_grads(params, X, t, bf16_points: bool = True):

@@ -873,6 +873,72 @@ __global__ __launch_bounds__(256) void gather_pool_kernel(const float *T, const 
     Sb[b * kHid + j] = to_bf16(s);
 }
 
+// Layers 2 and 3 and the output layer of a scoring tile: the 64 x 256 BF16
+// activations in LDS (At, row pitch P) become relu(A W^T + b) twice, wave w
+// computing columns [64w, 64w + 64) as 4 x 4 MFMA 16x16x32 tiles with W's
+// 16-byte fragments read from memory (the fragments and k order of
+// gemm_nt_kernel) and writing its BF16 result back over the tile once every
+// wave has read it; then y for the tile's `rows` rows, one wave per row, as
+// out_forward_kernel.  Called by all 256 threads after a barrier that
+// published the tile.
+template <int P>
+__device__ __forceinline__ void score_layers(uint16_t (*At)[P], const uint16_t *wb, const float *master, int wave,
+                                             int lane, int rows, int64_t b0, float *y)
+{
+    const int kk = (lane >> 4) * 8;
+#pragma unroll
+    for (int layer = 0; layer < 2; layer++) {
+        const uint16_t *W = wb + (layer == 0 ? kW2 : kW3);
+        const float *bias = master + (layer == 0 ? kB2 : kB3);
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k0 = 0; k0 < kHid; k0 += kKStep) {
+            bf16x8 af[4], bfr[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(W + (size_t)(wave * 64 + j * 16 + (lane & 15)) * kHid +
+                                                           k0 + kk);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                af[i] = *reinterpret_cast<const bf16x8 *>(&At[i * 16 + (lane & 15)][k0 + kk]);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();  // every wave has read the tile
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int col = wave * 64 + j * 16 + (lane & 15);
+            const float bc = bias[col];
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int e = 0; e < 4; e += 2) {
+                    const int row = i * 16 + (lane >> 4) * 4 + e;
+                    const uint32_t h = pack_bf16x2(fmaxf(acc[i][j][e] + bc, 0.f), fmaxf(acc[i][j][e + 1] + bc, 0.f));
+                    At[row][col] = (uint16_t)h;
+                    At[row + 1][col] = (uint16_t)(h >> 16);
+                }
+        }
+        __syncthreads();
+    }
+    for (int r = wave; r < rows; r += 4) {
+        float s = 0.f;
+        for (int c = lane; c < kHid; c += 64)
+            s += from_bf16(At[r][c]) * from_bf16(wb[kW4 + c]);
+        s = wave_sum(s);
+        if (lane == 0)
+            y[b0 + r] = s + master[kB4];
+    }
+}
+
 // Scoring in one kernel, for a tile of 64 orders of one set per workgroup:
 // the same values as table_kernel + gather_pool_kernel + the two hidden
 // layers (gemm_nt_kernel) + out_forward_kernel, bit for bit, with nothing
@@ -950,58 +1016,7 @@ __global__ __launch_bounds__(256) void score_kernel(const uint16_t *wb, const fl
     }
     __syncthreads();
 
-    const int kk = (lane >> 4) * 8;
-#pragma unroll
-    for (int layer = 0; layer < 2; layer++) {
-        const uint16_t *W = wb + (layer == 0 ? kW2 : kW3);
-        const float *bias = master + (layer == 0 ? kB2 : kB3);
-        f32x4 acc[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int k0 = 0; k0 < kHid; k0 += kKStep) {
-            bf16x8 af[4], bfr[4];
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                bfr[j] = *reinterpret_cast<const bf16x8 *>(W + (size_t)(wave * 64 + j * 16 + (lane & 15)) * kHid +
-                                                           k0 + kk);
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-                af[i] = *reinterpret_cast<const bf16x8 *>(&At[i * 16 + (lane & 15)][k0 + kk]);
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-#pragma unroll
-                for (int j = 0; j < 4; j++)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-        }
-        __syncthreads();  // every wave has read the tile
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int col = wave * 64 + j * 16 + (lane & 15);
-            const float bc = bias[col];
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-#pragma unroll
-                for (int e = 0; e < 4; e += 2) {
-                    const int row = i * 16 + (lane >> 4) * 4 + e;
-                    const uint32_t h = pack_bf16x2(fmaxf(acc[i][j][e] + bc, 0.f), fmaxf(acc[i][j][e + 1] + bc, 0.f));
-                    At[row][col] = (uint16_t)h;
-                    At[row + 1][col] = (uint16_t)(h >> 16);
-                }
-        }
-        __syncthreads();
-    }
-    for (int r = wave; r < rows; r += 4) {
-        float s = 0.f;
-        for (int c = lane; c < kHid; c += 64)
-            s += from_bf16(At[r][c]) * from_bf16(wb[kW4 + c]);
-        s = wave_sum(s);
-        if (lane == 0)
-            y[b0 + r] = s + master[kB4];
-    }
+    score_layers<kScPitch>(At, wb, master, wave, lane, rows, b0, y);
 }
 
 template <int N>
@@ -1016,6 +1031,254 @@ bool launch_score(int n, unsigned grid, hipStream_t st, const uint16_t *wb, cons
                   const uint8_t *pos, int32_t B, float *y, std::integer_sequence<int, Ns...>)
 {
     return ((n == Ns + 1 ? (launch_score_n<Ns + 1>(grid, st, wb, master, feat, pos, B, y), true) : false) || ...);
+}
+
+// ------------------------------------------------------------------ scoring, pooling on the matrix cores
+//
+// S = sum_i T[i][pos_i] is the product of an order's one-hot row with the
+// set's layer-1 table viewed as a matrix with one row per (kernel, slot).  An
+// order of an n-kernel set puts each kernel at a launch position 0..n-1 or
+// leaves it unplaced (16), so a kernel needs n + 1 slots: slot p for position
+// p < n and slot n for "unplaced".  With the table carried as two BF16
+// matrices, hi = bf16(T) and lo = bf16(T - hi) (together 16 significant bits
+// of T, a relative error below 2^-17), the pooling is a BF16 MFMA product
+// with float32 accumulation like the layers after it, instead of 3 n float32
+// instructions per hidden unit.  The one-hot entries are exact, so the result
+// differs from the table path only by that representation and the order of
+// the float32 additions; S is then rounded to BF16 as on every path.
+
+constexpr int kSplitK(int n) { return (n * (n + 1) + kKStep - 1) / kKStep * kKStep; }
+// LDS row pitch of the tile that holds the one-hot rows (up to 288 columns)
+// and then S and A2 (256 columns): 148 dwords
+constexpr int kOhPitch = kSplitK(KO_NN_MAX_TOKENS) + 8;
+
+// split[q][j][k] (BF16; q = 0 high part, 1 low part; hidden unit j; k =
+// (n + 1) i + slot for kernel i, zero from n (n + 1) up to KP = kSplitK(n)),
+// with T computed exactly as table_kernel does for the slot's position.
+// One workgroup row per hidden unit j (blockIdx.y), threads along k.
+__global__ void split_table_kernel(const uint16_t *wb, const float *master, const float *feat, int32_t n,
+                                   int32_t KP, uint16_t *split)
+{
+    const int j = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= KP)
+        return;
+    const int64_t idx = (int64_t)j * KP + k;
+    uint16_t hi = 0, lo = 0;
+    if (k < n * (n + 1)) {
+        const int i = k / (n + 1), slot = k % (n + 1);
+        const int p = slot < n ? slot : KO_NN_UNPLACED;
+        const uint4 w1r = *reinterpret_cast<const uint4 *>(wb + kW1 + (size_t)j * kIn);
+        const float g = layer1_base(w1r, feat + i * KO_NN_FEAT, master[kB1 + j]);
+        const float T = fmaxf(g + from_bf16(wb[kW1 + (size_t)j * kIn + KO_NN_FEAT + p]), 0.f);
+        hi = to_bf16(T);
+        lo = to_bf16(T - from_bf16(hi));
+    }
+    split[idx] = hi;
+    split[(int64_t)kHid * KP + idx] = lo;
+}
+
+// One product of the split scoring kernel for a wave: acc[8][4] (128 rows x
+// its 64 columns [64 w, 64 w + 64)) += A B^T over K = 32 KS, A from the LDS
+// tile (rows 0..127, k-contiguous), B's 16-byte fragments (column c at
+// Bm + c ldb, k-contiguous; with TWO a second matrix Bm2 at the same offsets,
+// accumulated after the first in each k step) read from memory one k step
+// ahead of the MFMAs that use them.
+template <int KS, bool TWO, int P>
+__device__ __forceinline__ void split_product(f32x4 (&acc)[8][4], uint16_t (*At)[P], const uint16_t *Bm,
+                                              const uint16_t *Bm2, int ldb, int wave, int lane)
+{
+    const int kk = (lane >> 4) * 8;
+    const uint16_t *bp = Bm + (size_t)(wave * 64 + (lane & 15)) * ldb + kk;
+    const uint16_t *bp2 = TWO ? Bm2 + (size_t)(wave * 64 + (lane & 15)) * ldb + kk : nullptr;
+    bf16x8 b[4], b2[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        b[j] = *reinterpret_cast<const bf16x8 *>(bp + (size_t)j * 16 * ldb);
+        if (TWO)
+            b2[j] = *reinterpret_cast<const bf16x8 *>(bp2 + (size_t)j * 16 * ldb);
+    }
+#pragma unroll 1
+    for (int ks = 0; ks < KS; ks++) {
+        bf16x8 nb[4], nb2[4];
+        if (ks + 1 < KS) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                nb[j] = *reinterpret_cast<const bf16x8 *>(bp + (size_t)j * 16 * ldb + (ks + 1) * kKStep);
+                if (TWO)
+                    nb2[j] = *reinterpret_cast<const bf16x8 *>(bp2 + (size_t)j * 16 * ldb + (ks + 1) * kKStep);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const bf16x8 af = *reinterpret_cast<const bf16x8 *>(&At[i * 16 + (lane & 15)][ks * kKStep + kk]);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b[j], acc[i][j], 0, 0, 0);
+                if (TWO)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b2[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        if (ks + 1 < KS) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                b[j] = nb[j];
+                if (TWO)
+                    b2[j] = nb2[j];
+            }
+        }
+    }
+}
+
+// Scoring of a tile of 128 orders per workgroup (4 waves; wave w owns
+// columns [64 w, 64 w + 64) of every product, for all 128 rows, so each
+// fragment of the table or of W feeds 8 MFMAs):
+//   1. the one-hot tile in LDS (row r: a 1 at 17 i + pos[r][i]);
+//   2. S = onehot (hi + lo), the hi then the lo product of each k step into
+//      one float32 accumulator; S as BF16 over the tile once every wave has
+//      read the one-hot rows;
+//   3. A2 = relu(S W2^T + b2) as BF16 over the tile, likewise;
+//   4. A3 = relu(A2 W3^T + b3) rounded to BF16 stays in registers: each
+//      lane multiplies its A3 values by w4, the 16 lanes of a row add their
+//      columns (xor shuffles), and the 4 waves' column sums of a row are
+//      added in wave order with b4: y.
+// Every sum has a fixed order, so y does not depend on scheduling.
+constexpr int kSpRows = 128;
+
+template <int N>
+__global__ __launch_bounds__(256, 2) void score_split_kernel(const uint16_t *wb, const float *master,
+                                                          const uint16_t *split, const uint8_t *pos, int32_t B,
+                                                          float scale, int32_t accumulate, float *y)
+{
+    constexpr int KP = kSplitK(N);
+    __shared__ __attribute__((aligned(16))) uint16_t At[kSpRows][kOhPitch];
+    __shared__ float yp[4][kSpRows];
+    __shared__ uint8_t bad[kSpRows];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    // the wave index is uniform across the wave (see out_forward_kernel)
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t b0 = (int64_t)blockIdx.x * kSpRows;
+    const int rows = (int)min((int64_t)kSpRows, (int64_t)B - b0);
+
+    for (int idx = tid; idx < kSpRows * (KP / 8); idx += 256) {
+        const int r = idx / (KP / 8), c = (idx % (KP / 8)) * 8;
+        *reinterpret_cast<uint4 *>(&At[r][c]) = make_uint4(0u, 0u, 0u, 0u);
+    }
+    __syncthreads();
+    if (tid < kSpRows)
+        bad[tid] = 0;
+    for (int idx = tid; idx < kSpRows * N; idx += 256) {
+        const int r = idx / N, i = idx % N;
+        if (r < rows) {
+            const int p = pos[(b0 + r) * N + i];
+            if (p < N || p >= KO_NN_UNPLACED)
+                At[r][i * (N + 1) + (p < N ? p : N)] = 0x3F80;   // BF16 1.0
+            else
+                bad[r] = 1;   // not a launch position of an N-kernel order
+        }
+    }
+    __syncthreads();
+
+    f32x4 acc[8][4];
+    auto clear = [&]() {
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    };
+    // the tile row and column of acc[i][j][e]
+    auto row_of = [&](int i, int e) { return i * 16 + (lane >> 4) * 4 + e; };
+    auto col_of = [&](int j) { return wave * 64 + j * 16 + (lane & 15); };
+    // BF16 of relu(acc + bias[col]) (bias null: of acc) over the tile
+    auto store_tile = [&](const float *bias) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int col = col_of(j);
+            const float bc = bias ? bias[col] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 8; i++)
+#pragma unroll
+                for (int e = 0; e < 4; e += 2) {
+                    const float v0 = bias ? fmaxf(acc[i][j][e] + bc, 0.f) : acc[i][j][e];
+                    const float v1 = bias ? fmaxf(acc[i][j][e + 1] + bc, 0.f) : acc[i][j][e + 1];
+                    const uint32_t h = pack_bf16x2(v0, v1);
+                    At[row_of(i, e)][col] = (uint16_t)h;
+                    At[row_of(i, e) + 1][col] = (uint16_t)(h >> 16);
+                }
+        }
+    };
+
+    clear();
+    split_product<KP / kKStep, true>(acc, At, split, split + (size_t)kHid * KP, KP, wave, lane);
+    __syncthreads();   // every wave has read the one-hot tile
+    store_tile(nullptr);
+    __syncthreads();
+    clear();
+    split_product<kHid / kKStep, false>(acc, At, wb + kW2, nullptr, kHid, wave, lane);
+    __syncthreads();   // every wave has read S
+    store_tile(master + kB2);
+    __syncthreads();
+    clear();
+    split_product<kHid / kKStep, false>(acc, At, wb + kW3, nullptr, kHid, wave, lane);
+
+    // output layer from the registers: part[i][e] = sum over this lane's 4 columns
+    float w4[4], b3[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        w4[j] = from_bf16(wb[kW4 + col_of(j)]);
+        b3[j] = master[kB3 + col_of(j)];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; i++)
+#pragma unroll
+        for (int e = 0; e < 4; e += 2) {
+            // rows e and e + 1: A3 rounded to BF16 two at a time
+            float part0 = 0.f, part1 = 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t h = pack_bf16x2(fmaxf(acc[i][j][e] + b3[j], 0.f), fmaxf(acc[i][j][e + 1] + b3[j], 0.f));
+                part0 += __uint_as_float(h << 16) * w4[j];
+                part1 += __uint_as_float(h & 0xFFFF0000u) * w4[j];
+            }
+            // the 16 lanes of a row group hold its 64 columns of this wave
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                part0 += __shfl_xor(part0, o);
+                part1 += __shfl_xor(part1, o);
+            }
+            if ((lane & 15) == 0) {
+                yp[wave][row_of(i, e)] = part0;
+                yp[wave][row_of(i, e) + 1] = part1;
+            }
+        }
+    __syncthreads();
+    if (tid < rows) {
+        const float v = bad[tid] ? __builtin_nanf("")
+                                 : (((yp[0][tid] + yp[1][tid]) + yp[2][tid]) + yp[3][tid]) + master[kB4];
+        y[b0 + tid] = accumulate ? y[b0 + tid] + scale * v : scale * v;
+    }
+}
+
+template <int N>
+void launch_score_split_n(unsigned grid, hipStream_t st, const uint16_t *wb, const float *master,
+                          const uint16_t *split, const uint8_t *pos, int32_t B, float scale, int32_t accumulate,
+                          float *y)
+{
+    hipLaunchKernelGGL(score_split_kernel<N>, dim3(grid), dim3(256), 0, st, wb, master, split, pos, B, scale,
+                       accumulate, y);
+}
+
+template <int... Ns>
+bool launch_score_split(int n, unsigned grid, hipStream_t st, const uint16_t *wb, const float *master,
+                        const uint16_t *split, const uint8_t *pos, int32_t B, float scale, int32_t accumulate,
+                        float *y, std::integer_sequence<int, Ns...>)
+{
+    return ((n == Ns + 1 ? (launch_score_split_n<Ns + 1>(grid, st, wb, master, split, pos, B, scale, accumulate, y),
+                            true)
+                         : false) ||
+            ...);
 }
 
 // ------------------------------------------------------------------ beam search
@@ -1841,6 +2104,53 @@ int ko_nn_score(const void *state_dev, const float *feat_dev, const uint8_t *pos
                  std::make_integer_sequence<int, KO_NN_MAX_TOKENS>{});
     NN_LAUNCHED();
     return KO_OK;
+}
+
+size_t ko_nn_split_table_bytes(int32_t n)
+{
+    if (n < 1 || n > KO_NN_MAX_TOKENS)
+        return 0;
+    return (size_t)2 * kHid * kSplitK(n) * sizeof(uint16_t);
+}
+
+int ko_nn_split_table(const void *state_dev, const float *feat_dev, int32_t n, uint16_t *split_dev,
+                      void *hip_stream)
+{
+    if (!state_dev || !feat_dev || !split_dev)
+        return fail(KO_EINVAL, "state, features and table must not be NULL");
+    if (n < 1 || n > KO_NN_MAX_TOKENS)
+        return fail(KO_EINVAL, "n must be in 1..%d", KO_NN_MAX_TOKENS);
+    if (((uintptr_t)split_dev & 15u) != 0)
+        return fail(KO_EINVAL, "the table must be 16-byte aligned");
+    State s = state_of(const_cast<void *>(state_dev));
+    const int32_t KP = kSplitK(n);
+    hipLaunchKernelGGL(split_table_kernel, dim3((unsigned)((KP + 255) / 256), kHid), dim3(256), 0, (hipStream_t)hip_stream,
+                       s.wb, s.master, feat_dev, n, KP, split_dev);
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+int ko_nn_score_split_acc(const void *state_dev, const uint16_t *split_dev, const uint8_t *pos_dev, int32_t B,
+                          int32_t n, float scale, int32_t accumulate, float *y_dev, void *hip_stream)
+{
+    if (!state_dev || !split_dev || !pos_dev || !y_dev)
+        return fail(KO_EINVAL, "state, table, positions and y must not be NULL");
+    if (B < 1 || n < 1 || n > KO_NN_MAX_TOKENS)
+        return fail(KO_EINVAL, "B must be >= 1 and n in 1..%d", KO_NN_MAX_TOKENS);
+    if (((uintptr_t)split_dev & 15u) != 0)
+        return fail(KO_EINVAL, "the table must be 16-byte aligned");
+    const State s = state_of(const_cast<void *>(state_dev));
+    const unsigned grid = (unsigned)(((int64_t)B + kSpRows - 1) / kSpRows);
+    launch_score_split(n, grid, (hipStream_t)hip_stream, s.wb, s.master, split_dev, pos_dev, B, scale,
+                       accumulate ? 1 : 0, y_dev, std::make_integer_sequence<int, KO_NN_MAX_TOKENS>{});
+    NN_LAUNCHED();
+    return KO_OK;
+}
+
+int ko_nn_score_split(const void *state_dev, const uint16_t *split_dev, const uint8_t *pos_dev, int32_t B,
+                      int32_t n, float *y_dev, void *hip_stream)
+{
+    return ko_nn_score_split_acc(state_dev, split_dev, pos_dev, B, n, 1.f, 0, y_dev, hip_stream);
 }
 
 int ko_nn_beam_expand(const uint8_t *prefix_dev, int32_t W, int32_t d, int32_t n, uint8_t *pos_dev,

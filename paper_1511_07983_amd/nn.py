@@ -38,6 +38,7 @@ EXPORTED = ("ko_nn_num_params", "ko_nn_state_bytes", "ko_nn_work_bytes", "ko_nn_
             "ko_nn_backward", "ko_nn_adam", "ko_nn_layer1_table", "ko_nn_score_work_bytes",
             "ko_nn_forward_positions", "ko_nn_score", "ko_nn_beam_expand", "ko_nn_beam_cap", "ko_nn_beam_gather",
             "ko_nn_train_step", "ko_nn_batch", "ko_nn_step_capture", "ko_nn_graph_launch", "ko_nn_graph_destroy",
+            "ko_nn_split_table_bytes", "ko_nn_split_table", "ko_nn_score_split", "ko_nn_score_split_acc",
             "ko_nn_last_error")
 
 _vp = ctypes.c_void_p
@@ -71,11 +72,18 @@ _lib.ko_nn_step_capture.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                     _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
 _lib.ko_nn_graph_launch.argtypes = [_vp, _vp]
 _lib.ko_nn_graph_destroy.argtypes = [_vp]
+_lib.ko_nn_split_table_bytes.argtypes = [ctypes.c_int32]
+_lib.ko_nn_split_table_bytes.restype = ctypes.c_size_t
+_lib.ko_nn_split_table.argtypes = [_vp, _vp, ctypes.c_int32, _vp, _vp]
+_lib.ko_nn_score_split.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
+_lib.ko_nn_score_split_acc.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_int32,
+                                       _vp, _vp]
 _lib.ko_nn_last_error.restype = ctypes.c_char_p
 for _f in ("ko_nn_load", "ko_nn_read", "ko_nn_features", "ko_nn_lower_bound", "ko_nn_tokens", "ko_nn_targets",
            "ko_nn_forward", "ko_nn_backward", "ko_nn_adam", "ko_nn_layer1_table", "ko_nn_within_set_ranks",
            "ko_nn_forward_positions", "ko_nn_score", "ko_nn_beam_expand", "ko_nn_beam_cap", "ko_nn_beam_gather",
-           "ko_nn_train_step", "ko_nn_batch", "ko_nn_step_capture", "ko_nn_graph_launch", "ko_nn_graph_destroy"):
+           "ko_nn_train_step", "ko_nn_batch", "ko_nn_step_capture", "ko_nn_graph_launch", "ko_nn_graph_destroy",
+           "ko_nn_split_table", "ko_nn_score_split", "ko_nn_score_split_acc"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -296,6 +304,32 @@ class Surrogate:
             y = torch.empty(B, dtype=torch.float32, device=self.device)
         _check(_lib.ko_nn_score(self.state.data_ptr(), feat.data_ptr(), pos.data_ptr(), B, n, y.data_ptr(),
                                 _stream_handle(stream)))
+        return y
+
+    def split_table(self, feat, stream=None):
+        """feat: device float32 [n, 8] of one set -> its split layer-1 table
+        (device int16 [2, 256, KP], the BF16 high and low parts) for score_split."""
+        n = feat.shape[0]
+        kp = int(_lib.ko_nn_split_table_bytes(n)) // (2 * D_HID * 2)
+        split = self.torch.empty((2, D_HID, kp), dtype=self.torch.int16, device=self.device)
+        _check(_lib.ko_nn_split_table(self.state.data_ptr(), feat.data_ptr(), n, split.data_ptr(),
+                                      _stream_handle(stream)))
+        return split
+
+    def score_split(self, split, pos, y=None, scale: float = 1.0, accumulate: bool = False, stream=None):
+        """pos: device uint8 [B, n] -> y [B], the pooling on the matrix cores
+        from the set's split table: y = scale * score, or y + scale * score
+        with accumulate (ko_nn_score_split_acc)."""
+        B, n = pos.shape
+        if split.numel() * 2 != int(_lib.ko_nn_split_table_bytes(n)):
+            raise ValueError("the split table was made for another number of kernels")
+        if y is None:
+            if accumulate:
+                raise ValueError("accumulate needs y")
+            y = self.torch.empty(B, dtype=self.torch.float32, device=self.device)
+        _check(_lib.ko_nn_score_split_acc(self.state.data_ptr(), split.data_ptr(), pos.data_ptr(), B, n,
+                                          float(scale), 1 if accumulate else 0, y.data_ptr(),
+                                          _stream_handle(stream)))
         return y
 
     def train_step(self, x, t, sched_dev, loss=None, stream=None):

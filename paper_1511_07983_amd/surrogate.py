@@ -183,12 +183,48 @@ def train(sur: "nn.Surrogate", table: SetTable, data: Samples, *, steps: int, ba
     return log
 
 
+class Ensemble:
+    """Several scorers trained alike from different initial weights and
+    minibatch orders; an order's score is their mean, computed in the scoring
+    kernel (ko_nn_score_split_acc: the first member writes score / m, each
+    other adds its score / m, in member order).  Exposes the scorer calls the
+    searches use (split_table, score_split)."""
+
+    def __init__(self, members):
+        self.members = list(members)
+
+    def split_table(self, feat):
+        return [m.split_table(feat) for m in self.members]
+
+    def score_split(self, split, pos, y=None, stream=None):
+        scale = 1.0 / len(self.members)
+        for k, (m, t) in enumerate(zip(self.members, split)):
+            y = m.score_split(t, pos, y=y, scale=scale, accumulate=k > 0, stream=stream)
+        return y
+
+
+def train_members(table: SetTable, data: Samples, members: int, *, seed: int, steps: int, batch: int, lr: float,
+                  log_every: int):
+    """`members` scorers on the same samples: member k starts from the weights
+    of seed + 1000 k and draws its minibatches with seed + 1 + 1000 k.
+    Returns (the ensemble, the first member's loss log)."""
+    models, first_log = [], None
+    for k in range(members):
+        sur = nn.Surrogate(_init_params(seed + 1000 * k))
+        log = train(sur, table, data, steps=steps, batch=batch, lr=lr, warmup=min(200, steps // 10),
+                    seed=seed + 1 + 1000 * k, log_every=log_every)
+        first_log = first_log or log
+        models.append(sur)
+    return Ensemble(models), first_log
+
+
 def predict(sur: "nn.Surrogate", table: SetTable, set_index: int, pos):
     """Scores of one set's orders given as positions [B, n] (device), float64
     host: lower is better.  With rank-quantile training a score estimates the
     order's quantile among the set's orders; with "lb" training it is cycles
     above the set's best over its lower bound."""
-    return sur.score(table.feat[set_index], pos).cpu().numpy().astype(np.float64)
+    split = sur.split_table(table.feat[set_index])
+    return sur.score_split(split, pos).cpu().numpy().astype(np.float64)
 
 
 def mae_cycles(res: "SearchResult", q: Quantile, target: str, lb: float) -> float:
@@ -265,13 +301,13 @@ def score_and_rerank(sur: "nn.Surrogate", table: SetTable, set_index: int, *, n_
     """Score `n_score` sampled orders, keep the `top_k` best predicted, re-simulate them exactly."""
     torch = _torch()
     n = table.n
-    feat = table.feat[set_index]
+    split = sur.split_table(table.feat[set_index])
     scores = torch.empty(n_score, dtype=torch.float32, device=device)
     pos = torch.empty(min(batch, n_score) * n, dtype=torch.uint8, device=device)
     for b0 in range(0, n_score, batch):
         c = min(batch, n_score - b0)
         ko_sample_orders(n, set_index, seed, c, first=b0, positions=pos[:c * n])
-        sur.score(feat, pos[:c * n].view(c, n), y=scores[b0:b0 + c])
+        sur.score_split(split, pos[:c * n].view(c, n), y=scores[b0:b0 + c])
     idx, val = ko_topk_f32(scores, top_k)
     orders = torch.empty(top_k * n, dtype=torch.uint8, device=device)
     ko_sample_orders(n, set_index, seed, top_k, indices=idx, orders=orders)
@@ -290,7 +326,7 @@ def beam_search(sur: "nn.Surrogate", table: SetTable, set_index: int, *, width: 
     """Grow orders position by position on the device, keeping the `width`
     best-scored prefixes (kernels not yet placed are "unplaced").  Each step
     expands every kept prefix by each unused kernel (ko_nn_beam_expand),
-    scores the partial orders (ko_nn_score), applies the diversity rules
+    scores the partial orders (ko_nn_score_split), applies the diversity rules
     (ko_nn_beam_cap: at most `max_children` children of one prefix survive,
     and with temperature > 0 Gumbel noise perturbs the scores, seeded per
     step), keeps the best (ko_topk_f32) and gathers their prefixes
@@ -298,14 +334,14 @@ def beam_search(sur: "nn.Surrogate", table: SetTable, set_index: int, *, width: 
     noise; they are ranked by that score and re-simulated exactly."""
     torch = _torch()
     n = table.n
-    feat = table.feat[set_index]
+    split = sur.split_table(table.feat[set_index])
     prefix = torch.empty((1, 0), dtype=torch.uint8, device=device)
     n_scored = 0
     val = None
     for d in range(n):
         W, m = prefix.shape[0], n - d
         pos, cand = nn.beam_expand(prefix, n)
-        scores = sur.score(feat, pos)
+        scores = sur.score_split(split, pos)
         n_scored += W * m
         last = d == n - 1
         if not last and (max_children > 0 or temperature > 0):
@@ -351,12 +387,13 @@ def _init_params(seed: int) -> np.ndarray:
 def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: int = 8192,
            per_set: int = 512, heldout: int = 8, n_score: int = 100_000_000, top_k: int = 10_000,
            steps: int = 65536, batch: int = 4096, lr: float = 1e-3, seed: int = 2015, target: str = "quantile",
-           quantiles: dict | None = None, out=print):
-    """Train on exact samples, then per held-out set: exact top-1% threshold by
-    full enumeration, scoring of `n_score` sampled orders, exact re-simulation
-    of the `top_k` best.  Prints one JSON line per held-out set and a summary.
-    `quantiles` (held-out set index -> Quantile), when given, keeps the
-    thresholds of earlier calls on the same held-out sets and is filled in."""
+           members: int = 4, quantiles: dict | None = None, out=print):
+    """Train `members` scorers on exact samples (an Ensemble), then per
+    held-out set: exact top-1% threshold by full enumeration, scoring of
+    `n_score` sampled orders, exact re-simulation of the `top_k` best.  Prints
+    one JSON line per held-out set and a summary.  `quantiles` (held-out set
+    index -> Quantile), when given, keeps the thresholds of earlier calls on
+    the same held-out sets and is filled in."""
     import json
     import time
 
@@ -369,14 +406,13 @@ def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: i
     data = exact_samples(table, per_set, seed=seed, target=target)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    sur = nn.Surrogate(_init_params(seed + 1))
     t0 = time.perf_counter()
-    log = train(sur, table, data, steps=steps, batch=batch, lr=lr, warmup=min(200, steps // 10),
-                seed=seed + 2, log_every=max(1, steps // 8))
+    sur, log = train_members(table, data, members, seed=seed + 1, steps=steps, batch=batch, lr=lr,
+                             log_every=max(1, steps // 8))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     out(json.dumps({"phase": "train", "target": target, "samples": data.count, "sets": train_sets, "n": table.n,
-                    "data_s": round(t_data, 3), "train_s": round(t_train, 3), "steps": steps,
+                    "members": members, "data_s": round(t_data, 3), "train_s": round(t_train, 3), "steps": steps,
                     "batch": batch, "loss": log}), flush=True)
     del data
     model = synth.WORKLOADS[heldout_workload].model
@@ -426,8 +462,8 @@ def _search_row(exact_ranked: np.ndarray, exact: np.ndarray, threshold, random_e
 def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets: int = 8192, per_set: int = 512,
                 eval_sets: int = 1024, width: int = 256, q_samples: int = 4096, steps: int = 32768,
                 batch: int = 4096, lr: float = 1e-3, mask_frac: float = 0.25, seed: int = 2016,
-                max_children: int = 2, temperature: float = 0.0, n_score: int = 1 << 20, sur=None,
-                out=print):
+                max_children: int = 2, temperature: float = 0.0, n_score: int = 1 << 20, members: int = 4,
+                sur=None, out=print):
     """Surrogate-guided search on n=16 sets against uniform sampling at the
     same exact budget (`width` exact simulations per set): beam search (width
     `width`, at most `max_children` children per prefix per step, optional
@@ -450,13 +486,12 @@ def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets:
         tr = [synth.draw_set(train_workload, s) for s in range(train_sets)]
         table = SetTable.build(synth.WORKLOADS[train_workload].model, tr)
         data = mask_suffixes(exact_samples(table, per_set, seed=seed, target="quantile"), mask_frac, seed + 1)
-        sur = nn.Surrogate(_init_params(seed + 2))
-        log = train(sur, table, data, steps=steps, batch=batch, lr=lr, warmup=min(200, steps // 10),
-                    seed=seed + 3, log_every=max(1, steps // 8))
+        sur, log = train_members(table, data, members, seed=seed + 2, steps=steps, batch=batch, lr=lr,
+                                 log_every=max(1, steps // 8))
         torch.cuda.synchronize()
         out(json.dumps({"phase": "train", "sets": train_sets, "n": table.n, "samples": data.count,
-                        "mask_frac": mask_frac, "train_s": round(time.perf_counter() - t0, 2), "loss": log}),
-            flush=True)
+                        "mask_frac": mask_frac, "members": members, "train_s": round(time.perf_counter() - t0, 2),
+                        "loss": log}), flush=True)
         del data
     model = synth.WORKLOADS[eval_workload].model
     ev = [synth.draw_set(eval_workload, s) for s in range(eval_sets)]
@@ -555,14 +590,15 @@ if __name__ == "__main__":
     ap.add_argument("--temperature", type=float, default=0.0, help="beam: Gumbel noise on each step's scores")
     ap.add_argument("--beam-n-score", type=int, default=1 << 20,
                     help="--beam: orders scored per set by sample-then-score")
+    ap.add_argument("--members", type=int, default=4, help="scorers trained and averaged (an ensemble)")
     a = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     if a.beam:
         report_beam(train_sets=a.train_sets, per_set=a.per_set, eval_sets=a.eval_sets, width=a.width,
                     steps=a.steps, batch=a.batch, lr=a.lr, max_children=a.max_children,
-                    temperature=a.temperature, n_score=a.beam_n_score)
+                    temperature=a.temperature, n_score=a.beam_n_score, members=a.members)
         raise SystemExit(0)
     report(train_workload=a.train_workload, heldout_workload=a.heldout_workload, train_sets=a.train_sets,
            per_set=a.per_set, heldout=a.heldout, n_score=a.n_score, top_k=a.top_k, steps=a.steps,
-           batch=a.batch, lr=a.lr, target=a.target)
+           batch=a.batch, lr=a.lr, target=a.target, members=a.members)

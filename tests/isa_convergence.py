@@ -224,18 +224,25 @@ def _transfer(inst: Inst, exec_state: str, tok: dict):
     if m.endswith("saveexec_b64") and ops:
         d = _pair(ops[0])
         src = _pair(ops[1]) if len(ops) > 1 else None
+        new_exec = PARTIAL
         if m == "s_and_saveexec_b64":
             new_tok = ("save", exec_state)
         elif m == "s_andn2_saveexec_b64" and tok.get(src, ("", None))[0] == "save":
             # exec = S & ~exec, D = old exec: D and the new exec partition what S restored
             new_tok = ("save", tok[src][1])
+        elif m == "s_or_saveexec_b64" and tok.get(src, ("", None))[0] == "save":
+            # the else entry of an if/else: S holds the lanes that the then-block
+            # (the current exec) lacks, so exec | S is the state S restores, and
+            # D = the then-lanes restore it again after the else-block
+            new_tok = ("save", tok[src][1])
+            new_exec = tok[src][1]
         else:
             new_tok = None
         if d is not None:
             _drop(tok, (d, d + 1))
             if new_tok:
                 tok[d] = new_tok
-        return PARTIAL
+        return new_exec
     if ops and ops[0] == "exec":
         if m == "s_or_b64" and len(ops) == 3 and "exec" in ops[1:]:
             other = ops[2] if ops[1] == "exec" else ops[1]

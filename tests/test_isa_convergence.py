@@ -137,7 +137,8 @@ def test_sort_scatter_collectives_full_exec(select_report):
 
 @pytest.mark.parametrize("needle", ["out_forward_kernel", "head_kernel", "colsum_multi_kernel", "finish_kernel",
                                     "dz1_kernel", "pool_kernel", "gather_pool_kernel", "within_set_rank_kernel",
-                                    "gemm_bf16_kernel", "gemm_nt_kernel", "panel_gemm_kernel", "score_kernel"])
+                                    "gemm_bf16_kernel", "gemm_nt_kernel", "panel_gemm_kernel", "score_kernel",
+                                    "score_split_kernel", "split_table_kernel"])
 def test_surrogate_collectives_full_exec(nn_report, needle):
     for name in _pick(nn_report, needle):
         bad, _ = nn_report[name]
@@ -219,3 +220,34 @@ def test_readfirstlane_of_a_lane_varying_value_is_reported(define):
     asm = SCALAR_SOURCE_ASM.replace("v_sub_co_u32_e64 v0, s[6:7], s2, 1", define)
     (bad, _), = ic.check(asm).values()
     assert [t for _, t in bad] == ["v_readfirstlane_b32 s1, v0"]
+
+
+IF_ELSE_ASM = """
+kern:
+	v_cmp_lt_u32_e32 vcc, s4, v0
+	s_and_saveexec_b64 s[4:5], vcc
+	s_xor_b64 s[4:5], exec, s[4:5]
+	v_lshrrev_b32_e32 v18, 2, v0
+	s_or_saveexec_b64 s[14:15], s[4:5]
+	s_xor_b64 exec, exec, s[14:15]
+	s_cbranch_execz .LBB0_2
+	v_mov_b32_e32 v1, 1
+	ds_bpermute_b32 v2, v3, v1
+.LBB0_2:
+	s_or_b64 exec, exec, s[14:15]
+	ds_bpermute_b32 v2, v3, v1
+	s_endpgm
+.Lfunc_end0:
+"""
+
+
+def test_if_else_restores_exec():
+    """The if/else idiom (then-lanes saved, the complement taken with xor, the
+    else entered with or_saveexec, exec restored with or): a cross-lane
+    instruction inside the else-block runs with lanes masked off, the one
+    after the construct with all lanes."""
+    (bad, _), = ic.check(IF_ELSE_ASM).values()
+    assert [i for i, _ in bad] == [bad[0][0]] and len(bad) == 1, bad
+    lines = IF_ELSE_ASM.strip().splitlines()
+    inside = next(k for k, l in enumerate(lines) if "ds_bpermute" in l)
+    assert "ds_bpermute" in lines[inside] and bad[0][1] == lines[inside].strip()

@@ -280,3 +280,112 @@ def test_fused_score_equals_table_path_bit_for_bit(B, n):
     m = min(B, 256)
     yo, _ = mlp.forward(mlp.unflatten(flat.astype(np.float64)), X[:m])
     assert np.abs(y_fused[:m] - yo).max() <= 1e-3 * (1.0 + np.abs(yo).max())
+
+
+def _split_bf16(T):
+    """hi = bf16(T), lo = bf16(T - hi) of float32 values, both as float64."""
+    T = np.asarray(T, dtype=np.float32)
+    hi = mlp.bf16(T)
+    lo = mlp.bf16((T.astype(np.float64) - hi).astype(np.float32))
+    return hi, lo
+
+
+def _slot_table(T, n):
+    """Rows of the layer-1 table T [n, 17, 256] in slot order: kernel i's
+    slots are its positions 0..n-1, then "unplaced" (16)."""
+    slots = list(range(n)) + [mlp.UNPLACED]
+    return T[:, slots, :].reshape(n * (n + 1), mlp.D_HID)
+
+
+@pytest.mark.parametrize("B,n", [(1, 1), (63, 5), (64, 16), (65, 12), (1000, 12), (4097, 9), (300, 16)])
+def test_split_score_matches_its_definition_and_oracle(B, n):
+    """ko_nn_score_split (pooling as a one-hot MFMA product with the table in
+    BF16 high and low parts, n + 1 slots per kernel): the split table is
+    exactly hi = bf16(T) and lo = bf16(T - hi) of the layer-1 table in slot
+    order.  y is compared with the oracle's layers applied to S = sum over
+    kernels of (hi + lo) (float64 sums), the path's definition: the device's S
+    differs from it only by float32 accumulation, so a row differs only where
+    that moves S across a BF16 rounding boundary (as for every path): at most
+    1% of the rows (or 2) by more than 1e-5 (1 + |y|), none by more than 1e-2
+    (1 + |y|).  Against the token model the 2^-17 representation of T adds about
+    one such BF16 flip of S per row (probability about 2^-8 per element),
+    each moving y by at most 2^-8 of one S element's contribution: every row
+    of the first 256 within 1e-2 (1 + max |y|)."""
+    rng, flat, feat, pos, X = make_case(90 + B + n, B, n)
+    if B > 3:
+        pos[2, :] = 200  # positions above 16 count as unplaced
+        X[2, :, mlp.N_FEAT:] = 0.0
+        X[2, :, mlp.N_FEAT + mlp.UNPLACED] = 1.0
+    say(f"split score B={B} n={n}")
+    model = nn.Surrogate(flat)
+    f = torch.from_numpy(feat[0]).to("cuda:0")
+    p = torch.from_numpy(pos).to("cuda:0")
+    T = model.layer1_table(f).cpu().numpy()                     # [n, 17, 256] float32
+    split = model.split_table(f)
+    got = split.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    got = got.view(np.float32).astype(np.float64)              # [2, 256, KP]
+    K1 = n * (n + 1)
+    assert got.shape[2] == -(-K1 // 32) * 32
+    Ts = _slot_table(T, n)                                      # [K1, 256]
+    hi, lo = _split_bf16(Ts.T)                                  # [256, K1]
+    assert np.array_equal(got[0, :, :K1], hi) and np.array_equal(got[1, :, :K1], lo)
+    assert not got[:, :, K1:].any()
+    assert np.abs(hi + lo - Ts.T).max() <= 2.0 ** -17 * np.abs(Ts).max()
+    y = model.score_split(split, p).cpu().numpy().astype(np.float64)
+    slot = np.where(pos.astype(np.int64) < n, pos.astype(np.int64), n)
+    S = (hi + lo).T[np.arange(n)[None, :] * (n + 1) + slot].sum(axis=1)  # [B, 256]
+    p64 = mlp.unflatten(flat.astype(np.float64))
+    ys, _ = mlp.from_pooled(p64, S)
+    err = np.abs(y - ys)
+    flips = int(np.sum(err > 1e-5 * (1.0 + np.abs(ys))))
+    assert flips <= max(2, 0.01 * B), (flips, err.max())
+    assert np.all(err <= 1e-2 * (1.0 + np.abs(ys))), err.max()
+    m = min(B, 256)
+    yo, _ = mlp.forward(p64, X[:m])
+    assert np.abs(y[:m] - yo).max() <= 1e-2 * (1.0 + np.abs(yo).max())
+
+
+def test_split_score_flags_positions_outside_the_set():
+    """A position in n..15 is no launch position of an n-kernel order: that
+    row's y is NaN and the other rows are as without it."""
+    B, n = 200, 6
+    rng, flat, feat, pos, X = make_case(7, B, n)
+    model = nn.Surrogate(flat)
+    f = torch.from_numpy(feat[0]).to("cuda:0")
+    split = model.split_table(f)
+    y0 = model.score_split(split, torch.from_numpy(pos).to("cuda:0")).cpu().numpy()
+    bad = pos.copy()
+    bad[3, 2] = 9
+    bad[150, 0] = 15
+    y1 = model.score_split(split, torch.from_numpy(bad).to("cuda:0")).cpu().numpy()
+    assert np.isnan(y1[3]) and np.isnan(y1[150])
+    keep = np.setdiff1d(np.arange(B), [3, 150])
+    assert np.isfinite(y0).all() and np.array_equal(y0[keep], y1[keep])
+
+
+def test_split_score_accumulates_an_ensemble_mean():
+    """ko_nn_score_split_acc: the first member writes scale * score, the others
+    add scale * score in order; against the members' own scores combined the
+    same way in float32 (the device may fuse each multiply-add: one rounding
+    instead of two, within 2 ulp of the result)."""
+    B, n = 700, 12
+    models, splits, own = [], [], []
+    rng, _, feat, pos, _ = make_case(5, B, n)
+    f = torch.from_numpy(feat[0]).to("cuda:0")
+    p = torch.from_numpy(pos).to("cuda:0")
+    for k in range(3):
+        _, flat, _, _, _ = make_case(30 + k, 1, n)
+        m = nn.Surrogate(flat)
+        models.append(m)
+        splits.append(m.split_table(f))
+        own.append(m.score_split(splits[-1], p).cpu().numpy())
+    scale = np.float32(1.0 / 3.0)
+    y = None
+    for k, (m, t) in enumerate(zip(models, splits)):
+        y = m.score_split(t, p, y=y, scale=float(scale), accumulate=k > 0)
+    y = y.cpu().numpy()
+    want = scale * own[0]
+    for k in (1, 2):
+        want = want + scale * own[k]
+    assert np.all(np.abs(y - want) <= 2 * np.spacing(np.abs(want).astype(np.float32))), np.abs(y - want).max()
+    assert not np.array_equal(own[0], own[1])
