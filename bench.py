@@ -47,14 +47,13 @@ OPS_PER_BLOCK = 13
 
 # HBM bytes per all-orders launch of the simulate kernel on the n=10 set, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs calibrated against a 256 MiB copy
-# (profiles/ holds the summaries).  They hold for the kernel sources they were
-# measured on, identified by hash; any change to those sources reports null
-# until the counters are taken again.
+# (profiles/ holds the summaries).  They hold for the kernel sources and the
+# host's work decomposition they were measured on, identified by hash; any
+# change to those sources reports null until the counters are taken again.
 TRAFFIC_SOURCES = ("paper_1511_07983_amd/csrc/ko_sim.hip", "paper_1511_07983_amd/csrc/ko_lanes.hip",
                    "paper_1511_07983_amd/csrc/ko_wave.h", "paper_1511_07983_amd/csrc/ko_orders.h",
-                   "paper_1511_07983_amd/csrc/ko_device.h")
-TRAFFIC_MEASURED = {"adf2a7b445e22d0b": int((290.5 * 2 + 29839.2) * 1024),
-                    "3cfd7875dd257e69": int((291.0 * 2 + 29839.2) * 1024)}
+                   "paper_1511_07983_amd/csrc/ko_device.h", "paper_1511_07983_amd/csrc/ko_host.cpp")
+TRAFFIC_MEASURED = {"f76bafeef501dcee": int((287.5 * 2 + 33825.9) * 1024)}
 
 
 def measured_traffic():

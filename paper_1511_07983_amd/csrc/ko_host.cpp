@@ -703,7 +703,7 @@ int slots_for(int n_cu)
 // of spilled orders.
 int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *set_offsets,
               int32_t n_sets, const ko_order_spec *spec, int cu_count, uint64_t chunk_req, int wg_per_cu,
-              int engine, BatchPlan *plan, uint64_t max_items = uint64_t(1) << 22,
+              int engine, BatchPlan *plan, uint64_t max_items = uint64_t(1) << 23,
               uint64_t spill_limit = kSpillCap)
 {
     std::vector<uint64_t> per_set;
@@ -739,9 +739,18 @@ int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *
     // per CU at these kernels' register use), never more than there are items
     plan->lane_grid = std::max(1, cu_count * std::min(2 * wg_per_cu, 32));
     uint64_t chunk = chunk_req;
-    if (chunk == 0 && plan->lane_class) {
-        // at most 256 orders (4 per lane; measured best on the n=10 and batch
-        // workloads), fewer when that leaves under 4 items per resident wave
+    const bool ranks = spec->mode == KO_ORDERS_ALL || spec->mode == KO_ORDERS_RANK_RANGE;
+    if (chunk == 0 && plan->lane_class && ranks) {
+        // consecutive ranks: one order per lane per item.  Neighbouring ranks
+        // share prefixes, so lanes that start together run similar event
+        // sequences in step (measured: n=10 all orders 14.8 ms against 16.6 ms
+        // with 2 orders per lane and 18.9 ms with 4; the 4096-set batch alike)
+        chunk = 64;
+    } else if (chunk == 0 && plan->lane_class) {
+        // sampled or given orders are unrelated: up to 4 per lane, so that
+        // lanes that finish early take the next one (measured: n=12 sampled
+        // 56.8 ms against 65.6 ms with one per lane), fewer when that leaves
+        // under 4 items per resident wave
         const uint64_t waves = (uint64_t)std::max(1, cu_count) * 12;
         chunk = pow2_at_least(std::max<uint64_t>(1, plan->total / (waves * 4)));
         chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, 64), 256);

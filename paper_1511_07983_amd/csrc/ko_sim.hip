@@ -162,6 +162,109 @@ __global__ __launch_bounds__(256) void spill_kernel(SimArgs a, uint32_t gslots)
     }
 }
 
+// A set's statistics while they are folded: extremes with their indices
+// (ties -> the smaller index) and counts.  Folding is associative and
+// commutative, so any reduction tree gives the same result.
+struct Fold {
+    int64_t mn, mx;
+    uint64_t amn, amx, nl, ne, ng, cnt;
+};
+
+__device__ inline Fold fold_empty()
+{
+    return Fold{INT64_MAX, INT64_MIN, 0, 0, 0, 0, 0, 0};
+}
+
+__device__ inline void fold_extremes(Fold &f, int64_t mn, uint64_t amn, int64_t mx, uint64_t amx)
+{
+    if (mn < f.mn || (mn == f.mn && amn < f.amn)) {
+        f.mn = mn;
+        f.amn = amn;
+    }
+    if (mx > f.mx || (mx == f.mx && amx < f.amx)) {
+        f.mx = mx;
+        f.amx = amx;
+    }
+}
+
+__device__ inline void fold_join(Fold &f, const Fold &o)
+{
+    fold_extremes(f, o.mn, o.amn, o.mx, o.amx);
+    f.nl += o.nl;
+    f.ne += o.ne;
+    f.ng += o.ng;
+    f.cnt += o.cnt;
+}
+
+// This thread's share of a set: item partials i = first, first + stride, ...
+// and spilled orders likewise.
+__device__ inline Fold fold_set(const ReduceArgs &a, int set, uint32_t first, uint32_t stride)
+{
+    const SetRec st = a.sets[set];
+    const uint64_t items = (st.n_orders + a.chunk - 1) / a.chunk;
+    Fold f = fold_empty();
+    for (uint64_t i = first; i < items; i += stride) {
+        const Partial p = a.partials[st.item_base + i];
+        fold_extremes(f, p.min_ms, p.argmin, p.max_ms, p.argmax);
+        f.nl += p.n_less;
+        f.ne += p.n_equal;
+        f.ng += p.n_greater;
+        f.cnt += p.count;
+    }
+    if (a.spill) {
+        const bool ranked = a.mode == kModeAll || a.mode == kModeRange;
+        const int64_t ref = a.ref ? a.ref[set] : 0;
+        const uint64_t n_spill = min((uint64_t)*a.spill_count, a.spill_cap);
+        for (uint64_t r = first; r < n_spill; r += stride) {
+            const SpillRec rec = a.spill[r];
+            if (rec.set != (uint32_t)set || ((a.handed_bits[rec.item >> 5] >> (rec.item & 31u)) & 1u))
+                continue;
+            const int64_t m = rec.makespan;
+            const uint64_t idx = ranked ? st.rank_lo + rec.sample : rec.sample;
+            fold_extremes(f, m, idx, m, idx);
+            if (a.ref) {
+                f.nl += (m < ref) ? 1u : 0u;
+                f.ne += (m == ref) ? 1u : 0u;
+                f.ng += (m > ref) ? 1u : 0u;
+            }
+        }
+    }
+    return f;
+}
+
+// Fold across the wave (xor butterfly: every lane ends with the wave's fold).
+__device__ inline Fold fold_wave(Fold f)
+{
+    for (int o = 32; o >= 1; o >>= 1) {
+        Fold g;
+        g.mn = __shfl_xor(f.mn, o);
+        g.mx = __shfl_xor(f.mx, o);
+        g.amn = __shfl_xor(f.amn, o);
+        g.amx = __shfl_xor(f.amx, o);
+        g.nl = __shfl_xor(f.nl, o);
+        g.ne = __shfl_xor(f.ne, o);
+        g.ng = __shfl_xor(f.ng, o);
+        g.cnt = __shfl_xor(f.cnt, o);
+        fold_join(f, g);
+    }
+    return f;
+}
+
+__device__ inline void fold_store(const ReduceArgs &a, int set, const Fold &f)
+{
+    Partial *out = reinterpret_cast<Partial *>(a.stats) + set;
+    Partial p;
+    p.min_ms = f.mn;
+    p.max_ms = f.mx;
+    p.argmin = (f.cnt == 0) ? 0 : f.amn;
+    p.argmax = (f.cnt == 0) ? 0 : f.amx;
+    p.n_less = f.nl;
+    p.n_equal = f.ne;
+    p.n_greater = f.ng;
+    p.count = f.cnt;
+    *out = p;
+}
+
 // One wavefront per set: combine the set's Partials (ties -> smaller index)
 // and the set's spilled orders.
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
@@ -172,79 +275,32 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
     const int set = (int)(blockIdx.x * 4 + uniform(threadIdx.x >> 6));
     if (set >= a.n_sets)
         return;
-    const SetRec st = a.sets[set];
-    const uint64_t items = (st.n_orders + a.chunk - 1) / a.chunk;
-    int64_t mn = INT64_MAX, mx = INT64_MIN;
-    uint64_t amn = 0, amx = 0, nl = 0, ne = 0, ng = 0, cnt = 0;
-    for (uint64_t i = lane; i < items; i += kWave) {
-        const Partial p = a.partials[st.item_base + i];
-        if (p.min_ms < mn || (p.min_ms == mn && p.argmin < amn)) {
-            mn = p.min_ms;
-            amn = p.argmin;
-        }
-        if (p.max_ms > mx || (p.max_ms == mx && p.argmax < amx)) {
-            mx = p.max_ms;
-            amx = p.argmax;
-        }
-        nl += p.n_less;
-        ne += p.n_equal;
-        ng += p.n_greater;
-        cnt += p.count;
-    }
-    if (a.spill) {
-        const bool ranked = a.mode == kModeAll || a.mode == kModeRange;
-        const int64_t ref = a.ref ? a.ref[set] : 0;
-        const uint64_t n_spill = min((uint64_t)*a.spill_count, a.spill_cap);
-        for (uint64_t r = lane; r < n_spill; r += kWave) {
-            const SpillRec rec = a.spill[r];
-            if (rec.set != (uint32_t)set || ((a.handed_bits[rec.item >> 5] >> (rec.item & 31u)) & 1u))
-                continue;
-            const int64_t m = rec.makespan;
-            const uint64_t idx = ranked ? st.rank_lo + rec.sample : rec.sample;
-            if (m < mn || (m == mn && idx < amn)) {
-                mn = m;
-                amn = idx;
-            }
-            if (m > mx || (m == mx && idx < amx)) {
-                mx = m;
-                amx = idx;
-            }
-            if (a.ref) {
-                nl += (m < ref) ? 1u : 0u;
-                ne += (m == ref) ? 1u : 0u;
-                ng += (m > ref) ? 1u : 0u;
-            }
-        }
-    }
-    for (int o = 32; o >= 1; o >>= 1) {
-        const int64_t omn = __shfl_xor(mn, o), omx = __shfl_xor(mx, o);
-        const uint64_t oamn = __shfl_xor(amn, o), oamx = __shfl_xor(amx, o);
-        if (omn < mn || (omn == mn && oamn < amn)) {
-            mn = omn;
-            amn = oamn;
-        }
-        if (omx > mx || (omx == mx && oamx < amx)) {
-            mx = omx;
-            amx = oamx;
-        }
-        nl += __shfl_xor(nl, o);
-        ne += __shfl_xor(ne, o);
-        ng += __shfl_xor(ng, o);
-        cnt += __shfl_xor(cnt, o);
-    }
-    if (lane == 0) {
-        Partial *out = reinterpret_cast<Partial *>(a.stats) + set;
-        Partial p;
-        p.min_ms = mn;
-        p.max_ms = mx;
-        p.argmin = (cnt == 0) ? 0 : amn;
-        p.argmax = (cnt == 0) ? 0 : amx;
-        p.n_less = nl;
-        p.n_equal = ne;
-        p.n_greater = ng;
-        p.count = cnt;
-        *out = p;
-    }
+    const Fold f = fold_wave(fold_set(a, set, lane, kWave));
+    if (lane == 0)
+        fold_store(a, set, f);
+}
+
+// One workgroup of kWideWaves waves per set, for launches with few sets (a
+// set of all n! orders has tens of thousands of work items): each wave folds
+// its stride of the items and spills, the first wave folds the waves' results.
+constexpr int kWideWaves = 16;
+
+__global__ __launch_bounds__(kWideWaves * kWave) void reduce_wide_kernel(ReduceArgs a)
+{
+    __shared__ Fold part[kWideWaves];
+    const uint32_t lane = lane_id();
+    const int wave = (int)uniform(threadIdx.x >> 6);
+    const int set = (int)blockIdx.x;
+    Fold f = fold_wave(fold_set(a, set, threadIdx.x, kWideWaves * kWave));
+    if (lane == 0)
+        part[wave] = f;
+    __syncthreads();
+    if (wave != 0)
+        return;
+    f = lane < (uint32_t)kWideWaves ? part[lane] : fold_empty();
+    f = fold_wave(f);
+    if (lane == 0)
+        fold_store(a, set, f);
 }
 
 // Histogram of each set's makespans: LDS-private bins per workgroup when they
@@ -346,8 +402,18 @@ int launch_spill(const SimArgs &a, int slots_per_lane, uint32_t group_slots, int
     return (int)hipGetLastError();
 }
 
+// fewer sets than this: a workgroup of kWideWaves waves per set
+constexpr int kWideSets = 256;
+
 int launch_reduce(const ReduceArgs &a, void *stream)
 {
+    if (a.n_sets <= 0)
+        return 0;
+    if (a.n_sets < kWideSets) {
+        hipLaunchKernelGGL(reduce_wide_kernel, dim3((uint32_t)a.n_sets), dim3(kWideWaves * kWave), 0,
+                           (hipStream_t)stream, a);
+        return (int)hipGetLastError();
+    }
     const int grid = (a.n_sets + 3) / 4;
     hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
     return (int)hipGetLastError();

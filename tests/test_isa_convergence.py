@@ -120,8 +120,9 @@ def test_spill_kernel_collectives_full_exec(sim_report):
         assert bad == [], (name, bad[:5])
 
 
-def test_reduce_collectives_full_exec(sim_report):
-    for name in _pick(sim_report, "reduce_kernel"):
+@pytest.mark.parametrize("needle", ["reduce_kernel", "reduce_wide_kernel"])
+def test_reduce_collectives_full_exec(sim_report, needle):
+    for name in _pick(sim_report, needle):
         bad, _ = sim_report[name]
         assert bad == [], (name, bad[:5])
 
