@@ -47,22 +47,23 @@ OPS_PER_BLOCK = 13
 
 # HBM bytes per all-orders launch of the simulate kernel on the n=10 set, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs calibrated against a 256 MiB copy
-# (profiles/ holds the summaries).  They hold for the kernel sources and the
-# host's work decomposition they were measured on, identified by hash; any
-# change to those sources reports null until the counters are taken again.
+# (profiles/ holds the summaries).  They hold for the kernel sources they were
+# measured on (identified by hash) and for the launch's work decomposition
+# (orders per work item and item count, which set the partials written); any
+# change to either reports null until the counters are taken again.
 TRAFFIC_SOURCES = ("paper_1511_07983_amd/csrc/ko_sim.hip", "paper_1511_07983_amd/csrc/ko_lanes.hip",
                    "paper_1511_07983_amd/csrc/ko_wave.h", "paper_1511_07983_amd/csrc/ko_orders.h",
-                   "paper_1511_07983_amd/csrc/ko_device.h", "paper_1511_07983_amd/csrc/ko_host.cpp")
-TRAFFIC_MEASURED = {"f76bafeef501dcee": int((287.5 * 2 + 33825.9) * 1024)}
+                   "paper_1511_07983_amd/csrc/ko_device.h")
+TRAFFIC_MEASURED = {"6b4d66087255b56b:64:56700": int((287.5 * 2 + 33825.9) * 1024)}
 
 
-def measured_traffic():
+def measured_traffic(chunk: int, work_items: int):
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return TRAFFIC_MEASURED.get(h.hexdigest()[:16])
+    return TRAFFIC_MEASURED.get(f"{h.hexdigest()[:16]}:{chunk}:{work_items}")
 
 
 def parse():
@@ -357,6 +358,7 @@ def main():
     # the kernel the all-orders leg runs (the library picks the engine by set size)
     probe = ko.Plan(w.model, kernels, off, ko.OrderSpec.all())
     engine = probe.engine()[0]
+    probe_chunk, probe_items = probe.chunk, probe.work_items
     probe.close()
     if engine == ko.ENGINE_LANES:
         rc, gc = (12, 8) if n <= 8 else (12, 10) if n <= 10 else (16, 12) if n <= 12 else (20, 16)
@@ -433,7 +435,8 @@ def main():
                    "cu_model": w.model.n_cu, "seed": f"SeedSequence([20151123, {w.index}, 0])",
                    "histogram_bins": 1024},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "Top/s",
-                     "frac": achieved / ALU_PEAK_TOPS, "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
+                     "frac": achieved / ALU_PEAK_TOPS, "traffic": measured_traffic(probe_chunk, probe_items),
+                     "traffic_unit": "bytes per launch", "work_items": probe_items, "orders_per_item": probe_chunk,
                      "kernel": kernel_name, "kernel_ms": 1e3 * kernel_avg,
                      "ops_per_order": ops_per_order},
         "heuristic": {"order": ko.ko_heuristic_order(w.model, kernels), "pct_inclusive": pct,

@@ -748,11 +748,13 @@ int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *
         chunk = 64;
     } else if (chunk == 0 && plan->lane_class) {
         // sampled or given orders are unrelated: up to 4 per lane, so that
-        // lanes that finish early take the next one (measured: n=12 sampled
-        // 56.8 ms against 65.6 ms with one per lane), fewer when that leaves
-        // under 4 items per resident wave
+        // lanes that finish early take the next one, fewer when that leaves
+        // a resident wave without an item (measured: n=12, 4 M sampled orders,
+        // 56.8 ms against 65.6 ms with one per lane; n=16, 262,144 orders:
+        // 128 per item 43.5 ms, 64: 46.1 ms, 256: 68.1 ms; 1 M orders: 256
+        // per item 148 ms, 128: 163 ms)
         const uint64_t waves = (uint64_t)std::max(1, cu_count) * 12;
-        chunk = pow2_at_least(std::max<uint64_t>(1, plan->total / (waves * 4)));
+        chunk = pow2_at_least(std::max<uint64_t>(1, plan->total / waves));
         chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, 64), 256);
     } else if (chunk == 0) {
         // about 8 items per persistent wave; a batch smaller than that gets one
