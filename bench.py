@@ -54,7 +54,7 @@ OPS_PER_BLOCK = 13
 TRAFFIC_SOURCES = ("paper_1511_07983_amd/csrc/ko_sim.hip", "paper_1511_07983_amd/csrc/ko_lanes.hip",
                    "paper_1511_07983_amd/csrc/ko_wave.h", "paper_1511_07983_amd/csrc/ko_orders.h",
                    "paper_1511_07983_amd/csrc/ko_device.h")
-TRAFFIC_MEASURED = {"6b4d66087255b56b:64:56700": int((287.5 * 2 + 33825.9) * 1024)}
+TRAFFIC_MEASURED = {"9b2c17f82561299d:64:56700": int((282.2 * 2 + 33825.9) * 1024)}
 
 
 def measured_traffic(chunk: int, work_items: int):
@@ -288,11 +288,19 @@ def batch_leg() -> dict:
 def contended_leg(model, kernels, off, N, ops_per_order, mem_blocks: int = 256) -> dict:
     """All orders of the same set when resident blocks share the chip's memory
     throughput (mem_blocks = one memory-bound block per CU at full speed):
-    the wave engine's contended mode, HIP events around the simulate kernel."""
+    the engine the library picks (the lane engine for this set), HIP events
+    around the simulate kernel and its follow-up launches."""
     import torch
 
     import paper_1511_07983_amd as ko
     gpu = dict(model.as_dict(), mem_blocks=mem_blocks)
+    probe = ko.Plan(gpu, kernels, off, ko.OrderSpec.all())
+    engine = probe.engine()[0]
+    probe.close()
+    n = int(off[1] - off[0])
+    cls = 8 if n <= 8 else 10 if n <= 10 else 12 if n <= 12 else 16
+    kernel = (f"ko::simulate_lanes_kernel<{12 if cls <= 10 else 16 if cls == 12 else 20}, {cls}, contended>"
+              if engine == ko.ENGINE_LANES else "ko::simulate_kernel<4, true>")
     ms = torch.empty(N, dtype=torch.int64, device="cuda:0")
     st = torch.empty(8, dtype=torch.int64, device="cuda:0")
     spec = ko.OrderSpec.all()
@@ -308,7 +316,7 @@ def contended_leg(model, kernels, off, N, ops_per_order, mem_blocks: int = 256) 
     rec = ko.stats_records(st)[0]
     k = float(np.median(t))
     print("[bench] contended done", file=sys.stderr, flush=True)
-    return {"kernel": "ko::simulate_kernel<4, true>", "mem_blocks": mem_blocks, "orders": N,
+    return {"kernel": kernel, "mem_blocks": mem_blocks, "orders": N,
             "kernel_ms": 1e3 * k, "orders_per_s": N / k, "achieved": ops_per_order * N / k / 1e12,
             "frac": ops_per_order * N / k / 1e12 / ALU_PEAK_TOPS,
             "min_makespan": int(rec["min_makespan"]), "max_makespan": int(rec["max_makespan"])}

@@ -82,9 +82,10 @@ typedef struct ko_gpu_model {
  * block needs duration * 65536 units and ends at the first whole cycle at
  * which it has them; all blocks ending at a cycle release before placement
  * resumes; placement is unchanged.  With mem_blocks large enough that U never
- * exceeds the cap, makespans equal those of mem_blocks = 0.  This model runs
- * on the wave engine only (KO_ENGINE_LANES is refused); ko_heuristic_order
- * ignores mem_blocks, ko_simulate_rounds refuses a nonzero value. */
+ * exceeds the cap, makespans equal those of mem_blocks = 0.  Both engines
+ * model it (the lane engine keeps each group's progress in 64 bits and steps
+ * the drain event by event); ko_heuristic_order ignores mem_blocks,
+ * ko_simulate_rounds refuses a nonzero value. */
 
 /* The per-kernel parameters of Table 1 (last three rows).  40 bytes. */
 typedef struct ko_kernel {

@@ -85,7 +85,7 @@ def autotune(gpu, kernels, set_offsets, spec: OrderSpec, *, reps: int = 3, use_c
              engines=(ENGINE_WAVE, ENGINE_LANES), chunks=None, wgs=None, log=None):
     """Best (engine, chunk_log2, wg_per_cu) for this batch; every candidate must
     give the same makespans bit for bit.  An engine that does not apply to the
-    batch (the lane engine past 16 kernels or under memory contention) is left
+    batch (the lane engine past 16 kernels or 256 CUs) is left
     out.  `chunks`/`wgs` override the per-engine candidate lists.  Returns
     (config dict, sweep rows)."""
     import torch

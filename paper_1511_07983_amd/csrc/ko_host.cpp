@@ -725,10 +725,7 @@ int make_plan(const ko_gpu_model *gpu, const ko_kernel *kernels, const int32_t *
     }
     plan->slots = slots_for(gpu->n_cu);
     plan->grid = std::max(1, cu_count * wg_per_cu);
-    // memory contention runs on the wave engine only
-    plan->lane_class = (engine == KO_ENGINE_WAVE || gpu->mem_blocks) ? 0 : lane_class_for(*gpu, plan->max_n);
-    if (engine == KO_ENGINE_LANES && gpu->mem_blocks)
-        return fail(KO_EINVAL, "the lane engine does not model memory contention (mem_blocks > 0)");
+    plan->lane_class = engine == KO_ENGINE_WAVE ? 0 : lane_class_for(*gpu, plan->max_n);
     // a batch too small to fill the lanes finishes sooner with one wavefront
     // per order (one order alone: about 5 us against 0.35 ms for one lane)
     if (engine == KO_ENGINE_AUTO && plan->total < kLaneMinOrders)

@@ -37,6 +37,13 @@
 // simulate_kernel, which rewrites its makespans and partial (its records are
 // then ignored).  Results never depend on the capacities.
 //
+// Memory contention (CONT; Section 4, the model of ko_wave.h): a group keeps
+// its progress left in units (64 bits) and its blocks' summed memory share;
+// every resident block advances at the rate the resident shares allow, so an
+// event is the first whole cycle at which a group has its progress, and the
+// drain after the last placement is simulated event by event, since each
+// release changes the rate.
+//
 // A lane that finishes an order takes the next one of the work item from a
 // cursor in LDS, so the wave keeps all lanes busy until the item runs dry.
 // Everything between taking the item and combining the lanes' statistics is
@@ -46,6 +53,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ko_device.h"
 #include "ko_orders.h"
 
@@ -54,13 +63,13 @@ namespace {
 
 constexpr uint32_t kFree = 0xFFFFFFFFu;
 constexpr int kTab = 16;          // largest set of the lane kernels
-constexpr int kTabWords = 10 * kTab;
+constexpr int kTabWords = 11 * kTab;
 constexpr int kEntBase = kTabWords + 64;  // the item's order cursor, then the entries
 
 // LDS kernel table, struct of arrays (word offsets)
 enum : int { kTUa = 0, kTUb = kTab, kTReg = 2 * kTab, kTLds = 3 * kTab, kTWave = 4 * kTab,
              kTIReg = 5 * kTab, kTILds = 6 * kTab, kTIWave = 7 * kTab, kTDur = 8 * kTab,
-             kTBlk = 9 * kTab };
+             kTBlk = 9 * kTab, kTSh = 10 * kTab };
 
 __device__ __forceinline__ uint32_t lane_no() { return __lane_id(); }
 
@@ -78,6 +87,18 @@ __device__ __forceinline__ uint32_t quot_clamp(uint32_t fr, uint32_t u, float in
     uint32_t q = (uint32_t)((float)fr * inv);
     q = min(q, clamp);
     return q - ((__umul24(q, u) > fr) ? 1u : 0u);
+}
+
+// floor(x / d) for x < 2^53 and 1 <= d < 2^53: the binary64 quotient is off by
+// at most one, and one exact integer comparison each way corrects it.
+__device__ __forceinline__ uint64_t div_u53(uint64_t x, uint64_t d)
+{
+    uint64_t q = (uint64_t)((double)x / (double)d);
+    if (q * d > x)
+        q--;
+    else if (x - q * d >= d)
+        q++;
+    return q;
 }
 
 constexpr double fact_d(int k) { return k <= 1 ? 1.0 : k * fact_d(k - 1); }
@@ -132,12 +153,17 @@ __device__ __forceinline__ uint64_t identity_nibbles(uint32_t n)
 __device__ __forceinline__ uint32_t lowest_bit(uint32_t m) { return (uint32_t)__builtin_ctz(m); }
 __device__ __forceinline__ uint32_t lowest_bit(uint64_t m) { return (uint32_t)__builtin_ctzll(m); }
 
-template <int RC, int GC, typename Mask>
+template <int RC, int GC, typename Mask, bool CONT>
 struct LaneSim {
+    // group progress left: cycles, or (CONT) units of 1/65536 cycle at full rate
+    using Rel = typename std::conditional<CONT, uint64_t, uint32_t>::type;
+    static constexpr Rel kFreeRel = ~Rel(0);
     uint32_t A[RC], B[RC], cap[RC];
     uint32_t R;
-    uint32_t rel[GC];
+    Rel rel[GC];
     Mask gm[GC];
+    uint32_t gsh[CONT ? GC : 1];  // CONT: a group's summed memory share
+    uint32_t ush;                 // CONT: summed share of every resident block
     Mask used;
     uint64_t t;
     uint32_t ptr, pos, k, rem;  // the front kernel's parameters are read from the LDS table
@@ -169,9 +195,12 @@ struct LaneSim {
         R = 1;
 #pragma unroll
         for (int s = 0; s < GC; s++) {
-            rel[s] = kFree;
+            rel[s] = kFreeRel;
             gm[s] = 0;
+            if constexpr (CONT)
+                gsh[s] = 0;
         }
+        ush = 0;
         used = 0;
         t = 0;
         ptr = 0;
@@ -247,6 +276,7 @@ struct LaneSim {
         // read once: the entry stores below are LDS stores the compiler cannot
         // tell apart from the table
         const uint32_t ua = tab[kTUa + k], ub = tab[kTUb + k], dur = tab[kTDur + k];
+        const uint32_t shk = CONT ? tab[kTSh + k] : 0u;
         uint32_t T = 0, cmax = 0;
 #pragma unroll
         for (int j = 0; j < RC; j++) {
@@ -370,17 +400,22 @@ struct LaneSim {
         // the set size); written as a search that assigns as it goes, which
         // keeps rel and gm in registers
         bool placed = false;
+        const Rel start = CONT ? (Rel)dur << 16 : (Rel)dur;
 #pragma unroll
         for (int s = 0; s < GC; s++) {
-            const bool take = !placed && rel[s] == kFree;
-            rel[s] = take ? dur : rel[s];
+            const bool take = !placed && rel[s] == kFreeRel;
+            rel[s] = take ? start : rel[s];
             gm[s] = take ? mask : gm[s];
+            if constexpr (CONT)
+                gsh[s] = take ? q * shk : gsh[s];
             placed = placed || take;
         }
         if (!placed) {
             ovf = true;
             return false;
         }
+        if constexpr (CONT)
+            ush += q * shk;
         merge();
         rem -= q;
         return true;
@@ -388,25 +423,67 @@ struct LaneSim {
 
     // Advance to the earliest group end and release every group ending then.
     // Returns false if nothing is running (cannot happen for a valid set).
-    __device__ __forceinline__ bool advance(uint32_t n_cu, const uint32_t *tab, const uint32_t *ent)
+    // CONT: advance to the first whole cycle at which a group has its progress
+    // (every resident block gains `rate` units per cycle) and end the groups
+    // done then.  Returns their entry mask; `none` when nothing is running.
+    __device__ __forceinline__ Mask contended_event(uint64_t mem_cap, bool &none)
     {
-        const uint32_t lane = lane_no();
-        uint32_t dt = kFree;
+        uint64_t left = kFreeRel;
 #pragma unroll
         for (int s = 0; s < GC; s++)
-            dt = min(dt, rel[s]);
-        if (dt == kFree)
-            return false;
+            left = min(left, (uint64_t)rel[s]);
+        none = left == (uint64_t)kFreeRel;
+        if (none)
+            return 0;
+        const uint64_t rate = (uint64_t)ush <= mem_cap ? 65536ull : div_u53(65536ull * mem_cap, ush);
+        const uint64_t dt = div_u53(left + rate - 1, rate);
+        const uint64_t adv = dt * rate;
         t += dt;
         Mask ending = 0;
 #pragma unroll
         for (int s = 0; s < GC; s++) {
-            if (rel[s] != kFree) {
-                rel[s] -= dt;
-                if (rel[s] == 0) {
+            if (rel[s] != kFreeRel) {
+                if ((uint64_t)rel[s] <= adv) {
                     ending |= gm[s];
-                    rel[s] = kFree;
+                    ush -= gsh[CONT ? s : 0];
+                    rel[s] = kFreeRel;
                     gm[s] = 0;
+                    gsh[CONT ? s : 0] = 0;
+                } else {
+                    rel[s] -= (Rel)adv;
+                }
+            }
+        }
+        return ending;
+    }
+
+    __device__ __forceinline__ bool advance(uint32_t n_cu, const uint32_t *tab, const uint32_t *ent,
+                                            uint64_t mem_cap)
+    {
+        const uint32_t lane = lane_no();
+        Mask ending = 0;
+        if constexpr (CONT) {
+            bool none;
+            ending = contended_event(mem_cap, none);
+            if (none)
+                return false;
+        } else {
+            uint32_t dt = kFree;
+#pragma unroll
+            for (int s = 0; s < GC; s++)
+                dt = min(dt, rel[s]);
+            if (dt == kFree)
+                return false;
+            t += dt;
+#pragma unroll
+            for (int s = 0; s < GC; s++) {
+                if (rel[s] != kFree) {
+                    rel[s] -= dt;
+                    if (rel[s] == 0) {
+                        ending |= gm[s];
+                        rel[s] = kFree;
+                        gm[s] = 0;
+                    }
                 }
             }
         }
@@ -439,7 +516,7 @@ struct LaneSim {
         uint32_t m = 0;
 #pragma unroll
         for (int s = 0; s < GC; s++)
-            m = max(m, rel[s] == kFree ? 0u : rel[s]);
+            m = max(m, rel[s] == kFreeRel ? 0u : (uint32_t)rel[s]);
         return m;
     }
 };
@@ -450,10 +527,10 @@ struct LaneSim {
 // vector register, so its address counts as lane-varying: the atomic stays one
 // LDS atomic per active lane instead of becoming a compiler-built scan and
 // broadcast inside lane-divergent code.
-template <int RC, int GC, typename Mask>
+template <int RC, int GC, typename Mask, bool CONT>
 __device__ __forceinline__ bool take_order(const SimArgs &a, const SetRec &st, int set, uint64_t first,
                                            uint64_t index0, bool ranked, uint64_t count, const uint32_t *tab,
-                                           uint32_t *cursor, LaneSim<RC, GC, Mask> &L, uint32_t &i,
+                                           uint32_t *cursor, LaneSim<RC, GC, Mask, CONT> &L, uint32_t &i,
                                            uint64_t &perm)
 {
     uint32_t zero = 0;
@@ -485,7 +562,7 @@ __device__ __forceinline__ bool take_order(const SimArgs &a, const SetRec &st, i
     return true;
 }
 
-template <int RC, int GC, typename Mask>
+template <int RC, int GC, typename Mask, bool CONT>
 __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t ecap)
 {
     extern __shared__ uint32_t lane_lds[];
@@ -534,6 +611,7 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
             tab[kTIWave + lane] = __float_as_uint(q.inv_wave);
             tab[kTDur + lane] = q.dur;
             tab[kTBlk + lane] = q.tblk;
+            tab[kTSh + lane] = CONT ? a.share[st.kbase + lane] : 0u;
         }
         *cursor = 0u;  // every lane stores the same value
         __syncthreads();
@@ -551,12 +629,12 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
         // independently (no lane waits for the wave's longest order), and a
         // pass costs one bulk step whatever the lanes' phases (a new order's
         // first cycle places several kernels, over several passes).
-        LaneSim<RC, GC, Mask> L;
+        LaneSim<RC, GC, Mask, CONT> L;
         uint32_t i = 0;
         uint64_t perm = 0;
         bool live = take_order(a, st, set, first, index0, ranked, count, tab, cursor, L, i, perm);
         while (live) {
-            if (L.bulk_step(n_cu, tab, ent, ecap) && L.rem == 0) {
+            if (L.pos < n && L.bulk_step(n_cu, tab, ent, ecap) && L.rem == 0) {
                 L.pos++;
                 if (L.pos < n) {
                     // the next kernel may still place blocks at this cycle
@@ -568,11 +646,20 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
             int64_t m = -1;
             bool fin = false;
             if (!L.ovf) {
-                if (L.pos >= n) {
+                const bool drain = L.pos >= n;
+                if (!CONT && drain) {
+                    // every block is placed: the longest group left sets the makespan
                     m = (int64_t)(L.t + L.max_left());
                     fin = true;
-                } else if (!L.advance(n_cu, tab, ent)) {
-                    atomicOr(a.status, kStatusGroupOverflow);
+                } else if (!L.advance(n_cu, tab, ent, a.mem_cap)) {
+                    // CONT drain: every group has ended (one event per pass, since
+                    // each release changes the rate; its releases of runs are
+                    // no longer needed but harmless).  Otherwise nothing runs
+                    // yet the front block fits nowhere.
+                    if (drain)
+                        m = (int64_t)L.t;
+                    else
+                        atomicOr(a.status, kStatusGroupOverflow);
                     fin = true;
                 }
             }
@@ -657,6 +744,28 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
     }
 }
 
+template <bool CONT>
+int launch_lanes_t(const SimArgs &a, int set_class, uint32_t ecap, size_t lds, int grid, hipStream_t st)
+{
+    switch (set_class) {
+    case 8:
+        hipLaunchKernelGGL((simulate_lanes_kernel<12, 8, uint32_t, CONT>), dim3(grid), dim3(64), lds, st, a, ecap);
+        break;
+    case 10:
+        hipLaunchKernelGGL((simulate_lanes_kernel<12, 10, uint32_t, CONT>), dim3(grid), dim3(64), lds, st, a, ecap);
+        break;
+    case 12:
+        hipLaunchKernelGGL((simulate_lanes_kernel<16, 12, uint64_t, CONT>), dim3(grid), dim3(64), lds, st, a, ecap);
+        break;
+    case 16:
+        hipLaunchKernelGGL((simulate_lanes_kernel<20, 16, uint64_t, CONT>), dim3(grid), dim3(64), lds, st, a, ecap);
+        break;
+    default:
+        return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
 }  // namespace
 
 // Lane kernels exist for sets of up to 8, 10, 12 and 16 kernels, with `entries`
@@ -669,23 +778,9 @@ int launch_simulate_lanes(const SimArgs &a, int set_class, uint32_t entries, int
     if (ecap > (set_class <= 10 ? 32u : 64u))
         return (int)hipErrorInvalidValue;
     const size_t lds = (size_t)(kEntBase + ecap * kWave) * sizeof(uint32_t);
-    switch (set_class) {
-    case 8:
-        hipLaunchKernelGGL((simulate_lanes_kernel<12, 8, uint32_t>), dim3(grid), dim3(64), lds, st, a, ecap);
-        break;
-    case 10:
-        hipLaunchKernelGGL((simulate_lanes_kernel<12, 10, uint32_t>), dim3(grid), dim3(64), lds, st, a, ecap);
-        break;
-    case 12:
-        hipLaunchKernelGGL((simulate_lanes_kernel<16, 12, uint64_t>), dim3(grid), dim3(64), lds, st, a, ecap);
-        break;
-    case 16:
-        hipLaunchKernelGGL((simulate_lanes_kernel<20, 16, uint64_t>), dim3(grid), dim3(64), lds, st, a, ecap);
-        break;
-    default:
-        return (int)hipErrorInvalidValue;
-    }
-    return (int)hipGetLastError();
+    if (a.share)
+        return launch_lanes_t<true>(a, set_class, ecap, lds, grid, st);
+    return launch_lanes_t<false>(a, set_class, ecap, lds, grid, st);
 }
 
 }  // namespace ko

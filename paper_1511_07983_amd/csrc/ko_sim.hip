@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void simulate_kernel(SimArgs a, uint32_t gslot
 // Orders the lane kernel spilled: one wavefront per order, taken from an
 // atomic cursor over the records; records of work items that are re-run whole
 // are skipped.  Writes the makespan into the record and the makespan array.
-template <int S>
+template <int S, bool CONT>
 __global__ __launch_bounds__(256) void spill_kernel(SimArgs a, uint32_t gslots)
 {
     extern __shared__ uint32_t lds_ring[];
@@ -154,7 +154,8 @@ __global__ __launch_bounds__(256) void spill_kernel(SimArgs a, uint32_t gslots)
             if (bad || seen != (1u << n) - 1u)
                 perm = unrank_lanes(0, n);  // the lane kernel raised the status bit
         }
-        const int64_t m = simulate_order<S>(a, a.krec + st.kbase, nullptr, n, perm, ring, gslots);
+        const uint32_t *sh = CONT ? a.share + st.kbase : nullptr;
+        const int64_t m = simulate_order<S, CONT>(a, a.krec + st.kbase, sh, n, perm, ring, gslots);
         // every lane stores the same values
         a.spill[r].makespan = m;
         if (a.makespans)
@@ -382,24 +383,32 @@ int launch_simulate(const SimArgs &a, int slots_per_lane, uint32_t group_slots, 
     return launch_simulate_t<false>(a, slots_per_lane, group_slots, grid, stream);
 }
 
-int launch_spill(const SimArgs &a, int slots_per_lane, uint32_t group_slots, int grid, void *stream)
+template <bool CONT>
+int launch_spill_t(const SimArgs &a, int slots_per_lane, uint32_t group_slots, int grid, void *stream)
 {
     const size_t lds = (size_t)4 * group_slots * kWave * sizeof(uint32_t);
     hipStream_t st = (hipStream_t)stream;
     switch (slots_per_lane) {
     case 1:
-        hipLaunchKernelGGL(spill_kernel<1>, dim3(grid), dim3(256), lds, st, a, group_slots);
+        hipLaunchKernelGGL((spill_kernel<1, CONT>), dim3(grid), dim3(256), lds, st, a, group_slots);
         break;
     case 2:
-        hipLaunchKernelGGL(spill_kernel<2>, dim3(grid), dim3(256), lds, st, a, group_slots);
+        hipLaunchKernelGGL((spill_kernel<2, CONT>), dim3(grid), dim3(256), lds, st, a, group_slots);
         break;
     case 4:
-        hipLaunchKernelGGL(spill_kernel<4>, dim3(grid), dim3(256), lds, st, a, group_slots);
+        hipLaunchKernelGGL((spill_kernel<4, CONT>), dim3(grid), dim3(256), lds, st, a, group_slots);
         break;
     default:
         return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
+}
+
+int launch_spill(const SimArgs &a, int slots_per_lane, uint32_t group_slots, int grid, void *stream)
+{
+    if (a.share)
+        return launch_spill_t<true>(a, slots_per_lane, group_slots, grid, stream);
+    return launch_spill_t<false>(a, slots_per_lane, group_slots, grid, stream);
 }
 
 // fewer sets than this: a workgroup of kWideWaves waves per set

@@ -57,6 +57,18 @@ def gpu_all(gpu, ks):
     return gpu_batch(gpu, ks, [0, n], ko.OrderSpec.all(), math.factorial(n))
 
 
+def plan_run(gpu, kernels, offsets, spec, total, engine, lane_entries=0):
+    """Makespans and the engine report of a plan with a forced engine."""
+    plan = ko.Plan(gpu, kernels, offsets, spec, engine=engine, lane_entries=lane_entries)
+    ms = torch.full((max(total, 1),), -7, dtype=torch.int64, device=DEV)
+    st = torch.zeros(8 * (len(offsets) - 1), dtype=torch.int64, device=DEV)
+    plan.launch(makespans=ms, stats=st)
+    plan.status()
+    rep = plan.engine()
+    plan.close()
+    return ms[:total].cpu().numpy(), ko.stats_records(st), rep
+
+
 def test_e5_hand_trace_on_the_gpu(golden):
     g = golden("e5_contention.json")
     gpu = with_b(g["gpu"], g["mem_blocks"])
@@ -155,7 +167,93 @@ def test_plans_graphs_and_noalloc_agree():
     ms2 = torch.full((720,), -7, dtype=torch.int64, device=DEV)
     ko.ko_simulate_batch_noalloc(gpu, ks, [0, len(ks)], ko.OrderSpec.all(), makespans=ms2)
     np.testing.assert_array_equal(ms2.cpu().numpy(), want)
-    # the lane engine does not model contention: refused, not silently ignored
-    with pytest.raises(ko.KoError) as e:
-        ko.Plan(gpu, ks, [0, len(ks)], ko.OrderSpec.all(), engine=ko.ENGINE_LANES)
-    assert e.value.code == ko.KO_EINVAL
+    for engine in (ko.ENGINE_WAVE, ko.ENGINE_LANES):
+        ms3, _, rep = plan_run(gpu, ks, [0, len(ks)], ko.OrderSpec.all(), 720, engine)
+        assert rep[0] == engine
+        np.testing.assert_array_equal(ms3, want)
+
+
+@pytest.mark.parametrize("b", [1, 3, 16, 1 << 24])
+@pytest.mark.parametrize("entries", [0, 2])
+def test_lane_engine_all_720_orders(b, entries):
+    """The lane engine under contention, forced (the batch is below the size
+    at which the library picks it by itself), with the class's entry
+    capacity and with 2 entries per lane, which spills most orders to the
+    wave engine's contended routine."""
+    ks = synth.draw_set(0, 0)
+    gpu = with_b(synth.SMALL_MODEL, b)
+    say("lanes n=6 all orders, mem_blocks", b, "entries", entries)
+    ms, st, rep = plan_run(gpu, ks, [0, 6], ko.OrderSpec.all(), 720, ko.ENGINE_LANES, lane_entries=entries)
+    want = oracle.contended_makespans(synth.SMALL_MODEL.as_dict(), ks, b, first=0, count=720)
+    np.testing.assert_array_equal(ms, want)
+    assert st[0]["min_makespan"] == want.min() and st[0]["argmin"] == int(np.argmin(want))
+    assert st[0]["max_makespan"] == want.max() and st[0]["argmax"] == int(np.argmax(want))
+    if entries:
+        assert rep[2] > 0  # orders went through the spill path
+
+
+@pytest.mark.parametrize("b", [64, 256])
+def test_lane_engine_n10_window_and_samples(b):
+    ks = synth.draw_set(1, 0)
+    base = synth.MI355X_MODEL.as_dict()
+    gpu = with_b(base, b)
+    lo, cnt = 2_400_000, 4096
+    say("lanes n=10 rank window, mem_blocks", b)
+    ms, _, rep = plan_run(gpu, ks, [0, 10], ko.OrderSpec.rank_range([[lo, lo + cnt]]), cnt, ko.ENGINE_LANES)
+    assert rep[0] == ko.ENGINE_LANES
+    np.testing.assert_array_equal(ms, oracle.contended_makespans(base, ks, b, first=lo, count=cnt))
+    seed, ns = 77, 2048
+    ranks = [sampling.sampled_rank(seed, 0, i, math.factorial(10)) for i in range(ns)]
+    orders = np.array([oracle.unrank(10, r) for r in ranks], dtype=np.int32)
+    ms, _, _ = plan_run(gpu, ks, [0, 10], ko.OrderSpec.sampled([ns], seed), ns, ko.ENGINE_LANES)
+    np.testing.assert_array_equal(ms, oracle.contended_makespans(base, ks, b, orders))
+
+
+def test_lane_engine_uneven_batch_and_random_models():
+    """Sets of n = 4..9 under contention on the lane engine, explicit orders,
+    against the oracle; then small random models (CU counts 1..256)."""
+    kernels, offsets = synth.draw_sets(2, 0, 24)
+    base = synth.MI355X_MODEL.as_dict()
+    rng = np.random.default_rng(17)
+    per, rows, want = [], [], []
+    for s in range(24):
+        n = int(offsets[s + 1] - offsets[s])
+        ks = kernels[offsets[s]:offsets[s + 1]]
+        o = np.array([rng.permutation(n) for _ in range(64)], dtype=np.int32)
+        per.append(64)
+        rows.append(o.astype(np.uint8).ravel())
+        want.append(oracle.contended_makespans(base, ks, 96, o))
+    spec = ko.OrderSpec.explicit(torch.tensor(np.concatenate(rows), device=DEV), np.array(per, dtype=np.int64))
+    say("lanes 24 sets explicit, mem_blocks 96")
+    ms, _, rep = plan_run(with_b(base, 96), kernels, offsets, spec, sum(per), ko.ENGINE_LANES)
+    assert rep[0] == ko.ENGINE_LANES
+    np.testing.assert_array_equal(ms, np.concatenate(want))
+    for seed in range(4):
+        r = np.random.default_rng(2000 + seed)
+        n_cu = int(r.choice([1, 2, 5, 64, 130, 256]))
+        model = synth.GpuModel(n_cu=n_cu, wave_size=64, wave_cu=int(r.integers(4, 65)),
+                               blk_cu=int(r.integers(1, 17)), reg_cu=65536, lds_cu=65536,
+                               rb_milli=int(r.integers(500, 20000)))
+        n = int(r.integers(2, 8))
+        ks = synth.random_tiny_set(r, n, model, tblk_hi=int(r.integers(1, 4 * n_cu + 2)), inst_hi=60)
+        b = int(r.choice([1, 2, 7, 40]))
+        say("lanes random model", n_cu, "n", n, "mem_blocks", b)
+        ms, _, _ = plan_run(with_b(model, b), ks, [0, n], ko.OrderSpec.all(), math.factorial(n), ko.ENGINE_LANES)
+        np.testing.assert_array_equal(ms, oracle.contended_makespans(model.as_dict(), ks, b, first=0,
+                                                                     count=math.factorial(n)))
+
+
+def test_engines_agree_on_all_n10_orders():
+    """All 3,628,800 orders of the n=10 set at mem_blocks 256: the lane engine's
+    contended makespans equal the wave engine's element by element (each is
+    compared with the oracle on windows and samples above), with the same
+    extremes and counts."""
+    ks = synth.draw_set(1, 0)
+    gpu = with_b(synth.MI355X_MODEL, 256)
+    N = math.factorial(10)
+    say("n=10 all orders, both engines, mem_blocks 256")
+    lanes, st_l, rep_l = plan_run(gpu, ks, [0, 10], ko.OrderSpec.all(), N, ko.ENGINE_LANES)
+    wave, st_w, rep_w = plan_run(gpu, ks, [0, 10], ko.OrderSpec.all(), N, ko.ENGINE_WAVE)
+    assert rep_l[0] == ko.ENGINE_LANES and rep_w[0] == ko.ENGINE_WAVE
+    np.testing.assert_array_equal(lanes, wave)
+    assert st_l == st_w
