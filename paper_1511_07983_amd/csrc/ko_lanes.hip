@@ -611,7 +611,8 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
             tab[kTIWave + lane] = __float_as_uint(q.inv_wave);
             tab[kTDur + lane] = q.dur;
             tab[kTBlk + lane] = q.tblk;
-            tab[kTSh + lane] = CONT ? a.share[st.kbase + lane] : 0u;
+            if constexpr (CONT)
+                tab[kTSh + lane] = a.share[st.kbase + lane];
         }
         *cursor = 0u;  // every lane stores the same value
         __syncthreads();
@@ -634,7 +635,8 @@ __global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t 
         uint64_t perm = 0;
         bool live = take_order(a, st, set, first, index0, ranked, count, tab, cursor, L, i, perm);
         while (live) {
-            if (L.pos < n && L.bulk_step(n_cu, tab, ent, ecap) && L.rem == 0) {
+            // (only the contended drain comes here with every kernel placed)
+            if ((!CONT || L.pos < n) && L.bulk_step(n_cu, tab, ent, ecap) && L.rem == 0) {
                 L.pos++;
                 if (L.pos < n) {
                     // the next kernel may still place blocks at this cycle
