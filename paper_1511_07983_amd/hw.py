@@ -85,7 +85,7 @@ def simulate(model, kernels, orders) -> np.ndarray:
 
 
 def validate_set(model, kernels, *, n_random: int, seed: int, target_ms: float = 100.0, reps: int = 2,
-                 probe_scale: int = 4096):
+                 probe_scale: int = 4096, mem_blocks=()):
     hk = hardware_kernels(kernels)
     n = len(hk)
     rng = np.random.default_rng(seed)
@@ -96,8 +96,14 @@ def validate_set(model, kernels, *, n_random: int, seed: int, target_ms: float =
     scale = max(256, int(round(probe_scale * probe / target_ms)))
     measured = ko_hw_time_orders(kernels, orders, scale, reps)
     simulated = simulate(model, hk, orders)
+    # the same orders under the memory-contention mode (Section 4's balance of
+    # instructions and memory accesses across co-resident blocks), one B each
+    base = model if isinstance(model, dict) else model.as_dict()
+    contended = {int(b): simulate(dict(base, mem_blocks=int(b)), hk, orders) for b in mem_blocks}
     return {"orders": orders.tolist(), "scale": scale, "measured_ms": measured.tolist(),
             "simulated_cycles": simulated.tolist(), "spearman": spearman(simulated, measured),
+            "spearman_contended": {b: spearman(c, measured) for b, c in contended.items()},
+            "contended_cycles": {b: c.tolist() for b, c in contended.items()},
             "heuristic_rank_measured": int((measured < measured[0]).sum()),
             "heuristic_rank_simulated": int((simulated < simulated[0]).sum())}
 
@@ -113,7 +119,10 @@ def main(argv=None):
     ap.add_argument("--random-orders", type=int, default=7)
     ap.add_argument("--target-ms", type=float, default=100.0)
     ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--mem-blocks", default="",
+                    help="comma-separated mem_blocks values: also rank the orders under memory contention")
     a = ap.parse_args(argv)
+    mem_blocks = [int(b) for b in a.mem_blocks.split(",") if b.strip()]
     queues = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
     import torch
     import synth
@@ -123,7 +132,7 @@ def main(argv=None):
     for s in range(a.sets):
         ks = synth.draw_set(a.workload, s)
         row = validate_set(w.model, ks, n_random=a.random_orders, seed=1000 + s, target_ms=a.target_ms,
-                           reps=a.reps)
+                           reps=a.reps, mem_blocks=mem_blocks)
         row["set"] = s
         row["hw_queues"] = queues
         m = np.array(row["measured_ms"])
@@ -131,15 +140,16 @@ def main(argv=None):
         row["spread_measured"] = float(m.max() / m.min() - 1.0)
         row["spread_simulated"] = float(c.max() / c.min() - 1.0)
         rows.append(row)
-        print(json.dumps({k: row[k] for k in ("set", "hw_queues", "scale", "spearman", "spread_measured",
-                                              "spread_simulated", "heuristic_rank_measured",
+        print(json.dumps({k: row[k] for k in ("set", "hw_queues", "scale", "spearman", "spearman_contended",
+                                              "spread_measured", "spread_simulated", "heuristic_rank_measured",
                                               "heuristic_rank_simulated", "measured_ms", "simulated_cycles")}),
               flush=True)
     rho = [r["spearman"] for r in rows]
     print(json.dumps({"calibration": True, "hw_queues": queues, **calibrate(rows)}), flush=True)
+    contended = {b: float(np.nanmean([r["spearman_contended"][b] for r in rows])) for b in mem_blocks}
     print(json.dumps({"summary": True, "hw_queues": queues, "sets": a.sets, "orders_per_set": a.random_orders + 1,
                       "spearman_mean": float(np.nanmean(rho)), "spearman_min": float(np.nanmin(rho)),
-                      "spearman_max": float(np.nanmax(rho))}), flush=True)
+                      "spearman_max": float(np.nanmax(rho)), "spearman_mean_contended": contended}), flush=True)
     return 0
 
 
