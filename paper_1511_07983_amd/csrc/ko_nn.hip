@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -1078,72 +1079,146 @@ __global__ void split_table_kernel(const uint16_t *wb, const float *master, cons
     split[(int64_t)kHid * KP + idx] = lo;
 }
 
-// One product of the split scoring kernel for a wave: acc[8][4] (128 rows x
-// its 64 columns [64 w, 64 w + 64)) += A B^T over K = 32 KS, A from the LDS
-// tile (rows 0..127, k-contiguous), B's 16-byte fragments (column c at
-// Bm + c ldb, k-contiguous; with TWO a second matrix Bm2 at the same offsets,
-// accumulated after the first in each k step) read from memory one k step
-// ahead of the MFMAs that use them.
-template <int KS, bool TWO, int P>
-__device__ __forceinline__ void split_product(f32x4 (&acc)[8][4], uint16_t (*At)[P], const uint16_t *Bm,
-                                              const uint16_t *Bm2, int ldb, int wave, int lane)
-{
-    const int kk = (lane >> 4) * 8;
-    const uint16_t *bp = Bm + (size_t)(wave * 64 + (lane & 15)) * ldb + kk;
-    const uint16_t *bp2 = TWO ? Bm2 + (size_t)(wave * 64 + (lane & 15)) * ldb + kk : nullptr;
+// One product of the split scoring kernel for a wave, computed transposed:
+// acc[i][j] (hidden units [64 w + 16 j, +16) x the tile's orders [16 i, +16))
+// = init[j] + B A^T over K = 32 KS, where B (the weights or the split table,
+// hidden unit h at row h, k-contiguous; with TWO a second matrix at the same
+// offsets, accumulated after the first in each k step) is the MFMA's first
+// operand and A (the tile's rows, k-contiguous in LDS) its second.  A lane so
+// holds 4 consecutive hidden units of one order.  The first k step takes
+// init[j] (the bias of the lane's 4 units, or zero) as its addend, so nothing
+// is cleared or added afterwards.
+//
+// Operands arrive ahead of use: B's fragments one k step ahead, through two
+// fragment sets in turn (the caller loads step 0's into f0 before the barrier
+// and epilogue that precede the product, so its latency hides behind them);
+// A's fragments (LDS) two row blocks ahead, the next step's first two read
+// during the current step's last blocks.  The loads are fenced off from the
+// scheduler (sched_barrier), which would otherwise sink them towards their
+// first use and expose their latency.
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+template <bool TWO>
+struct SplitFrag {
     bf16x8 b[4], b2[4];
+};
+
+// the lane's fragment pointers of B (and B2) at k step 0: row 64 w + (lane & 15),
+// column 8 (lane >> 4); the 4 fragments of a k step are 16 rows apart
+struct SplitB {
+    const uint16_t *p, *p2;
+    int ld;
+    template <bool TWO>
+    __device__ __forceinline__ void load(SplitFrag<TWO> &f, int ks) const
+    {
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-        b[j] = *reinterpret_cast<const bf16x8 *>(bp + (size_t)j * 16 * ldb);
-        if (TWO)
-            b2[j] = *reinterpret_cast<const bf16x8 *>(bp2 + (size_t)j * 16 * ldb);
-    }
-#pragma unroll 1
-    for (int ks = 0; ks < KS; ks++) {
-        bf16x8 nb[4], nb2[4];
-        if (ks + 1 < KS) {
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                nb[j] = *reinterpret_cast<const bf16x8 *>(bp + (size_t)j * 16 * ldb + (ks + 1) * kKStep);
-                if (TWO)
-                    nb2[j] = *reinterpret_cast<const bf16x8 *>(bp2 + (size_t)j * 16 * ldb + (ks + 1) * kKStep);
-            }
+        for (int j = 0; j < 4; j++) {
+            f.b[j] = *reinterpret_cast<const bf16x8 *>(p + (size_t)j * 16 * ld + ks * kKStep);
+            if (TWO)
+                f.b2[j] = *reinterpret_cast<const bf16x8 *>(p2 + (size_t)j * 16 * ld + ks * kKStep);
         }
+    }
+};
+
+__device__ __forceinline__ SplitB split_b(const uint16_t *Bm, const uint16_t *Bm2, int ld, int wave, int lane)
+{
+    const size_t off = (size_t)(wave * 64 + (lane & 15)) * ld + (lane >> 4) * 8;
+    return SplitB{Bm + off, Bm2 ? Bm2 + off : nullptr, ld};
+}
+
+template <int KS, bool TWO, int P>
+__device__ __forceinline__ void split_product(f32x4 (&acc)[8][4], uint16_t (*At)[P], const SplitB &bm,
+                                              SplitFrag<TWO> &f0, const f32x4 (&init)[4], int lane)
+{
+    static_assert(KS >= 1, "at least one k step");
+    // the lane's A fragment of row block i at k step ks
+    const uint16_t *ap = &At[lane & 15][(lane >> 4) * 8];
+    auto afrag = [&](int ks, int i) {
+        return *reinterpret_cast<const bf16x8 *>(ap + (size_t)i * 16 * P + ks * kKStep);
+    };
+    // one k step with fragment set f; c0, c1: its blocks 0 and 1, replaced by
+    // the next step's (when there is one)
+    auto step = [&](const SplitFrag<TWO> &f, int ks, bool first, bool next, bf16x8 &c0, bf16x8 &c1) {
+        bf16x8 a[8];
+        a[0] = c0;
+        a[1] = c1;
 #pragma unroll
         for (int i = 0; i < 8; i++) {
-            const bf16x8 af = *reinterpret_cast<const bf16x8 *>(&At[i * 16 + (lane & 15)][ks * kKStep + kk]);
+            if (i + 2 < 8)
+                a[i + 2] = afrag(ks, i + 2);
+            else if (next) {
+                if (i == 6)
+                    c0 = afrag(ks + 1, 0);
+                else
+                    c1 = afrag(ks + 1, 1);
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.b[j], a[i], first ? init[j] : acc[i][j], 0, 0, 0);
                 if (TWO)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b2[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.b2[j], a[i], acc[i][j], 0, 0, 0);
             }
         }
+    };
+    bf16x8 c0 = afrag(0, 0), c1 = afrag(0, 1);
+    SplitFrag<TWO> f1;
+    if (KS > 1)
+        bm.load(f1, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    step(f0, 0, true, KS > 1, c0, c1);
+#pragma unroll 1
+    for (int ks = 1; ks < KS; ks += 2) {
+        if (ks + 1 < KS)
+            bm.load(f0, ks + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        step(f1, ks, false, ks + 1 < KS, c0, c1);
         if (ks + 1 < KS) {
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                b[j] = nb[j];
-                if (TWO)
-                    b2[j] = nb2[j];
-            }
+            if (ks + 2 < KS)
+                bm.load(f1, ks + 2);
+            __builtin_amdgcn_sched_barrier(0);
+            step(f0, ks + 1, false, ks + 2 < KS, c0, c1);
         }
     }
 }
 
-// Scoring of a tile of 128 orders per workgroup (4 waves; wave w owns
-// columns [64 w, 64 w + 64) of every product, for all 128 rows, so each
+// BF16 of acc's 4 values (round to nearest even), with relu applied to the
+// rounded values (a BF16 value below zero, -0 included, has its sign bit set:
+// as a 16-bit integer it is negative, and the integer maximum with 0 gives
+// +0; rounding and relu commute for every number).
+template <bool RELU>
+__device__ __forceinline__ uint2 bf16x4_of(const f32x4 &a)
+{
+    uint2 u{pack_bf16x2(a[0], a[1]), pack_bf16x2(a[2], a[3])};
+    if (RELU) {
+        s16x2 x, y;
+        const s16x2 z = {0, 0};
+        __builtin_memcpy(&x, &u.x, 4);
+        __builtin_memcpy(&y, &u.y, 4);
+        x = __builtin_elementwise_max(x, z);
+        y = __builtin_elementwise_max(y, z);
+        __builtin_memcpy(&u.x, &x, 4);
+        __builtin_memcpy(&u.y, &y, 4);
+    }
+    return u;
+}
+
+// Scoring of a tile of 128 orders per workgroup (4 waves; wave w owns hidden
+// units [64 w, 64 w + 64) of every product, for all 128 orders, so each
 // fragment of the table or of W feeds 8 MFMAs):
 //   1. the one-hot tile in LDS (row r: a 1 at 17 i + pos[r][i]);
 //   2. S = onehot (hi + lo), the hi then the lo product of each k step into
 //      one float32 accumulator; S as BF16 over the tile once every wave has
-//      read the one-hot rows;
-//   3. A2 = relu(S W2^T + b2) as BF16 over the tile, likewise;
-//   4. A3 = relu(A2 W3^T + b3) rounded to BF16 stays in registers: each
-//      lane multiplies its A3 values by w4, the 16 lanes of a row add their
-//      columns (xor shuffles), and the 4 waves' column sums of a row are
-//      added in wave order with b4: y.
+//      read the one-hot rows (8 bytes per lane and tile: an order's 4
+//      consecutive hidden units);
+//   3. A2 = relu(b2 + S W2^T) as BF16 over the tile, likewise;
+//   4. A3 = relu(b3 + A2 W3^T) rounded to BF16 stays in registers: each lane
+//      multiplies its 16 A3 values of an order by w4, the 4 lanes that hold
+//      the order's other units of this wave add theirs (two xor shuffles),
+//      and the 4 waves' sums of a row are added in wave order with b4: y.
 // Every sum has a fixed order, so y does not depend on scheduling.
 constexpr int kSpRows = 128;
+static_assert(kB2 % 4 == 0 && kB3 % 4 == 0 && kW4 % 4 == 0, "16-byte bias and 8-byte w4 loads");
 
 template <int N>
 __global__ __launch_bounds__(256, 2) void score_split_kernel(const uint16_t *wb, const float *master,
@@ -1160,18 +1235,31 @@ __global__ __launch_bounds__(256, 2) void score_split_kernel(const uint16_t *wb,
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t b0 = (int64_t)blockIdx.x * kSpRows;
     const int rows = (int)min((int64_t)kSpRows, (int64_t)B - b0);
+    // the table's first fragments and the tile's positions (every load
+    // issued before any is waited for) arrive while the tile is cleared
+    const SplitB tb = split_b(split, split + (size_t)kHid * KP, KP, wave, lane);
+    SplitFrag<true> tf;
+    tb.load(tf, 0);
+    constexpr int kPosPer = (kSpRows * N + 255) / 256;
+    int pv[kPosPer];
+#pragma unroll
+    for (int q = 0; q < kPosPer; q++) {
+        const int idx = tid + q * 256;
+        pv[q] = idx < rows * N ? pos[b0 * N + idx] : 0;
+    }
 
     for (int idx = tid; idx < kSpRows * (KP / 8); idx += 256) {
         const int r = idx / (KP / 8), c = (idx % (KP / 8)) * 8;
         *reinterpret_cast<uint4 *>(&At[r][c]) = make_uint4(0u, 0u, 0u, 0u);
     }
-    __syncthreads();
     if (tid < kSpRows)
         bad[tid] = 0;
-    for (int idx = tid; idx < kSpRows * N; idx += 256) {
-        const int r = idx / N, i = idx % N;
-        if (r < rows) {
-            const int p = pos[(b0 + r) * N + i];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPosPer; q++) {
+        const int idx = tid + q * 256;
+        if (idx < rows * N) {
+            const int r = idx / N, i = idx % N, p = pv[q];
             if (p < N || p >= KO_NN_UNPLACED)
                 At[r][i * (N + 1) + (p < N ? p : N)] = 0x3F80;   // BF16 1.0
             else
@@ -1181,78 +1269,71 @@ __global__ __launch_bounds__(256, 2) void score_split_kernel(const uint16_t *wb,
     __syncthreads();
 
     f32x4 acc[8][4];
-    auto clear = [&]() {
+    // the tile row (order) of acc[i][.] and the first of the 4 hidden units of acc[.][j]
+    const int rl = lane & 15;
+    auto unit_of = [&](int j) { return wave * 64 + j * 16 + (lane >> 4) * 4; };
+    auto bias_of = [&](const float *b, f32x4 (&init)[4]) {
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            init[j] = *reinterpret_cast<const f32x4 *>(b + unit_of(j));
+    };
+    // BF16 of acc (relu for RELU) over the tile
+    auto store_tile = [&](auto relu) {
 #pragma unroll
         for (int i = 0; i < 8; i++)
 #pragma unroll
             for (int j = 0; j < 4; j++)
-                acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    };
-    // the tile row and column of acc[i][j][e]
-    auto row_of = [&](int i, int e) { return i * 16 + (lane >> 4) * 4 + e; };
-    auto col_of = [&](int j) { return wave * 64 + j * 16 + (lane & 15); };
-    // BF16 of relu(acc + bias[col]) (bias null: of acc) over the tile
-    auto store_tile = [&](const float *bias) {
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int col = col_of(j);
-            const float bc = bias ? bias[col] : 0.f;
-#pragma unroll
-            for (int i = 0; i < 8; i++)
-#pragma unroll
-                for (int e = 0; e < 4; e += 2) {
-                    const float v0 = bias ? fmaxf(acc[i][j][e] + bc, 0.f) : acc[i][j][e];
-                    const float v1 = bias ? fmaxf(acc[i][j][e + 1] + bc, 0.f) : acc[i][j][e + 1];
-                    const uint32_t h = pack_bf16x2(v0, v1);
-                    At[row_of(i, e)][col] = (uint16_t)h;
-                    At[row_of(i, e) + 1][col] = (uint16_t)(h >> 16);
-                }
-        }
+                *reinterpret_cast<uint2 *>(&At[i * 16 + rl][unit_of(j)]) = bf16x4_of<decltype(relu)::value>(acc[i][j]);
     };
 
-    clear();
-    split_product<KP / kKStep, true>(acc, At, split, split + (size_t)kHid * KP, KP, wave, lane);
+    f32x4 init[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+        init[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    split_product<KP / kKStep, true>(acc, At, tb, tf, init, lane);
+    const SplitB w2 = split_b(wb + kW2, nullptr, kHid, wave, lane);
+    SplitFrag<false> wf;
+    w2.load(wf, 0);
+    bias_of(master + kB2, init);
     __syncthreads();   // every wave has read the one-hot tile
-    store_tile(nullptr);
+    store_tile(std::false_type{});
     __syncthreads();
-    clear();
-    split_product<kHid / kKStep, false>(acc, At, wb + kW2, nullptr, kHid, wave, lane);
+    split_product<kHid / kKStep, false>(acc, At, w2, wf, init, lane);
+    const SplitB w3 = split_b(wb + kW3, nullptr, kHid, wave, lane);
+    w3.load(wf, 0);
+    bias_of(master + kB3, init);
     __syncthreads();   // every wave has read S
-    store_tile(master + kB2);
+    store_tile(std::true_type{});
     __syncthreads();
-    clear();
-    split_product<kHid / kKStep, false>(acc, At, wb + kW3, nullptr, kHid, wave, lane);
+    split_product<kHid / kKStep, false>(acc, At, w3, wf, init, lane);
 
-    // output layer from the registers: part[i][e] = sum over this lane's 4 columns
-    float w4[4], b3[4];
+    // output layer from the registers: w4 of the lane's 16 hidden units
+    float w4[4][4];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
-        w4[j] = from_bf16(wb[kW4 + col_of(j)]);
-        b3[j] = master[kB3 + col_of(j)];
+        const uint2 h = *reinterpret_cast<const uint2 *>(wb + kW4 + unit_of(j));
+        w4[j][0] = __uint_as_float(h.x << 16);
+        w4[j][1] = __uint_as_float(h.x & 0xFFFF0000u);
+        w4[j][2] = __uint_as_float(h.y << 16);
+        w4[j][3] = __uint_as_float(h.y & 0xFFFF0000u);
     }
 #pragma unroll
-    for (int i = 0; i < 8; i++)
+    for (int i = 0; i < 8; i++) {
+        float part = 0.f;
 #pragma unroll
-        for (int e = 0; e < 4; e += 2) {
-            // rows e and e + 1: A3 rounded to BF16 two at a time
-            float part0 = 0.f, part1 = 0.f;
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const uint32_t h = pack_bf16x2(fmaxf(acc[i][j][e] + b3[j], 0.f), fmaxf(acc[i][j][e + 1] + b3[j], 0.f));
-                part0 += __uint_as_float(h << 16) * w4[j];
-                part1 += __uint_as_float(h & 0xFFFF0000u) * w4[j];
-            }
-            // the 16 lanes of a row group hold its 64 columns of this wave
-#pragma unroll
-            for (int o = 1; o < 16; o <<= 1) {
-                part0 += __shfl_xor(part0, o);
-                part1 += __shfl_xor(part1, o);
-            }
-            if ((lane & 15) == 0) {
-                yp[wave][row_of(i, e)] = part0;
-                yp[wave][row_of(i, e) + 1] = part1;
-            }
+        for (int j = 0; j < 4; j++) {
+            const uint2 h = bf16x4_of<true>(acc[i][j]);
+            part += __uint_as_float(h.x << 16) * w4[j][0];
+            part += __uint_as_float(h.x & 0xFFFF0000u) * w4[j][1];
+            part += __uint_as_float(h.y << 16) * w4[j][2];
+            part += __uint_as_float(h.y & 0xFFFF0000u) * w4[j][3];
         }
+        // the 4 lanes rl, rl + 16, rl + 32, rl + 48 hold the row's 64 units of this wave
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (lane < 16)
+            yp[wave][i * 16 + rl] = part;
+    }
     __syncthreads();
     if (tid < rows) {
         const float v = bad[tid] ? __builtin_nanf("")

@@ -347,7 +347,11 @@ def test_split_score_matches_its_definition_and_oracle(B, n):
 
 def test_split_score_flags_positions_outside_the_set():
     """A position in n..15 is no launch position of an n-kernel order: that
-    row's y is NaN and the other rows are as without it."""
+    row's y is NaN and the other rows are as without it.  The tile's thread t
+    reads position bytes t, t + 256, ... (row-major, n per row) and thread r
+    clears row r's flag: rows 11 and 21 of the first tile have their bad
+    position read by a thread of another wave than the one that clears the
+    flag (bytes 68 and 130 at n = 6)."""
     B, n = 200, 6
     rng, flat, feat, pos, X = make_case(7, B, n)
     model = nn.Surrogate(flat)
@@ -356,10 +360,13 @@ def test_split_score_flags_positions_outside_the_set():
     y0 = model.score_split(split, torch.from_numpy(pos).to("cuda:0")).cpu().numpy()
     bad = pos.copy()
     bad[3, 2] = 9
+    bad[11, 2] = 7
+    bad[21, 4] = 12
     bad[150, 0] = 15
+    rows = [3, 11, 21, 150]
     y1 = model.score_split(split, torch.from_numpy(bad).to("cuda:0")).cpu().numpy()
-    assert np.isnan(y1[3]) and np.isnan(y1[150])
-    keep = np.setdiff1d(np.arange(B), [3, 150])
+    assert np.all(np.isnan(y1[rows])), y1[rows]
+    keep = np.setdiff1d(np.arange(B), rows)
     assert np.isfinite(y0).all() and np.array_equal(y0[keep], y1[keep])
 
 
