@@ -212,21 +212,28 @@ int ko_nn_score(const void *state_dev, const float *feat_dev, const uint8_t *pos
  * representation of T and the order of the float32 additions (S, like every
  * path's, is then rounded to BF16).
  *
- * ko_nn_split_table_bytes — bytes of the split table of a set of n kernels:
- * 2 x 256 x KP BF16 values, KP = n (n + 1) rounded up to a multiple of 32.
+ * ko_nn_split_table_bytes — bytes of the scoring operand pack of a set of n
+ * kernels: (2 x 256 x KP + 2 x 256 x 256) BF16 values, KP = n (n + 1)
+ * rounded up to a multiple of 32.
  *
- * ko_nn_split_table — the split table of one set (features feat[n][8],
- * float32, device): split[q][j][k] (BF16, device, 16-byte aligned; q = 0
- * high and 1 low part, hidden unit j, k = (n + 1) i + slot for kernel i,
- * zero from n (n + 1) to KP), from the same first-layer values as
- * ko_nn_layer1_table.  1 <= n <= 16.  Errors: KO_EINVAL. */
+ * ko_nn_split_table — the scoring operand pack of one set (features
+ * feat[n][8], float32, device) into split (device, 16-byte aligned, owned by
+ * the caller): four BF16 matrices one after the other, the split table's
+ * high part hi[j][k] and low part lo[j][k] ([256][KP]: hidden unit j, k =
+ * (n + 1) i + slot for kernel i, zero from n (n + 1) to KP; from the same
+ * first-layer values as ko_nn_layer1_table), then the BF16 copies of W2 and
+ * W3 ([256][256]).  Each matrix M[256][32 KS] is stored in MFMA fragment
+ * order: element (h, k) at ((h / 16) KS + k / 32) 512 + (16 ((k % 32) / 8) +
+ * h % 16) 8 + k % 8, so the 512 values of one 16 x 32 operand fragment are
+ * contiguous.  The pack holds a copy of the weights: after they change, make
+ * it again.  1 <= n <= 16.  Errors: KO_EINVAL. */
 size_t ko_nn_split_table_bytes(int32_t n);
 int ko_nn_split_table(const void *state_dev, const float *feat_dev, int32_t n, uint16_t *split_dev,
                       void *hip_stream);
 
 /* ko_nn_score_split — y[B] (float32, device) for B orders of one set given as
  * positions pos[B][n] (uint8, device: 0..n-1, or 16 and above = unplaced),
- * from the set's split table (ko_nn_split_table, made with the current
+ * from the set's operand pack (ko_nn_split_table, made with the current
  * weights).  A position in n..15 is no launch position of an n-kernel order:
  * that order's y is NaN.  One kernel per 128-order tile: the one-hot tile in
  * LDS, the pooling product, both 256x256 layers and the output layer, nothing

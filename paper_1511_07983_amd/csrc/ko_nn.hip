@@ -1053,18 +1053,46 @@ constexpr int kSplitK(int n) { return (n * (n + 1) + kKStep - 1) / kKStep * kKSt
 // and then S and A2 (256 columns): 148 dwords
 constexpr int kOhPitch = kSplitK(KO_NN_MAX_TOKENS) + 8;
 
-// split[q][j][k] (BF16; q = 0 high part, 1 low part; hidden unit j; k =
-// (n + 1) i + slot for kernel i, zero from n (n + 1) up to KP = kSplitK(n)),
-// with T computed exactly as table_kernel does for the slot's position.
-// One workgroup row per hidden unit j (blockIdx.y), threads along k.
-__global__ void split_table_kernel(const uint16_t *wb, const float *master, const float *feat, int32_t n,
-                                   int32_t KP, uint16_t *split)
+// Fragment order of a [256][32 KS] BF16 matrix (hidden unit h, k): the 512
+// values of the MFMA operand fragment of unit block h / 16 at k step k / 32
+// (64 lanes x 8 values: lane 16 (k % 32 / 8) + h % 16 holds k % 8 = 0..7) are
+// contiguous, the blocks in (unit block, k step) order.
+constexpr int kFragElems = 512;
+
+constexpr int64_t frag_index(int h, int k, int KS)
 {
-    const int j = blockIdx.y;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= KP)
-        return;
-    const int64_t idx = (int64_t)j * KP + k;
+    return ((int64_t)(h >> 4) * KS + (k >> 5)) * kFragElems + ((((k & 31) >> 3) << 4) | (h & 15)) * 8 + (k & 7);
+}
+
+// the kernels below write fragment (unit block rb, k step ks) with thread t
+// holding unit 16 rb + (t / 8) % 16 and k = 32 ks + 8 (t / 128) + t % 8; the
+// scoring kernel's lane l reads values [8 l, 8 l + 8) of a fragment as the
+// MFMA operand of unit 16 rb + l % 16, k = 32 ks + 8 (l / 16) + 0..7
+constexpr bool frag_order_consistent()
+{
+    for (int t = 0; t < kFragElems; t++) {
+        const int lane = t >> 3;
+        if (frag_index(16 + (lane & 15), 2 * kKStep + (lane >> 4) * 8 + (t & 7), 5) != (1 * 5 + 2) * kFragElems + t)
+            return false;
+    }
+    return true;
+}
+static_assert(frag_order_consistent(), "fragment order and the threads' mapping agree");
+
+// The scoring operand pack of one set, BF16 in fragment order: the split
+// table's high part [256][KP] (hidden unit j, k = (n + 1) i + slot for kernel
+// i, zero from n (n + 1) up to KP = kSplitK(n)), its low part, then W2 and W3
+// [256][256] (the BF16 copies).  The table's T is computed exactly as
+// table_kernel does for the slot's position.  One workgroup of 512 threads
+// per fragment, grid (KP / 32, 16): thread t = 8 lane + e writes value e of
+// the fragment's lane, so the writes are contiguous.
+__global__ __launch_bounds__(512) void split_table_kernel(const uint16_t *wb, const float *master, const float *feat,
+                                                          int32_t n, int32_t KP, uint16_t *split)
+{
+    const int ks = blockIdx.x, rb = blockIdx.y, t = threadIdx.x;
+    const int lane = t >> 3;
+    const int j = rb * 16 + (lane & 15), k = ks * kKStep + (lane >> 4) * 8 + (t & 7);
+    const int64_t idx = ((int64_t)rb * (KP / kKStep) + ks) * kFragElems + t;
     uint16_t hi = 0, lo = 0;
     if (k < n * (n + 1)) {
         const int i = k / (n + 1), slot = k % (n + 1);
@@ -1079,23 +1107,34 @@ __global__ void split_table_kernel(const uint16_t *wb, const float *master, cons
     split[(int64_t)kHid * KP + idx] = lo;
 }
 
+// W2 (blockIdx.z = 0) and W3 (1) in fragment order into out[2][256 x 256];
+// grid (8, 16, 2) of 512 threads, one fragment each
+__global__ __launch_bounds__(512) void frag_weights_kernel(const uint16_t *wb, uint16_t *out)
+{
+    const int ks = blockIdx.x, rb = blockIdx.y, m = blockIdx.z, t = threadIdx.x;
+    const int lane = t >> 3;
+    const int h = rb * 16 + (lane & 15), k = ks * kKStep + (lane >> 4) * 8 + (t & 7);
+    const size_t src = (m == 0 ? kW2 : kW3) + (size_t)h * kHid + k;
+    out[(size_t)m * kHid * kHid + ((size_t)rb * (kHid / kKStep) + ks) * kFragElems + t] = wb[src];
+}
+
 // One product of the split scoring kernel for a wave, computed transposed:
 // acc[i][j] (hidden units [64 w + 16 j, +16) x the tile's orders [16 i, +16))
-// = init[j] + B A^T over K = 32 KS, where B (the weights or the split table,
-// hidden unit h at row h, k-contiguous; with TWO a second matrix at the same
-// offsets, accumulated after the first in each k step) is the MFMA's first
-// operand and A (the tile's rows, k-contiguous in LDS) its second.  A lane so
-// holds 4 consecutive hidden units of one order.  The first k step takes
-// init[j] (the bias of the lane's 4 units, or zero) as its addend, so nothing
-// is cleared or added afterwards.
+// = init[j] + B A^T over K = 32 KS, where B (the weights or the split table in
+// fragment order; with TWO a second matrix of the same shape, accumulated
+// after the first in each k step) is the MFMA's first operand and A (the
+// tile's rows, k-contiguous in LDS) its second.  A lane so holds 4
+// consecutive hidden units of one order.  The first k step takes init[j]
+// (the bias of the lane's 4 units, or zero) as its addend, so nothing is
+// cleared or added afterwards.
 //
-// Operands arrive ahead of use: B's fragments one k step ahead, through two
-// fragment sets in turn (the caller loads step 0's into f0 before the barrier
-// and epilogue that precede the product, so its latency hides behind them);
-// A's fragments (LDS) two row blocks ahead, the next step's first two read
-// during the current step's last blocks.  The loads are fenced off from the
-// scheduler (sched_barrier), which would otherwise sink them towards their
-// first use and expose their latency.
+// B's fragments come from memory D k steps ahead of the MFMAs that use them,
+// through D + 1 fragment sets in turn; the caller loads the first D
+// (split_prefetch) before the barrier and epilogue that precede the product,
+// so their latency hides behind them.  Each prefetch is fenced off from the
+// scheduler (sched_barrier), which would otherwise sink the loads towards
+// their first use; the k loop is unrolled in full, so every fragment set is
+// a fixed set of registers.
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 
 template <bool TWO>
@@ -1103,81 +1142,61 @@ struct SplitFrag {
     bf16x8 b[4], b2[4];
 };
 
-// the lane's fragment pointers of B (and B2) at k step 0: row 64 w + (lane & 15),
-// column 8 (lane >> 4); the 4 fragments of a k step are 16 rows apart
+// The lane's fragment pointers of B (and B2) in fragment order (frag_index):
+// the fragments of unit block 4 w + j at k step ks are 1 KB contiguous, lane l
+// reading bytes [16 l, 16 l + 16), so a fragment load touches 8 whole cache
+// lines instead of 16 half lines.
 struct SplitB {
     const uint16_t *p, *p2;
-    int ld;
+    int ks_total;
     template <bool TWO>
     __device__ __forceinline__ void load(SplitFrag<TWO> &f, int ks) const
     {
 #pragma unroll
         for (int j = 0; j < 4; j++) {
-            f.b[j] = *reinterpret_cast<const bf16x8 *>(p + (size_t)j * 16 * ld + ks * kKStep);
+            f.b[j] = *reinterpret_cast<const bf16x8 *>(p + (size_t)(j * ks_total + ks) * kFragElems);
             if (TWO)
-                f.b2[j] = *reinterpret_cast<const bf16x8 *>(p2 + (size_t)j * 16 * ld + ks * kKStep);
+                f.b2[j] = *reinterpret_cast<const bf16x8 *>(p2 + (size_t)(j * ks_total + ks) * kFragElems);
         }
     }
 };
 
-__device__ __forceinline__ SplitB split_b(const uint16_t *Bm, const uint16_t *Bm2, int ld, int wave, int lane)
+__device__ __forceinline__ SplitB split_b(const uint16_t *Bm, const uint16_t *Bm2, int ks_total, int wave, int lane)
 {
-    const size_t off = (size_t)(wave * 64 + (lane & 15)) * ld + (lane >> 4) * 8;
-    return SplitB{Bm + off, Bm2 ? Bm2 + off : nullptr, ld};
+    const size_t off = (size_t)(wave * 4) * ks_total * kFragElems + lane * 8;
+    return SplitB{Bm + off, Bm2 ? Bm2 + off : nullptr, ks_total};
 }
 
-template <int KS, bool TWO, int P>
-__device__ __forceinline__ void split_product(f32x4 (&acc)[8][4], uint16_t (*At)[P], const SplitB &bm,
-                                              SplitFrag<TWO> &f0, const f32x4 (&init)[4], int lane)
+// k steps 0 .. D-1 of B into f[0 .. D-1]
+template <int KS, int D, bool TWO>
+__device__ __forceinline__ void split_prefetch(const SplitB &bm, SplitFrag<TWO> (&f)[D + 1])
 {
-    static_assert(KS >= 1, "at least one k step");
-    // the lane's A fragment of row block i at k step ks
-    const uint16_t *ap = &At[lane & 15][(lane >> 4) * 8];
-    auto afrag = [&](int ks, int i) {
-        return *reinterpret_cast<const bf16x8 *>(ap + (size_t)i * 16 * P + ks * kKStep);
-    };
-    // one k step with fragment set f; c0, c1: its blocks 0 and 1, replaced by
-    // the next step's (when there is one)
-    auto step = [&](const SplitFrag<TWO> &f, int ks, bool first, bool next, bf16x8 &c0, bf16x8 &c1) {
-        bf16x8 a[8];
-        a[0] = c0;
-        a[1] = c1;
+#pragma unroll
+    for (int s = 0; s < D && s < KS; s++)
+        bm.load(f[s], s);
+}
+
+template <int KS, int D, bool TWO, int P>
+__device__ __forceinline__ void split_product(f32x4 (&acc)[8][4], uint16_t (*At)[P], const SplitB &bm,
+                                              SplitFrag<TWO> (&f)[D + 1], const f32x4 (&init)[4], int lane)
+{
+    static_assert(KS >= 1 && D >= 1, "at least one k step, prefetched at least one ahead");
+    const int kk = (lane >> 4) * 8;
+#pragma clang loop unroll(full)
+    for (int ks = 0; ks < KS; ks++) {
+        if (ks + D < KS)
+            bm.load(f[(ks + D) % (D + 1)], ks + D);
+        __builtin_amdgcn_sched_barrier(0);
+        const SplitFrag<TWO> &g = f[ks % (D + 1)];
 #pragma unroll
         for (int i = 0; i < 8; i++) {
-            if (i + 2 < 8)
-                a[i + 2] = afrag(ks, i + 2);
-            else if (next) {
-                if (i == 6)
-                    c0 = afrag(ks + 1, 0);
-                else
-                    c1 = afrag(ks + 1, 1);
-            }
-            __builtin_amdgcn_sched_barrier(0);
+            const bf16x8 af = *reinterpret_cast<const bf16x8 *>(&At[i * 16 + (lane & 15)][ks * kKStep + kk]);
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.b[j], a[i], first ? init[j] : acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g.b[j], af, ks == 0 ? init[j] : acc[i][j], 0, 0, 0);
                 if (TWO)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.b2[j], a[i], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g.b2[j], af, acc[i][j], 0, 0, 0);
             }
-        }
-    };
-    bf16x8 c0 = afrag(0, 0), c1 = afrag(0, 1);
-    SplitFrag<TWO> f1;
-    if (KS > 1)
-        bm.load(f1, 1);
-    __builtin_amdgcn_sched_barrier(0);
-    step(f0, 0, true, KS > 1, c0, c1);
-#pragma unroll 1
-    for (int ks = 1; ks < KS; ks += 2) {
-        if (ks + 1 < KS)
-            bm.load(f0, ks + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        step(f1, ks, false, ks + 1 < KS, c0, c1);
-        if (ks + 1 < KS) {
-            if (ks + 2 < KS)
-                bm.load(f1, ks + 2);
-            __builtin_amdgcn_sched_barrier(0);
-            step(f0, ks + 1, false, ks + 2 < KS, c0, c1);
         }
     }
 }
@@ -1218,6 +1237,10 @@ __device__ __forceinline__ uint2 bf16x4_of(const f32x4 &a)
 //      and the 4 waves' sums of a row are added in wave order with b4: y.
 // Every sum has a fixed order, so y does not depend on scheduling.
 constexpr int kSpRows = 128;
+// prefetch distances (k steps) of the pooling product (fragment sets of 32
+// VGPRs, 64 MFMAs a step) and of the layer products (16 VGPRs, 32 MFMAs)
+constexpr int kPoolAhead = 1;
+constexpr int kLayerAhead = 2;
 static_assert(kB2 % 4 == 0 && kB3 % 4 == 0 && kW4 % 4 == 0, "16-byte bias and 8-byte w4 loads");
 
 template <int N>
@@ -1237,9 +1260,9 @@ __global__ __launch_bounds__(256, 2) void score_split_kernel(const uint16_t *wb,
     const int rows = (int)min((int64_t)kSpRows, (int64_t)B - b0);
     // the table's first fragments and the tile's positions (every load
     // issued before any is waited for) arrive while the tile is cleared
-    const SplitB tb = split_b(split, split + (size_t)kHid * KP, KP, wave, lane);
-    SplitFrag<true> tf;
-    tb.load(tf, 0);
+    const SplitB tb = split_b(split, split + (size_t)kHid * KP, KP / kKStep, wave, lane);
+    SplitFrag<true> tf[kPoolAhead + 1];
+    split_prefetch<KP / kKStep, kPoolAhead>(tb, tf);
     constexpr int kPosPer = (kSpRows * N + 255) / 256;
     int pv[kPosPer];
 #pragma unroll
@@ -1290,22 +1313,23 @@ __global__ __launch_bounds__(256, 2) void score_split_kernel(const uint16_t *wb,
 #pragma unroll
     for (int j = 0; j < 4; j++)
         init[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    split_product<KP / kKStep, true>(acc, At, tb, tf, init, lane);
-    const SplitB w2 = split_b(wb + kW2, nullptr, kHid, wave, lane);
-    SplitFrag<false> wf;
-    w2.load(wf, 0);
+    split_product<KP / kKStep, kPoolAhead, true>(acc, At, tb, tf, init, lane);
+    const uint16_t *wfrag = split + (size_t)2 * kHid * KP;   // W2 and W3 in fragment order
+    const SplitB w2 = split_b(wfrag, nullptr, kHid / kKStep, wave, lane);
+    SplitFrag<false> wf[kLayerAhead + 1];
+    split_prefetch<kHid / kKStep, kLayerAhead>(w2, wf);
     bias_of(master + kB2, init);
     __syncthreads();   // every wave has read the one-hot tile
     store_tile(std::false_type{});
     __syncthreads();
-    split_product<kHid / kKStep, false>(acc, At, w2, wf, init, lane);
-    const SplitB w3 = split_b(wb + kW3, nullptr, kHid, wave, lane);
-    w3.load(wf, 0);
+    split_product<kHid / kKStep, kLayerAhead, false>(acc, At, w2, wf, init, lane);
+    const SplitB w3 = split_b(wfrag + (size_t)kHid * kHid, nullptr, kHid / kKStep, wave, lane);
+    split_prefetch<kHid / kKStep, kLayerAhead>(w3, wf);
     bias_of(master + kB3, init);
     __syncthreads();   // every wave has read S
     store_tile(std::true_type{});
     __syncthreads();
-    split_product<kHid / kKStep, false>(acc, At, w3, wf, init, lane);
+    split_product<kHid / kKStep, kLayerAhead, false>(acc, At, w3, wf, init, lane);
 
     // output layer from the registers: w4 of the lane's 16 hidden units
     float w4[4][4];
@@ -2191,7 +2215,7 @@ size_t ko_nn_split_table_bytes(int32_t n)
 {
     if (n < 1 || n > KO_NN_MAX_TOKENS)
         return 0;
-    return (size_t)2 * kHid * kSplitK(n) * sizeof(uint16_t);
+    return ((size_t)2 * kHid * kSplitK(n) + (size_t)2 * kHid * kHid) * sizeof(uint16_t);
 }
 
 int ko_nn_split_table(const void *state_dev, const float *feat_dev, int32_t n, uint16_t *split_dev,
@@ -2205,8 +2229,11 @@ int ko_nn_split_table(const void *state_dev, const float *feat_dev, int32_t n, u
         return fail(KO_EINVAL, "the table must be 16-byte aligned");
     State s = state_of(const_cast<void *>(state_dev));
     const int32_t KP = kSplitK(n);
-    hipLaunchKernelGGL(split_table_kernel, dim3((unsigned)((KP + 255) / 256), kHid), dim3(256), 0, (hipStream_t)hip_stream,
-                       s.wb, s.master, feat_dev, n, KP, split_dev);
+    hipLaunchKernelGGL(split_table_kernel, dim3((unsigned)(KP / kKStep), kHid / 16), dim3(kFragElems), 0,
+                       (hipStream_t)hip_stream, s.wb, s.master, feat_dev, n, KP, split_dev);
+    NN_LAUNCHED();
+    hipLaunchKernelGGL(frag_weights_kernel, dim3(kHid / kKStep, kHid / 16, 2), dim3(kFragElems), 0,
+                       (hipStream_t)hip_stream, s.wb, split_dev + (size_t)2 * kHid * KP);
     NN_LAUNCHED();
     return KO_OK;
 }

@@ -307,11 +307,13 @@ class Surrogate:
         return y
 
     def split_table(self, feat, stream=None):
-        """feat: device float32 [n, 8] of one set -> its split layer-1 table
-        (device int16 [2, 256, KP], the BF16 high and low parts) for score_split."""
+        """feat: device float32 [n, 8] of one set -> its scoring operand pack
+        for score_split (device int16, flat: the split layer-1 table's BF16
+        high and low parts [256, KP] and the BF16 W2 and W3, each in MFMA
+        fragment order, as include/ko_nn.h describes)."""
         n = feat.shape[0]
-        kp = int(_lib.ko_nn_split_table_bytes(n)) // (2 * D_HID * 2)
-        split = self.torch.empty((2, D_HID, kp), dtype=self.torch.int16, device=self.device)
+        split = self.torch.empty(int(_lib.ko_nn_split_table_bytes(n)) // 2, dtype=self.torch.int16,
+                                 device=self.device)
         _check(_lib.ko_nn_split_table(self.state.data_ptr(), feat.data_ptr(), n, split.data_ptr(),
                                       _stream_handle(stream)))
         return split

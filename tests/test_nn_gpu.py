@@ -290,6 +290,17 @@ def _split_bf16(T):
     return hi, lo
 
 
+def _unfrag(raw, ks):
+    """A [256, 32 ks] BF16 matrix (uint16) from its MFMA fragment order:
+    element (h, k) at ((h // 16) ks + k // 32) 512 + (16 ((k % 32) // 8) +
+    h % 16) 8 + k % 8."""
+    return raw.reshape(16, ks, 4, 16, 8).transpose(0, 3, 1, 2, 4).reshape(16 * 16, ks * 32)
+
+
+def _bf16_bits_to_f64(u16):
+    return (u16.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
 def _slot_table(T, n):
     """Rows of the layer-1 table T [n, 17, 256] in slot order: kernel i's
     slots are its positions 0..n-1, then "unplaced" (16)."""
@@ -300,9 +311,9 @@ def _slot_table(T, n):
 @pytest.mark.parametrize("B,n", [(1, 1), (63, 5), (64, 16), (65, 12), (1000, 12), (4097, 9), (300, 16)])
 def test_split_score_matches_its_definition_and_oracle(B, n):
     """ko_nn_score_split (pooling as a one-hot MFMA product with the table in
-    BF16 high and low parts, n + 1 slots per kernel): the split table is
+    BF16 high and low parts, n + 1 slots per kernel): the operand pack holds
     exactly hi = bf16(T) and lo = bf16(T - hi) of the layer-1 table in slot
-    order.  y is compared with the oracle's layers applied to S = sum over
+    order and the BF16 W2 and W3, each in fragment order.  y is compared with the oracle's layers applied to S = sum over
     kernels of (hi + lo) (float64 sums), the path's definition: the device's S
     differs from it only by float32 accumulation, so a row differs only where
     that moves S across a BF16 rounding boundary (as for every path): at most
@@ -322,14 +333,21 @@ def test_split_score_matches_its_definition_and_oracle(B, n):
     p = torch.from_numpy(pos).to("cuda:0")
     T = model.layer1_table(f).cpu().numpy()                     # [n, 17, 256] float32
     split = model.split_table(f)
-    got = split.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
-    got = got.view(np.float32).astype(np.float64)              # [2, 256, KP]
     K1 = n * (n + 1)
-    assert got.shape[2] == -(-K1 // 32) * 32
+    KP = -(-K1 // 32) * 32
+    raw = split.cpu().numpy().view(np.uint16)
+    assert raw.size == 2 * 256 * KP + 2 * 256 * 256
+    got = np.stack([_bf16_bits_to_f64(_unfrag(raw[q * 256 * KP:(q + 1) * 256 * KP], KP // 32)) for q in (0, 1)])
     Ts = _slot_table(T, n)                                      # [K1, 256]
     hi, lo = _split_bf16(Ts.T)                                  # [256, K1]
     assert np.array_equal(got[0, :, :K1], hi) and np.array_equal(got[1, :, :K1], lo)
     assert not got[:, :, K1:].any()
+    # the pack's copies of W2 and W3: the BF16 weights, in fragment order
+    pw = mlp.unflatten(flat.astype(np.float64))
+    off = 2 * 256 * KP
+    for q, name in enumerate(("W2", "W3")):
+        w = _bf16_bits_to_f64(_unfrag(raw[off + q * 65536:off + (q + 1) * 65536], 8))
+        assert np.array_equal(w, mlp.bf16(pw[name])), name
     assert np.abs(hi + lo - Ts.T).max() <= 2.0 ** -17 * np.abs(Ts).max()
     y = model.score_split(split, p).cpu().numpy().astype(np.float64)
     slot = np.where(pos.astype(np.int64) < n, pos.astype(np.int64), n)
