@@ -1049,9 +1049,6 @@ bool launch_score(int n, unsigned grid, hipStream_t st, const uint16_t *wb, cons
 // the float32 additions; S is then rounded to BF16 as on every path.
 
 constexpr int kSplitK(int n) { return (n * (n + 1) + kKStep - 1) / kKStep * kKStep; }
-// LDS row pitch of the tile that holds the one-hot rows (up to 288 columns)
-// and then S and A2 (256 columns): 148 dwords
-constexpr int kOhPitch = kSplitK(KO_NN_MAX_TOKENS) + 8;
 
 // Fragment order of a [256][32 KS] BF16 matrix (hidden unit h, k): the 512
 // values of the MFMA operand fragment of unit block h / 16 at k step k / 32
@@ -1176,12 +1173,11 @@ __device__ __forceinline__ void split_prefetch(const SplitB &bm, SplitFrag<TWO> 
         bm.load(f[s], s);
 }
 
-template <int KS, int D, bool TWO, int P>
-__device__ __forceinline__ void split_product(f32x4 (&acc)[8][4], uint16_t (*At)[P], const SplitB &bm,
+template <int KS, int D, bool TWO>
+__device__ __forceinline__ void split_product(f32x4 (&acc)[8][4], const uint16_t *At, const SplitB &bm,
                                               SplitFrag<TWO> (&f)[D + 1], const f32x4 (&init)[4], int lane)
 {
     static_assert(KS >= 1 && D >= 1, "at least one k step, prefetched at least one ahead");
-    const int kk = (lane >> 4) * 8;
 #pragma clang loop unroll(full)
     for (int ks = 0; ks < KS; ks++) {
         if (ks + D < KS)
@@ -1190,7 +1186,7 @@ __device__ __forceinline__ void split_product(f32x4 (&acc)[8][4], uint16_t (*At)
         const SplitFrag<TWO> &g = f[ks % (D + 1)];
 #pragma unroll
         for (int i = 0; i < 8; i++) {
-            const bf16x8 af = *reinterpret_cast<const bf16x8 *>(&At[i * 16 + (lane & 15)][ks * kKStep + kk]);
+            const bf16x8 af = *reinterpret_cast<const bf16x8 *>(At + ((size_t)i * KS + ks) * kFragElems + lane * 8);
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g.b[j], af, ks == 0 ? init[j] : acc[i][j], 0, 0, 0);
@@ -1249,7 +1245,9 @@ __global__ __launch_bounds__(256, 2) void score_split_kernel(const uint16_t *wb,
                                                           float scale, int32_t accumulate, float *y)
 {
     constexpr int KP = kSplitK(N);
-    __shared__ __attribute__((aligned(16))) uint16_t At[kSpRows][kOhPitch];
+    // the tile [128 orders][K] in fragment order (frag_index, orders as the
+    // units): the one-hot rows (K = KP), then S and A2 (K = 256)
+    __shared__ __attribute__((aligned(16))) uint16_t At[kSpRows * kSplitK(KO_NN_MAX_TOKENS)];
     __shared__ float yp[4][kSpRows];
     __shared__ uint8_t bad[kSpRows];
     const int tid = threadIdx.x;
@@ -1271,10 +1269,8 @@ __global__ __launch_bounds__(256, 2) void score_split_kernel(const uint16_t *wb,
         pv[q] = idx < rows * N ? pos[b0 * N + idx] : 0;
     }
 
-    for (int idx = tid; idx < kSpRows * (KP / 8); idx += 256) {
-        const int r = idx / (KP / 8), c = (idx % (KP / 8)) * 8;
-        *reinterpret_cast<uint4 *>(&At[r][c]) = make_uint4(0u, 0u, 0u, 0u);
-    }
+    for (int idx = tid; idx < kSpRows * KP / 8; idx += 256)
+        *reinterpret_cast<uint4 *>(At + (size_t)idx * 8) = make_uint4(0u, 0u, 0u, 0u);
     if (tid < kSpRows)
         bad[tid] = 0;
     __syncthreads();
@@ -1284,7 +1280,7 @@ __global__ __launch_bounds__(256, 2) void score_split_kernel(const uint16_t *wb,
         if (idx < rows * N) {
             const int r = idx / N, i = idx % N, p = pv[q];
             if (p < N || p >= KO_NN_UNPLACED)
-                At[r][i * (N + 1) + (p < N ? p : N)] = 0x3F80;   // BF16 1.0
+                At[frag_index(r, i * (N + 1) + (p < N ? p : N), KP / kKStep)] = 0x3F80;   // BF16 1.0
             else
                 bad[r] = 1;   // not a launch position of an N-kernel order
         }
@@ -1306,7 +1302,8 @@ __global__ __launch_bounds__(256, 2) void score_split_kernel(const uint16_t *wb,
         for (int i = 0; i < 8; i++)
 #pragma unroll
             for (int j = 0; j < 4; j++)
-                *reinterpret_cast<uint2 *>(&At[i * 16 + rl][unit_of(j)]) = bf16x4_of<decltype(relu)::value>(acc[i][j]);
+                *reinterpret_cast<uint2 *>(At + frag_index(i * 16 + rl, unit_of(j), kHid / kKStep)) =
+                    bf16x4_of<decltype(relu)::value>(acc[i][j]);
     };
 
     f32x4 init[4];
