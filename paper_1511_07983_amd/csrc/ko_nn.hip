@@ -1120,7 +1120,8 @@ __global__ __launch_bounds__(512) void frag_weights_kernel(const uint16_t *wb, u
 // = init[j] + B A^T over K = 32 KS, where B (the weights or the split table in
 // fragment order; with TWO a second matrix of the same shape, accumulated
 // after the first in each k step) is the MFMA's first operand and A (the
-// tile's rows, k-contiguous in LDS) its second.  A lane so holds 4
+// tile in LDS, in the same fragment order with orders as the units, so a
+// wave's read is 1 KB contiguous) its second.  A lane so holds 4
 // consecutive hidden units of one order.  The first k step takes init[j]
 // (the bias of the lane's 4 units, or zero) as its addend, so nothing is
 // cleared or added afterwards.
