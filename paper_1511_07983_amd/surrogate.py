@@ -385,12 +385,16 @@ def _init_params(seed: int) -> np.ndarray:
 
 
 def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: int = 8192,
-           per_set: int = 512, heldout: int = 8, n_score: int = 100_000_000, top_k: int = 10_000,
+           per_set: int = 512, heldout: int = 8, n_score: int = 1 << 18, top_k: int = 10_000,
            steps: int = 65536, batch: int = 4096, lr: float = 1e-3, seed: int = 2015, target: str = "quantile",
            members: int = 4, quantiles: dict | None = None, out=print):
     """Train `members` scorers on exact samples (an Ensemble), then per
     held-out set: exact top-1% threshold by full enumeration, scoring of
-    `n_score` sampled orders, exact re-simulation of the `top_k` best.  Prints
+    `n_score` sampled orders, exact re-simulation of the `top_k` best (the
+    default 2^18 lies in the range 2^14..2^19 over which the first-hit ratio
+    of validation sets, disjoint from the held-out ones, stays flat; scoring
+    10^8 orders reaches further into the scores' extremes, where they are
+    least reliable, and does worse).  Prints
     one JSON line per held-out set and a summary.  `quantiles` (held-out set
     index -> Quantile), when given, keeps the thresholds of earlier calls on
     the same held-out sets and is filled in."""
@@ -574,7 +578,7 @@ if __name__ == "__main__":
     ap.add_argument("--train-sets", type=int, default=8192)
     ap.add_argument("--per-set", type=int, default=512)
     ap.add_argument("--heldout", type=int, default=8)
-    ap.add_argument("--n-score", type=int, default=100_000_000)
+    ap.add_argument("--n-score", type=int, default=1 << 18)
     ap.add_argument("--top-k", type=int, default=10_000)
     ap.add_argument("--steps", type=int, default=65536)
     ap.add_argument("--batch", type=int, default=4096)
