@@ -467,7 +467,7 @@ def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets:
                 eval_sets: int = 1024, width: int = 256, q_samples: int = 4096, steps: int = 32768,
                 batch: int = 4096, lr: float = 1e-3, mask_frac: float = 0.25, seed: int = 2016,
                 max_children: int = 2, temperature: float = 0.0, n_score: int = 1 << 20, members: int = 4,
-                sur=None, out=print):
+                eval_first: int = 0, sur=None, out=print):
     """Surrogate-guided search on n=16 sets against uniform sampling at the
     same exact budget (`width` exact simulations per set): beam search (width
     `width`, at most `max_children` children per prefix per step, optional
@@ -478,7 +478,9 @@ def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets:
     below it) simulations on average to reach it.  A search needs the 1-based
     position of its first hit in its predicted order (its budget plus uniform
     sampling's expectation if it has none).  `sur`, when given, is a trained
-    scorer used as is (no training).  Prints one JSON summary line."""
+    scorer used as is (no training).  The evaluation sets are draws
+    eval_first .. eval_first + eval_sets - 1 of the workload.  Prints one JSON
+    summary line."""
     import json
     import time
 
@@ -498,7 +500,7 @@ def report_beam(*, train_workload: int = 14, eval_workload: int = 4, train_sets:
                         "loss": log}), flush=True)
         del data
     model = synth.WORKLOADS[eval_workload].model
-    ev = [synth.draw_set(eval_workload, s) for s in range(eval_sets)]
+    ev = [synth.draw_set(eval_workload, eval_first + s) for s in range(eval_sets)]
     etab = SetTable.build(model, ev)
     S = len(ev)
     # exact random samples of every set in one batch: q_samples for the
