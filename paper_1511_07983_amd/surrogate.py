@@ -385,7 +385,7 @@ def _init_params(seed: int) -> np.ndarray:
 
 
 def report(*, train_workload: int = 3, heldout_workload: int = 13, train_sets: int = 8192,
-           per_set: int = 512, heldout: int = 8, n_score: int = 1 << 18, top_k: int = 10_000,
+           per_set: int = 512, heldout: int = 32, n_score: int = 1 << 18, top_k: int = 10_000,
            steps: int = 65536, batch: int = 4096, lr: float = 1e-3, seed: int = 2015, target: str = "quantile",
            members: int = 4, quantiles: dict | None = None, out=print):
     """Train `members` scorers on exact samples (an Ensemble), then per
@@ -579,7 +579,7 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser(description="surrogate-guided search report (one GPU)")
     ap.add_argument("--train-sets", type=int, default=8192)
     ap.add_argument("--per-set", type=int, default=512)
-    ap.add_argument("--heldout", type=int, default=8)
+    ap.add_argument("--heldout", type=int, default=32)
     ap.add_argument("--n-score", type=int, default=1 << 18)
     ap.add_argument("--top-k", type=int, default=10_000)
     ap.add_argument("--steps", type=int, default=65536)
