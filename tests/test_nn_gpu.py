@@ -363,6 +363,35 @@ def test_split_score_matches_its_definition_and_oracle(B, n):
     assert np.abs(y[:m] - yo).max() <= 1e-2 * (1.0 + np.abs(yo).max())
 
 
+def test_split_pack_follows_the_weights():
+    """The operand pack holds a copy of W2 and W3: a pack made after an Adam
+    step carries the updated BF16 weights (and scores with them), the pack made
+    before keeps the old ones."""
+    B, n = 300, 9
+    rng, flat, feat, pos, X = make_case(17, B, n)
+    model = nn.Surrogate(flat)
+    f = torch.from_numpy(feat[0]).to("cuda:0")
+    p = torch.from_numpy(pos).to("cuda:0")
+    before = model.split_table(f).cpu().numpy().view(np.uint16)
+    x = device_tokens(model, feat, pos)
+    t = torch.from_numpy(rng.normal(0.0, 1.0, size=B).astype(np.float32)).to("cuda:0")
+    model.backward(x, t)
+    model.adam(1, 1e-2)
+    after_t = model.split_table(f)
+    after = after_t.cpu().numpy().view(np.uint16)
+    KP = -(-n * (n + 1) // 32) * 32
+    off = 2 * 256 * KP
+    pw = mlp.unflatten(model.read("weights").astype(np.float64))
+    for q, name in enumerate(("W2", "W3")):
+        blk = slice(off + q * 65536, off + (q + 1) * 65536)
+        assert np.array_equal(_bf16_bits_to_f64(_unfrag(after[blk], 8)), mlp.bf16(pw[name])), name
+        assert not np.array_equal(after[blk], before[blk]), name
+    # scores from the new pack are the new model's (within the split path's tolerance)
+    y = model.score_split(after_t, p).cpu().numpy().astype(np.float64)
+    yo, _ = mlp.forward(pw, X[:256])
+    assert np.abs(y[:256] - yo).max() <= 1e-2 * (1.0 + np.abs(yo).max())
+
+
 def test_split_score_flags_positions_outside_the_set():
     """A position in n..15 is no launch position of an n-kernel order: that
     row's y is NaN and the other rows are as without it.  The tile's thread t
