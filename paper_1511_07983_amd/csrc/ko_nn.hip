@@ -1201,7 +1201,7 @@ __device__ __forceinline__ void split_product(f32x4 (&acc)[8][4], const uint16_t
 // BF16 of acc's 4 values (round to nearest even), with relu applied to the
 // rounded values (a BF16 value below zero, -0 included, has its sign bit set:
 // as a 16-bit integer it is negative, and the integer maximum with 0 gives
-// +0; rounding and relu commute for every number).
+// +0; rounding and relu commute for every number that is not NaN).
 template <bool RELU>
 __device__ __forceinline__ uint2 bf16x4_of(const f32x4 &a)
 {
@@ -1222,7 +1222,8 @@ __device__ __forceinline__ uint2 bf16x4_of(const f32x4 &a)
 // Scoring of a tile of 128 orders per workgroup (4 waves; wave w owns hidden
 // units [64 w, 64 w + 64) of every product, for all 128 orders, so each
 // fragment of the table or of W feeds 8 MFMAs):
-//   1. the one-hot tile in LDS (row r: a 1 at 17 i + pos[r][i]);
+//   1. the one-hot tile in LDS (row r: a 1 at (n + 1) i + slot for kernel
+//      i, the slot being its position, or n when unplaced);
 //   2. S = onehot (hi + lo), the hi then the lo product of each k step into
 //      one float32 accumulator; S as BF16 over the tile once every wave has
 //      read the one-hot rows (8 bytes per lane and tile: an order's 4
