@@ -562,8 +562,22 @@ __device__ __forceinline__ bool take_order(const SimArgs &a, const SetRec &st, i
     return true;
 }
 
+// Resident waves per SIMD.  The contended variants of up to 10 kernels (192
+// VGPRs unconstrained) and the plain 12-kernel variant (213) would run 2 waves;
+// asked for 3 (at most 168 VGPRs) the compiler moves a few values to scratch
+// (8, 15 and 57 dwords), which costs less than the third wave gains: all 10!
+// contended n=10 orders in 17.4 ms instead of 23.1, all 12! orders of an n=12
+// set in 3.33 s instead of 4.03, the same makespans.  The others fit 3 waves
+// (plain, up to 10 kernels) or would spill too much (the 16-kernel variants).
+template <int GC, bool CONT>
+constexpr int lane_waves_per_simd()
+{
+    return ((CONT && GC <= 10) || (!CONT && GC == 12)) ? 3 : 1;
+}
+
 template <int RC, int GC, typename Mask, bool CONT>
-__global__ __launch_bounds__(64) void simulate_lanes_kernel(SimArgs a, uint32_t ecap)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(lane_waves_per_simd<GC, CONT>())))
+void simulate_lanes_kernel(SimArgs a, uint32_t ecap)
 {
     extern __shared__ uint32_t lane_lds[];
     uint32_t *tab = lane_lds;
